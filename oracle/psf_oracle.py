@@ -1,0 +1,286 @@
+"""FP64 reference ("oracle") for the field-dependent PSF operator.
+
+TEST INFRASTRUCTURE ONLY.  This module is imported by the test-suite, by the
+package's ``smoke()`` check and by the benchmark's CPU-baseline leg, and by
+nothing else: the product path (the HIP library and its Python binding) never
+calls it and shares no code with it.
+
+It follows Milani & Douglas, "Faster imaging simulation through complex
+systems: a coronagraphic example" (arXiv 2106.09122):
+
+* Sec. 2 and Eqs. (2)-(3): the scene meshgrid of pixel-centre offsets,
+  the polar conversion of each field point, radial interpolation of the
+  off-axis PSF datacube (linear or nearest) and rotation of the result to the
+  field point's position angle; one flattened PSF per scene pixel.
+* Sec. 3, Eqs. (4)-(6): the library matrix A = [I_1 ... I_{N^2}] with one
+  column per scene pixel, and the simulated image S = A Z.
+
+Everything is plain numpy in float64, one column at a time, in the order the
+paper describes.  Inputs are the same float32 cube values (promoted exactly)
+and float64 radii the GPU receives.
+
+Readings taken where the paper is silent or garbled (each one is listed in
+the repository's design notes):
+
+* meshgrid centres are (q - (N-1)/2) * S for column q and (p - (N-1)/2) * S
+  for row p: x follows the column index, y the row index, both flattened
+  row-major;
+* the polar angle is carried as (cos, sin) = (x/r, y/r), and (1, 0) at r = 0
+  (the value atan2 gives there);
+* rotation turns the +x-axis PSF so that its core lands on the field point
+  (with y increasing with row index), about the array centre ((n-1)/2,
+  (n-1)/2), keeping the n x n frame; the rotated image is sampled bilinearly
+  with zero padding outside the array;
+* offsets beyond the last sample either hold the last PSF (``clamp``) or give
+  an all-zero column (``zero``); offsets below the first sample hold the
+  first PSF;
+* nearest-neighbour radial interpolation rounds ties to the lower sample;
+* the operator applies no normalisation of its own (Sec. 3 leaves PSF
+  normalisation to the user); column sums are reported instead.
+
+The per-column power-of-two scaled 16-bit storage (``pow2_exponents``,
+``round_to_format``) is not in the paper, which stores float64; it is the
+reduced-precision form of the same matrix, and its exact FP64 definition is
+given here so the GPU's rounding error can be measured against it.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "scene_geometry", "radial_bracket", "interpolate_radial", "rotate_bilinear",
+    "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
+    "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
+    "quantize_library", "scale_exponent",
+]
+
+
+# ------------------------------------------------------------------ a1 ----
+def scene_geometry(N: int, S: float):
+    """Pixel-centre offsets and polar form of every scene pixel.
+
+    Sec. 2, Eqs. (2)-(3): a meshgrid running over the N pixels with a half
+    pixel shift, scaled by the scene pixel scale S; flattened so that scene
+    pixel (row p, col q) is field point j = p*N + q.  The polar conversion
+    (Sec. 2, "standard 2D arctangent") is kept as r and the unit vector
+    (cos, sin) = (x/r, y/r).
+
+    Returns x, y, r, ct, st as float64 arrays of length N*N.
+    """
+    N = int(N)
+    S = float(S)
+    C = (N - 1) / 2.0
+    p, q = np.meshgrid(np.arange(N, dtype=np.float64), np.arange(N, dtype=np.float64),
+                       indexing="ij")
+    x = ((q - C) * S).ravel()
+    y = ((p - C) * S).ravel()
+    r = np.sqrt(x * x + y * y)
+    ct = np.ones_like(r)
+    st = np.zeros_like(r)
+    nz = r > 0
+    ct[nz] = x[nz] / r[nz]
+    st[nz] = y[nz] / r[nz]
+    return x, y, r, ct, st
+
+
+# ------------------------------------------------------------------ a2 ----
+def radial_bracket(r: float, radii: np.ndarray, interp: str = "linear", oob: str = "clamp"):
+    """Radial sample pair and weight for one offset r.
+
+    Sec. 2: the interpolating function, set up on the datacube of PSFs with
+    offsets along one axis, returns the PSF interpolated (linear or nearest)
+    to the offset r.  Returns (k, w, zero): Q = (1-w) P_k + w P_{k+1}; if
+    ``zero`` the column is identically zero.
+    """
+    radii = np.asarray(radii, dtype=np.float64)
+    K = radii.size
+    if K == 1:
+        return 0, 0.0, False
+    if r <= radii[0]:
+        return 0, 0.0, False
+    if r >= radii[K - 1]:
+        if oob == "zero" and r > radii[K - 1]:
+            return K - 2, 0.0, True
+        return K - 2, 1.0, False
+    # largest k with radii[k] <= r  (0 <= k <= K-2 here)
+    k = int(np.searchsorted(radii, r, side="right")) - 1
+    lo, hi = radii[k], radii[k + 1]
+    if interp == "nearest":
+        # ties go to the lower sample
+        return k, (1.0 if (r - lo) > (hi - r) else 0.0), False
+    return k, (r - lo) / (hi - lo), False
+
+
+def interpolate_radial(cube: np.ndarray, k: int, w: float) -> np.ndarray:
+    """Q = (1-w) P_k + w P_{k+1} in float64 (Sec. 2, linear interpolation in
+    offset at the integer pixel nodes of the datacube)."""
+    P = np.asarray(cube, dtype=np.float64)
+    if P.shape[0] == 1:
+        return P[0].copy()
+    return (1.0 - w) * P[k] + w * P[k + 1]
+
+
+# ------------------------------------------------------------------ a3 ----
+def rotate_bilinear(Q: np.ndarray, ct: float, st: float) -> np.ndarray:
+    """Rotate an n x n PSF about its centre so that a feature on +x moves to
+    position angle theta (cos theta = ct, sin theta = st), sampling bilinearly
+    with zero padding (Sec. 2, the rotation step).
+
+    Output pixel (a, b) has offset u = (b - c, a - c) from the centre
+    c = (n-1)/2; it samples Q at c + R(-theta) u, i.e. at column
+    c + ct*ux + st*uy and row c - st*ux + ct*uy.
+    """
+    Q = np.asarray(Q, dtype=np.float64)
+    n = Q.shape[0]
+    c = (n - 1) / 2.0
+    a, b = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64),
+                       indexing="ij")
+    ux = b - c
+    uy = a - c
+    sx = ct * ux + st * uy
+    sy = (-st) * ux + ct * uy
+    col = c + sx
+    row = c + sy
+    c0 = np.floor(col)
+    r0 = np.floor(row)
+    fx = col - c0
+    fy = row - r0
+    c0 = c0.astype(np.int64)
+    r0 = r0.astype(np.int64)
+
+    def tap(rr, cc):
+        ok = (rr >= 0) & (rr < n) & (cc >= 0) & (cc < n)
+        v = np.zeros_like(fx)
+        v[ok] = Q[rr[ok], cc[ok]]
+        return v
+
+    return ((1.0 - fy) * (1.0 - fx) * tap(r0, c0)
+            + (1.0 - fy) * fx * tap(r0, c0 + 1)
+            + fy * (1.0 - fx) * tap(r0 + 1, c0)
+            + fy * fx * tap(r0 + 1, c0 + 1))
+
+
+def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp") -> np.ndarray:
+    """One library column I_j: radial interpolation, rotation, flattening
+    (Sec. 2, one iteration of the field-point loop)."""
+    cube = np.asarray(cube)
+    n = cube.shape[1]
+    k, w, zero = radial_bracket(r, radii, interp, oob)
+    if zero:
+        return np.zeros(n * n, dtype=np.float64)
+    Q = interpolate_radial(cube, k, w)
+    return rotate_bilinear(Q, ct, st).ravel()
+
+
+def build_library(cube, radii, N: int, S: float, interp: str = "linear", oob: str = "clamp",
+                  columns=None) -> np.ndarray:
+    """The library matrix A (Sec. 3, Eqs. (4)-(5)): n^2 rows, one column per
+    scene pixel, column j the flattened interpolated-and-rotated PSF of field
+    point j.  ``columns`` selects a subset of j (returned in that order).
+    Returns float64 [n*n][len(columns)]."""
+    cube = np.asarray(cube)
+    if cube.ndim != 3 or cube.shape[1] != cube.shape[2]:
+        raise ValueError("cube must be [K][n][n]")
+    radii = np.asarray(radii, dtype=np.float64)
+    if radii.size != cube.shape[0]:
+        raise ValueError("one radius per PSF")
+    n = cube.shape[1]
+    _, _, r, ct, st = scene_geometry(N, S)
+    cols = np.arange(N * N) if columns is None else np.asarray(columns, dtype=np.int64)
+    A = np.empty((n * n, cols.size), dtype=np.float64)
+    for t, j in enumerate(cols):
+        A[:, t] = library_column(cube, radii, r[j], ct[j], st[j], interp, oob)
+    return A
+
+
+# ---------------------------------------------------------- a5, a6, a7 ----
+def column_sums(A: np.ndarray) -> np.ndarray:
+    """tau_j = sum_i A_ij: the throughput of each library column."""
+    return np.asarray(A, dtype=np.float64).sum(axis=0)
+
+
+def apply(A: np.ndarray, Z) -> np.ndarray:
+    """Simulated image S = A Z (Sec. 3, Eq. (6)), float64."""
+    return np.asarray(A, dtype=np.float64) @ np.asarray(Z, dtype=np.float64)
+
+
+def apply_adjoint(A: np.ndarray, g) -> np.ndarray:
+    """G = A^T g, the adjoint of the simulation (gradient of <g, A Z> in Z)."""
+    return np.asarray(A, dtype=np.float64).T @ np.asarray(g, dtype=np.float64)
+
+
+def apply_batched(A: np.ndarray, Zb) -> np.ndarray:
+    """Images of B scenes at once: out[b] = A Z_b.  Zb is [B][N*N]."""
+    Zb = np.asarray(Zb, dtype=np.float64)
+    return (np.asarray(A, dtype=np.float64) @ Zb.T).T
+
+
+# ------------------------------------------------------------------ a4 ----
+def scale_exponent(m: float) -> int:
+    """Power-of-two exponent e with m * 2**-e in [2**14, 2**15) for m > 0,
+    and 0 for m == 0."""
+    if m == 0.0:
+        return 0
+    _, E = math.frexp(m)  # m = f * 2**E, f in [0.5, 1)
+    return E - 15
+
+
+def column_max_bound(cube, radii, N: int, S: float, interp="linear", oob="clamp") -> np.ndarray:
+    """Per-column upper bound on max_i A_ij that needs no column values:
+    (1-w) max(P_k) + w max(P_{k+1}).  Bilinear rotation is a convex
+    combination of Q's pixels (or zero), so the column never exceeds it."""
+    cube = np.asarray(cube, dtype=np.float64)
+    pmax = cube.reshape(cube.shape[0], -1).max(axis=1)
+    _, _, r, _, _ = scene_geometry(N, S)
+    out = np.empty(r.size, dtype=np.float64)
+    for j in range(r.size):
+        k, w, zero = radial_bracket(r[j], radii, interp, oob)
+        if zero:
+            out[j] = 0.0
+        elif cube.shape[0] == 1:
+            out[j] = pmax[0]
+        else:
+            out[j] = (1.0 - w) * pmax[k] + w * pmax[k + 1]
+    return out
+
+
+def pow2_exponents(bound: np.ndarray) -> np.ndarray:
+    """Per-column exponents e_j = scale_exponent(bound_j) (int32)."""
+    return np.array([scale_exponent(float(b)) for b in np.asarray(bound, dtype=np.float64)],
+                    dtype=np.int32)
+
+
+def round_to_format(v, fmt: str) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 or IEEE binary16 value
+    (round to nearest, ties to even), returned as float64.
+
+    binary16: 11 significant bits, normal exponents down to -14 and
+    subnormals spaced 2**-24, largest finite 65504.  bfloat16: 8
+    significant bits with the float32 exponent range (subnormals spaced
+    2**-133)."""
+    v = np.asarray(v, dtype=np.float64)
+    if fmt == "fp16":
+        p, emin, vmax = 11, -14, 65504.0
+    elif fmt == "bf16":
+        p, emin, vmax = 8, -126, float(np.ldexp(255.0 / 128.0, 127))
+    else:
+        raise ValueError(fmt)
+    out = np.zeros_like(v)
+    a = np.abs(v)
+    nz = a > 0
+    _, E = np.frexp(a[nz])  # a = f * 2**E, f in [0.5, 1): leading bit at 2**(E-1)
+    lead = np.maximum(E - 1, emin)
+    quantum = np.ldexp(1.0, lead - (p - 1))
+    q = np.rint(a[nz] / quantum) * quantum  # rint: ties to even
+    q = np.where(q > vmax, np.inf, q)  # rounded past the largest finite value
+    out[nz] = np.copysign(q, v[nz])
+    return out
+
+
+def quantize_library(A: np.ndarray, e: np.ndarray, fmt: str) -> np.ndarray:
+    """Mantissa matrix M_ij = RN(A_ij * 2**-e_j) in the 16-bit format, as
+    float64 (exact)."""
+    A = np.asarray(A, dtype=np.float64)
+    return round_to_format(A * np.ldexp(1.0, -np.asarray(e, dtype=np.int64))[None, :], fmt)
