@@ -1,0 +1,174 @@
+/*
+ * psflib -- field-dependent PSF operator on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the method of Milani & Douglas, "Faster imaging simulation
+ * through complex systems: a coronagraphic example" (arXiv 2106.09122):
+ *
+ *   Sec. 2, Eqs. (2)-(3)  the library build: every scene pixel (field point)
+ *                         gets the off-axis PSF interpolated in offset from a
+ *                         datacube of PSFs sampled along +x and rotated to the
+ *                         field point's position angle;
+ *   Sec. 3, Eqs. (4)-(6)  the library matrix A = [I_1 ... I_{N^2}] (n^2 rows,
+ *                         one column per scene pixel) and the simulated image
+ *                         S = A Z.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers named d_* are HIP device memory; h_* are host memory.  The
+ *    caller owns every buffer passed in, including the library buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call that touches the device is stream-ordered and returns without
+ *    waiting for the GPU.
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Scene pixel (row p, col q) of an N x N scene is j = p*N + q; image pixel
+ *    (row a, col b) of the n x n image is i = a*n + b (row-major).  The optical
+ *    axis is at ((n-1)/2, (n-1)/2) of every PSF and at ((N-1)/2, (N-1)/2) of
+ *    the scene; x runs along columns and y along rows.
+ *  - Radii and the scene pixel scale share one angular unit (any unit).  The
+ *    PSF pixel scale is not an input: the rotation depends only on the angle.
+ *  - Every call returns a status.  Arguments are validated before anything is
+ *    enqueued, so a call that fails validation has enqueued nothing.  Errors
+ *    raised by the HIP runtime (including faults of earlier asynchronous
+ *    work) are returned as PSFLIB_ERR_DEVICE.  psflib_last_error() gives a
+ *    human-readable message for the last failing call on the calling thread.
+ *  - A handle shares one device workspace between its calls: calls on the
+ *    same handle must not run concurrently (issue them on one stream, or
+ *    order them with events).  Different handles are independent.
+ */
+#ifndef PSFLIB_H
+#define PSFLIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSFLIB_OK = 0,
+  PSFLIB_ERR_INVALID_ARG = 1, /* null pointer, bad enum, non-positive size, bad scale */
+  PSFLIB_ERR_RADII = 2,       /* radii not finite or not strictly increasing */
+  PSFLIB_ERR_SIZE = 3,        /* size overflow, or a buffer too small */
+  PSFLIB_ERR_UNSUPPORTED = 4, /* valid request this library does not provide */
+  PSFLIB_ERR_DEVICE = 5       /* HIP runtime error */
+} psflib_status;
+
+/* Radial interpolation of the PSF datacube (Sec. 2: linear or nearest). */
+typedef enum { PSFLIB_INTERP_LINEAR = 0, PSFLIB_INTERP_NEAREST = 1 } psflib_interp;
+
+/* Offsets r > radii[K-1]: CLAMP holds the last sampled PSF; ZERO gives an
+ * all-zero column.  Offsets r < radii[0] always hold the first PSF. */
+typedef enum { PSFLIB_OOB_CLAMP = 0, PSFLIB_OOB_ZERO = 1 } psflib_oob;
+
+/* Storage of the library matrix.
+ *  FP32       A as float, column-major: column j is the n*n floats of the
+ *             flattened PSF I_j at element offset j*n*n (the layout of Eq. (5)).
+ *  BF16_POW2  A_ij = M_ij * 2^e_j with M in bfloat16 and one int32 exponent
+ *  FP16_POW2  per column (IEEE binary16 for FP16_POW2).  e_j makes the largest
+ *             value the column can reach, (1-w) max P_k + w max P_{k+1}, land
+ *             in [2^14, 2^15) after scaling, so binary16 neither overflows nor
+ *             loses the column's faint wings to underflow.  Mantissas are
+ *             stored in groups of 8 columns: element (i, j) sits at
+ *             ((j/8)*n*n + i)*8 + j%8, so one 16-byte load holds row i of 8
+ *             adjacent columns (the operand shape of the matrix cores).
+ *             Products accumulate in float32. */
+typedef enum { PSFLIB_FP32 = 0, PSFLIB_BF16_POW2 = 1, PSFLIB_FP16_POW2 = 2 } psflib_storage;
+
+typedef struct {
+  int32_t n;             /* PSF side = image side (pixels); the image has n*n pixels */
+  int32_t n_psf;         /* K >= 1 sampled off-axis PSFs, sources on +x */
+  int32_t N;             /* scene side (pixels); the library has N*N columns */
+  int32_t interp;        /* psflib_interp */
+  double scene_pixscale; /* S > 0, in the unit of the radii (Eqs. (2)-(3)) */
+  int32_t oob;           /* psflib_oob */
+  int32_t storage;       /* psflib_storage */
+} psflib_desc;
+
+typedef struct psflib_handle psflib_handle;
+
+/* Human-readable name of a status code (static storage). */
+const char* psflib_status_string(psflib_status s);
+
+/* Message describing the last failing call made on this thread (static,
+ * thread-local storage; empty if none). */
+const char* psflib_last_error(void);
+
+/* Bytes the caller must allocate for the library buffer of `desc`: the matrix
+ * (n^2 x N^2 entries in the chosen storage, with the 16-bit forms padded to a
+ * multiple of 64 columns), followed by the per-column float64 column sums and,
+ * for the 16-bit forms, the int32 exponents.  Fails with PSFLIB_ERR_SIZE if
+ * the size does not fit in size_t or exceeds 2^62. */
+psflib_status psflib_library_bytes(const psflib_desc* desc, size_t* bytes);
+
+/* Build the interpolated PSF library (Sec. 2; Eqs. (4)-(5)).
+ *   d_cube   float32 [K][n][n] off-axis PSFs (k, row, col), source of PSF k at
+ *            offset h_radii[k] on +x; values must be finite.  Read only during
+ *            the build (the caller may free it once the stream passes the build).
+ *   h_radii  float64 [K], finite and strictly increasing (copied before return).
+ *   d_lib    library buffer of at least psflib_library_bytes() bytes, 256-byte
+ *            aligned; written by the build and read by every later call.
+ *   out      receives a new handle (host object) on success; it refers to
+ *            d_lib, which must outlive it.  Free it with psflib_destroy().
+ * Column j is, for field point (x_j, y_j) = ((q-(N-1)/2) S, (p-(N-1)/2) S),
+ * r = sqrt(x^2+y^2), (cos, sin) = (x/r, y/r) ((1, 0) at r = 0): the PSF
+ * interpolated to offset r, Q = (1-w) P_k + w P_{k+1}, rotated about the array
+ * centre so that +x turns to the position angle (output pixel at offset u from
+ * the centre samples Q at R(-theta) u), bilinearly with zero padding.
+ * Allocates the handle's device workspace (hipMalloc) and temporary build
+ * buffers (stream-ordered). */
+psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const double* h_radii,
+                           void* d_lib, size_t lib_bytes, void* stream, psflib_handle** out);
+
+/* Simulated image S = A Z (Sec. 3, Eq. (6)).
+ *   d_scene  float32 [N*N] scene (flattened row-major, Sec. 3).
+ *   d_image  float32 [n*n] output image.
+ * Float32 accumulation in a fixed order (results are bitwise reproducible). */
+psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream);
+
+/* Adjoint G = A^T g: the gradient of <g, A Z> with respect to Z.
+ *   d_g           float32 [n*n] image-space vector.
+ *   d_scene_grad  float32 [N*N] output.
+ * Float32 accumulation in a fixed order. */
+psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
+                                   void* stream);
+
+/* Images of B scenes at once (Sec. 5: simulating many scenes at once):
+ * d_images[b] = A d_scenes[b] for b < B.
+ *   d_scenes  float32 [B][N*N];  d_images  float32 [B][n*n];  B >= 0.
+ * FP32 storage runs float32 matrix-core products; the 16-bit forms round each
+ * scene to the storage format with a per-scene power-of-two scale (so the
+ * scaled scene spans [2^14, 2^15) at its largest) and run 16-bit matrix-core
+ * products with float32 accumulation.  Allocates stream-ordered scratch for
+ * the 16-bit forms. */
+psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
+                                   int32_t B, void* stream);
+
+/* Column sums tau_j = sum_i A_ij (float64 [N*N]), computed during the build
+ * from the float32 values (before 16-bit rounding). */
+psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* stream);
+
+/* Copy `count` library columns, dequantised to float32, into d_out
+ * [count][n*n]; d_cols is a device int32 array of column indices in [0, N*N). */
+psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, int32_t count,
+                                 float* d_out, void* stream);
+
+/* Per-column exponents e_j (int32 [N*N]) of the 16-bit forms;
+ * PSFLIB_ERR_UNSUPPORTED for FP32 storage. */
+psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void* stream);
+
+/* Per-column geometry the build used (Sec. 2, Eqs. (2)-(3) and the radial
+ * interpolation step): d_geom float64 [N*N][4] = (r, cos theta, sin theta, w)
+ * and d_k int32 [N*N] = k, the lower radial sample (Q = (1-w) P_k + w P_{k+1}),
+ * or -1 for a column that is identically zero (PSFLIB_OOB_ZERO beyond the
+ * last sample).  Either output pointer may be NULL. */
+psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_t* d_k, void* stream);
+
+/* Release the handle and its workspace.  Waits for the device to finish work
+ * that uses the workspace.  NULL is ignored. */
+void psflib_destroy(psflib_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSFLIB_H */

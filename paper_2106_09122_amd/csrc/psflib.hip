@@ -1,0 +1,332 @@
+// C ABI of psflib: argument validation, the library layout, the handle and
+// its workspace, and dispatch to the kernels.  Every argument is checked
+// before anything is enqueued, so a failed call leaves the stream untouched.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psflib_internal.h"
+
+struct psflib_handle {
+  psflib_desc desc;
+  psflib::Layout L;
+  int device;
+  void* lib;            // caller-owned library buffer
+  void* ws;             // device workspace (owned)
+  psflib::ColGeom* geo;
+  double* radii_dev;
+  float* pmax;
+  float* mv_part;
+  int32_t* mv_count;   // arrival counters of the fused split-K reduction
+  float* adj_part;
+  std::vector<double> radii;  // host copy (source of the radii upload)
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+psflib_status fail(psflib_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+psflib_status device_fail(hipError_t e, const char* what) {
+  return fail(PSFLIB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int32_t kMaxN = 8192;   // image side: n^2 rows fit comfortably in 32-bit pixel indices
+constexpr int32_t kMaxScene = 46340;  // scene side: N^2 < 2^31 columns
+
+psflib_status check_desc(const psflib_desc* d) {
+  if (!d) return fail(PSFLIB_ERR_INVALID_ARG, "desc is NULL");
+  if (d->n < 1 || d->n > kMaxN) return fail(PSFLIB_ERR_INVALID_ARG, "n must be in [1, 8192]");
+  if (d->N < 1 || d->N > kMaxScene) return fail(PSFLIB_ERR_INVALID_ARG, "N must be in [1, 46340]");
+  if (d->n_psf < 1) return fail(PSFLIB_ERR_INVALID_ARG, "n_psf must be >= 1");
+  if (!(d->scene_pixscale > 0.0) || !isfinite(d->scene_pixscale))
+    return fail(PSFLIB_ERR_INVALID_ARG, "scene_pixscale must be finite and > 0");
+  if (d->interp != PSFLIB_INTERP_LINEAR && d->interp != PSFLIB_INTERP_NEAREST)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unknown interp");
+  if (d->oob != PSFLIB_OOB_CLAMP && d->oob != PSFLIB_OOB_ZERO)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unknown oob mode");
+  if (d->storage != PSFLIB_FP32 && d->storage != PSFLIB_BF16_POW2 && d->storage != PSFLIB_FP16_POW2)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unknown storage");
+  return PSFLIB_OK;
+}
+
+psflib_status check_handle(const psflib_handle* h) {
+  if (!h) return fail(PSFLIB_ERR_INVALID_ARG, "handle is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev != h->device)
+    return fail(PSFLIB_ERR_INVALID_ARG, "current device differs from the device the library was built on");
+  return PSFLIB_OK;
+}
+
+}  // namespace
+
+namespace psflib {
+
+bool compute_layout(const psflib_desc& d, Layout* L) {
+  const int64_t M = (int64_t)d.n * d.n;
+  const int64_t ncols = (int64_t)d.N * d.N;
+  const int64_t ncols_pad =
+      (d.storage == PSFLIB_FP32) ? ncols : ((ncols + kColPad - 1) / kColPad) * kColPad;
+  const int64_t esize = (d.storage == PSFLIB_FP32) ? 4 : 2;
+  // M <= 2^26 and ncols_pad < 2^31 + 64: the product stays below 2^60.
+  const unsigned __int128 mat = (unsigned __int128)M * (unsigned __int128)ncols_pad * esize;
+  if (mat > ((unsigned __int128)1 << 62)) return false;
+  size_t off = align256((size_t)mat);
+  L->M = M;
+  L->ncols = ncols;
+  L->ncols_pad = ncols_pad;
+  L->off_tau = off;
+  off = align256(off + (size_t)ncols * 8);
+  L->off_exp = off;
+  if (d.storage != PSFLIB_FP32) off = align256(off + (size_t)ncols_pad * 4);
+  L->total = off;
+  return L->total <= ((size_t)1 << 62);
+}
+
+}  // namespace psflib
+
+extern "C" {
+
+const char* psflib_status_string(psflib_status s) {
+  switch (s) {
+    case PSFLIB_OK: return "PSFLIB_OK";
+    case PSFLIB_ERR_INVALID_ARG: return "PSFLIB_ERR_INVALID_ARG";
+    case PSFLIB_ERR_RADII: return "PSFLIB_ERR_RADII";
+    case PSFLIB_ERR_SIZE: return "PSFLIB_ERR_SIZE";
+    case PSFLIB_ERR_UNSUPPORTED: return "PSFLIB_ERR_UNSUPPORTED";
+    case PSFLIB_ERR_DEVICE: return "PSFLIB_ERR_DEVICE";
+  }
+  return "PSFLIB_ERR_UNKNOWN";
+}
+
+const char* psflib_last_error(void) { return g_last_error.c_str(); }
+
+psflib_status psflib_library_bytes(const psflib_desc* desc, size_t* bytes) {
+  psflib_status st = check_desc(desc);
+  if (st != PSFLIB_OK) return st;
+  if (!bytes) return fail(PSFLIB_ERR_INVALID_ARG, "bytes is NULL");
+  psflib::Layout L;
+  if (!psflib::compute_layout(*desc, &L)) return fail(PSFLIB_ERR_SIZE, "library size exceeds 2^62 bytes");
+  *bytes = L.total;
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const double* h_radii,
+                           void* d_lib, size_t lib_bytes, void* stream, psflib_handle** out) {
+  psflib_status st = check_desc(desc);
+  if (st != PSFLIB_OK) return st;
+  if (!d_cube || !h_radii || !d_lib || !out)
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_cube, h_radii, d_lib and out must be non-NULL");
+  if (((uintptr_t)d_lib & 255u) != 0) return fail(PSFLIB_ERR_INVALID_ARG, "d_lib must be 256-byte aligned");
+  const int K = desc->n_psf;
+  for (int k = 0; k < K; ++k) {
+    if (!isfinite(h_radii[k])) return fail(PSFLIB_ERR_RADII, "radii must be finite");
+    if (k > 0 && !(h_radii[k] > h_radii[k - 1]))
+      return fail(PSFLIB_ERR_RADII, "radii must be strictly increasing");
+  }
+  psflib::Layout L;
+  if (!psflib::compute_layout(*desc, &L)) return fail(PSFLIB_ERR_SIZE, "library size exceeds 2^62 bytes");
+  if (lib_bytes < L.total)
+    return fail(PSFLIB_ERR_SIZE, "library buffer too small: need " + std::to_string(L.total) +
+                                     " bytes, got " + std::to_string(lib_bytes));
+  const int storage = desc->storage;
+  const int64_t mv_floats = psflib::matvec_partial_floats(storage, L.M, L.ncols, L.ncols_pad);
+  const int64_t adj_floats = psflib::adjoint_partial_floats(storage, L.M, L.ncols, L.ncols_pad);
+
+  (void)hipGetLastError();  // clear a stale error left by unrelated work
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+
+  psflib_handle* h = new (std::nothrow) psflib_handle();
+  if (!h) return fail(PSFLIB_ERR_DEVICE, "host allocation failed");
+  h->desc = *desc;
+  h->L = L;
+  h->device = dev;
+  h->lib = d_lib;
+  h->radii.assign(h_radii, h_radii + K);
+
+  // Workspace: radii | pmax | per-column geometry | matvec partials | adjoint partials.
+  size_t off = 0;
+  const size_t off_radii = off; off = align256(off + (size_t)K * 8);
+  const size_t off_pmax = off;  off = align256(off + (size_t)K * 4);
+  const size_t off_geo = off;   off = align256(off + (size_t)L.ncols_pad * sizeof(psflib::ColGeom));
+  const size_t off_mv = off;    off = align256(off + (size_t)mv_floats * 4);
+  const int64_t ncount = psflib::matvec_counters(storage, L.M);
+  const size_t off_cnt = off;   off = align256(off + (size_t)ncount * 4);
+  const size_t off_adj = off;   off = align256(off + (size_t)adj_floats * 4);
+  e = hipMalloc(&h->ws, off);
+  if (e != hipSuccess) {
+    delete h;
+    return device_fail(e, "hipMalloc(workspace)");
+  }
+  char* ws = reinterpret_cast<char*>(h->ws);
+  h->radii_dev = reinterpret_cast<double*>(ws + off_radii);
+  h->pmax = reinterpret_cast<float*>(ws + off_pmax);
+  h->geo = reinterpret_cast<psflib::ColGeom*>(ws + off_geo);
+  h->mv_part = reinterpret_cast<float*>(ws + off_mv);
+  h->adj_part = reinterpret_cast<float*>(ws + off_adj);
+  h->mv_count = reinterpret_cast<int32_t*>(ws + off_cnt);
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* lib = reinterpret_cast<char*>(d_lib);
+  double* tau = reinterpret_cast<double*>(lib + L.off_tau);
+  int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
+  const size_t pair_bytes = (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
+  void* pairs = nullptr;
+  auto bail = [&](hipError_t err, const char* what) {
+    psflib_status r = device_fail(err, what);
+    (void)hipDeviceSynchronize();
+    if (pairs) (void)hipFree(pairs);
+    (void)hipFree(h->ws);
+    delete h;
+    return r;
+  };
+  e = hipMemcpyAsync(h->radii_dev, h->radii.data(), (size_t)K * 8, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
+  e = hipMemsetAsync(h->mv_count, 0, (size_t)ncount * 4, s);
+  if (e != hipSuccess) return bail(e, "hipMemsetAsync(counters)");
+  e = hipMallocAsync(&pairs, pair_bytes, s);
+  if (e != hipSuccess) { pairs = nullptr; return bail(e, "hipMallocAsync(pairs)"); }
+  e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(pairs), s);
+  if (e != hipSuccess) return bail(e, "pair_cube kernel");
+  if (storage != PSFLIB_FP32) {
+    e = psflib::launch_cube_max(d_cube, K, L.M, h->pmax, s);
+    if (e != hipSuccess) return bail(e, "cube_max kernel");
+  }
+  e = psflib::launch_geometry(desc->N, desc->scene_pixscale, h->radii_dev, K, desc->interp,
+                              desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
+                              exps, s);
+  if (e != hipSuccess) return bail(e, "geometry kernel");
+  e = psflib::launch_build(storage, reinterpret_cast<const float*>(pairs), h->geo, desc->n, L.M,
+                           L.ncols, L.ncols_pad, d_lib, tau, s);
+  if (e != hipSuccess) return bail(e, "build kernel");
+  e = hipFreeAsync(pairs, s);
+  if (e != hipSuccess) { pairs = nullptr; return bail(e, "hipFreeAsync(pairs)"); }
+  *out = h;
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (!d_scene || !d_image) return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be non-NULL");
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  hipError_t e = psflib::launch_matvec(h->desc.storage, h->lib, exps, d_scene, h->L.M, h->L.ncols,
+                                       h->L.ncols_pad, h->mv_part, h->mv_count, d_image,
+                                       reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "matvec kernel");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
+                                   void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (!d_g || !d_scene_grad) return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be non-NULL");
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  hipError_t e = psflib::launch_adjoint(h->desc.storage, h->lib, exps, d_g, h->L.M, h->L.ncols,
+                                        h->L.ncols_pad, h->adj_part, d_scene_grad,
+                                        reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "adjoint kernel");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
+                                   int32_t B, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (B < 0) return fail(PSFLIB_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0) return PSFLIB_OK;
+  if (!d_scenes || !d_images) return fail(PSFLIB_ERR_INVALID_ARG, "d_scenes and d_images must be non-NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t bytes = psflib::batched_scratch_bytes(h->desc.storage, h->L.M, h->L.ncols_pad, B);
+  void* scratch = nullptr;
+  hipError_t e;
+  if (bytes > 0) {
+    e = hipMallocAsync(&scratch, bytes, s);
+    if (e != hipSuccess) return device_fail(e, "hipMallocAsync(batched scratch)");
+  }
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  e = psflib::launch_batched(h->desc.storage, h->lib, exps, d_scenes, d_images, h->L.M, h->L.ncols,
+                             h->L.ncols_pad, B, scratch, bytes, s);
+  if (scratch) {
+    hipError_t e2 = hipFreeAsync(scratch, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return device_fail(e, "batched kernels");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (!d_tau) return fail(PSFLIB_ERR_INVALID_ARG, "d_tau must be non-NULL");
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  hipError_t e = hipMemcpyAsync(d_tau, lib + h->L.off_tau, (size_t)h->L.ncols * 8,
+                                hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "hipMemcpyAsync(tau)");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, int32_t count,
+                                 float* d_out, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (count < 0) return fail(PSFLIB_ERR_INVALID_ARG, "count must be >= 0");
+  if (count == 0) return PSFLIB_OK;
+  if (count > 65535) return fail(PSFLIB_ERR_INVALID_ARG, "count must be <= 65535");
+  if (!d_cols || !d_out) return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be non-NULL");
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  hipError_t e = psflib::launch_get_columns(h->desc.storage, h->lib, exps, d_cols, count, h->L.M,
+                                            h->L.ncols, d_out, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "get_columns kernel");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (h->desc.storage == PSFLIB_FP32)
+    return fail(PSFLIB_ERR_UNSUPPORTED, "FP32 storage has no exponents");
+  if (!d_exp) return fail(PSFLIB_ERR_INVALID_ARG, "d_exp must be non-NULL");
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  hipError_t e = hipMemcpyAsync(d_exp, lib + h->L.off_exp, (size_t)h->L.ncols * 4,
+                                hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "hipMemcpyAsync(exponents)");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_t* d_k, void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (!d_geom && !d_k) return PSFLIB_OK;
+  hipError_t e = psflib::launch_export_geometry(h->geo, h->L.ncols, d_geom, d_k,
+                                                reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "export_geometry kernel");
+  return PSFLIB_OK;
+}
+
+void psflib_destroy(psflib_handle* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(h->ws);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal declarations shared by the psflib translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psflib.h"
+
+namespace psflib {
+
+// Per-column geometry and radial bracket, written by the geometry kernel.
+struct ColGeom {
+  double r, ct, st, w;  // offset, cos/sin of the position angle, radial weight
+  int32_t k;            // lower radial sample; -1 for an identically zero column
+  int32_t e;            // power-of-two exponent of the 16-bit storage (0 for FP32)
+  int32_t pad[2];
+};
+static_assert(sizeof(ColGeom) == 48, "ColGeom layout");
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Launch-shape constants shared between the host code and the kernels.
+constexpr int kBuildThreads = 256;   // build kernel: one workgroup per group of 8 columns
+constexpr int kMvThreads = 256;      // FP32 matvec threads per workgroup (4 rows each)
+constexpr int kMvChunk = 128;        // columns per split-K chunk of the matvec
+constexpr int kMv16Threads = 256;    // 16-bit matvec threads per workgroup (1 row each)
+constexpr int kMv16Groups = 16;      // 8-column groups per split-K chunk (128 columns)
+constexpr int kAdjThreads = 256;     // adjoint threads per workgroup
+constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 float4 per thread)
+constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
+constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
+constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
+
+struct Layout {
+  int64_t M;          // n*n image pixels (rows of A)
+  int64_t ncols;      // N*N scene pixels (columns of A)
+  int64_t ncols_pad;  // columns stored (multiple of kColPad for 16-bit forms)
+  size_t off_tau, off_exp, total;
+};
+
+bool compute_layout(const psflib_desc& d, Layout* L);
+
+// ---- kernel launchers (each returns hipGetLastError() after its launch) ----
+hipError_t launch_cube_max(const float* cube, int K, int64_t M, float* pmax, hipStream_t s);
+hipError_t launch_pair_cube(const float* cube, int K, int64_t M, float* pairs, hipStream_t s);
+hipError_t launch_geometry(int N, double S, const double* radii, int K, int interp, int oob,
+                           const float* pmax, bool want_exp, ColGeom* geo, int64_t ncols_pad,
+                           int32_t* exps, hipStream_t s);
+hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
+                        int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
+hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
+                         int64_t M, int64_t ncols, int64_t ncols_pad, float* partial,
+                         int32_t* counters, float* out, hipStream_t s);
+int64_t matvec_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad);
+int64_t matvec_counters(int storage, int64_t M);
+hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, const float* g,
+                          int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
+                          hipStream_t s);
+int64_t adjoint_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad);
+hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, const float* Z,
+                          float* out, int64_t M, int64_t ncols, int64_t ncols_pad, int B,
+                          void* scratch, size_t scratch_bytes, hipStream_t s);
+size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols_pad, int B);
+hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
+                              const int32_t* cols, int count, int64_t M, int64_t ncols,
+                              float* out, hipStream_t s);
+hipError_t launch_export_geometry(const ColGeom* geo, int64_t ncols, double* geom, int32_t* k,
+                                  hipStream_t s);
+
+}  // namespace psflib

@@ -1,0 +1,122 @@
+"""Parity at the full 128 x 128 workload (16384 x 16384 library, the size the
+benchmark times), in the same launch configuration, on outputs the oracle
+can compute one by one: sampled library columns, images of scenes supported
+on those columns, and properties that hold at any size (flux, adjoint
+identity)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_REL = 1e-5
+LIB_REL = 1e-6
+U16 = {"bf16": 2.0**-8, "fp16": 2.0**-11}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config_inputs(2)
+
+
+@pytest.fixture(scope="module")
+def sample(c2):
+    N = c2["N"]
+    rng = synth.rng_for(2, synth.STREAM_SUBSAMPLE)
+    C = N // 2
+    special = [0, N - 1, N * N - 1, N * (N - 1), C * N + C, (C - 1) * N + C - 1, C * N + N - 1,
+               (N - 1) * N + C]
+    cols = np.unique(np.concatenate([rng.choice(N * N, 56, replace=False), special]))
+    A = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols)
+    return cols, A
+
+
+def _build(torch, c2, storage):
+    from paper_2106_09122_amd import psflib
+    return psflib.Library(torch.from_numpy(c2["cube"]).cuda(), c2["radii"], c2["N"], c2["S"],
+                          storage=storage)
+
+
+def _sparse_scenes(cols, ncols, B, seed):
+    rng = np.random.default_rng(seed)
+    Z = np.zeros((B, ncols), dtype=np.float32)
+    Z[:, cols] = (rng.random((B, cols.size)) * 10.0 ** rng.uniform(-9, -7, (B, cols.size))).astype(np.float32)
+    return Z
+
+
+def test_c2_fp32_sampled(torch, c2, sample):
+    cols, Aref = sample
+    lib = _build(torch, c2, "fp32")
+    got = lib.get_columns(cols).cpu().numpy().T.astype(np.float64)
+    pos = Aref > 0
+    assert np.all(got[~pos] == 0)
+    assert np.max(np.abs(got[pos] - Aref[pos]) / Aref[pos]) <= LIB_REL
+    tau = lib.column_sums().cpu().numpy()
+    np.testing.assert_allclose(tau[cols], Aref.sum(axis=0), rtol=LIB_REL, atol=0)
+    # single scene supported on the sampled columns
+    Zs = _sparse_scenes(cols, c2["N"] ** 2, 1, 1)[0]
+    ref = Aref @ Zs[cols].astype(np.float64)
+    img = lib.apply(torch.from_numpy(Zs).cuda()).cpu().numpy()
+    pos = ref > 0
+    assert np.all(img[~pos] == 0)
+    assert np.max(np.abs(img[pos] - ref[pos]) / ref[pos]) <= FP32_REL
+    # the benchmark's scene: flux and adjoint identity
+    Z = c2["scene"]
+    S = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy().astype(np.float64)
+    assert abs(S.sum() - tau @ Z.astype(np.float64)) <= 1e-5 * (tau @ Z.astype(np.float64))
+    g = np.random.default_rng(2).standard_normal(c2["n"] ** 2).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
+    lhs, rhs = S @ g.astype(np.float64), Z.astype(np.float64) @ G
+    assert abs(lhs - rhs) <= 1e-5 * (np.abs(S) @ np.abs(g))
+    Gref = Aref.T @ g.astype(np.float64)
+    den = np.abs(Aref).T @ np.abs(g.astype(np.float64))
+    assert np.all(G[cols][den == 0] == 0)
+    assert np.max(np.abs(G[cols] - Gref) / np.maximum(den, 1e-300)) <= FP32_REL
+    # batched: scenes supported on the sampled columns
+    for B in (1, 64, 257):
+        Zb = _sparse_scenes(cols, c2["N"] ** 2, B, 10 + B)
+        refb = Zb[:, cols].astype(np.float64) @ Aref.T
+        outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+        pos = refb > 0
+        assert np.all(outb[~pos] == 0)
+        assert np.max(np.abs(outb[pos] - refb[pos]) / refb[pos]) <= FP32_REL, B
+    lib.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_c2_16bit_sampled(torch, c2, sample, fmt):
+    cols, Aref = sample
+    lib = _build(torch, c2, fmt)
+    e_ref = O.pow2_exponents(O.column_max_bound(c2["cube"], c2["radii"], c2["N"], c2["S"]))
+    assert np.array_equal(lib.exponents().cpu().numpy(), e_ref)
+    u = U16[fmt]
+    deq = lib.get_columns(cols).cpu().numpy().T.astype(np.float64)
+    tol = (u * (1 + 1e-5) + LIB_REL) * Aref + 2.0**-25 * np.ldexp(1.0, e_ref[cols])[None, :]
+    assert np.all(np.abs(deq - Aref) <= tol)
+    Zs = _sparse_scenes(cols, c2["N"] ** 2, 1, 3)[0]
+    ref = Aref @ Zs[cols].astype(np.float64)
+    img = lib.apply(torch.from_numpy(Zs).cuda()).cpu().numpy()
+    big = ref > 1e-6 * ref.max()
+    assert np.max(np.abs(img - ref)[big] / ref[big]) <= u + FP32_REL
+    g = np.random.default_rng(6).standard_normal(c2["n"] ** 2).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
+    den = np.abs(Aref).T @ np.abs(g.astype(np.float64))
+    assert np.all(G[cols][den == 0] == 0)
+    err = np.abs(G[cols] - Aref.T @ g.astype(np.float64)) / np.maximum(den, 1e-300)
+    assert np.max(err) <= u + FP32_REL
+    for B in (1, 64, 300):
+        Zb = _sparse_scenes(cols, c2["N"] ** 2, B, 20 + B)
+        refb = Zb[:, cols].astype(np.float64) @ Aref.T
+        outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+        err = np.max(np.abs(outb - refb), axis=1) / np.max(np.abs(refb), axis=1)
+        assert np.max(err) <= 2 * u, (B, np.max(err))
+    lib.close()

@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (derived from the arithmetic, see the design notes):
+  * geometry (r, cos, sin, w) and brackets: bit-exact (same float64 operations,
+    no contraction, correctly rounded sqrt and division);
+  * FP32 library entries: relative 1e-6, zeros exact;
+  * FP32 images: per-pixel relative 1e-5 (all terms are non-negative), zeros exact;
+  * FP32 adjoint: |dG_j| <= 1e-5 (|A|^T |g|)_j;
+  * column sums: relative 1e-6;
+  * 16-bit forms: entries within the format's rounding unit u (2^-8 bf16,
+    2^-11 fp16) of the FP64 value; images within u per pixel on pixels above
+    1e-6 of the peak and 2u peak-normalised for the batched form.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_REL = 1e-5
+LIB_REL = 1e-6
+U16 = {"bf16": 2.0**-8, "fp16": 2.0**-11}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def psflib():
+    from paper_2106_09122_amd import psflib as p
+    return p
+
+
+def _lib(torch, psflib, cube, radii, N, S, **kw):
+    return psflib.Library(torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float32)).cuda(),
+                          radii, N, S, **kw)
+
+
+def _rel_err_pos(got, ref):
+    """max |got-ref|/ref over ref > 0; asserts exact zeros elsewhere."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    pos = ref > 0
+    assert np.all(got[~pos] == 0), "entries whose exact value is 0 must be exactly 0"
+    if not pos.any():
+        return 0.0
+    return float(np.max(np.abs(got[pos] - ref[pos]) / ref[pos]))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.config_inputs(1)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    return O.build_library(c1["cube"], c1["radii"], c1["N"], c1["S"])
+
+
+# ------------------------------------------------------------- C1 ---------
+def test_c1_geometry_bitwise(torch, psflib, c1):
+    lib = _lib(torch, psflib, c1["cube"], c1["radii"], c1["N"], c1["S"])
+    g, k = lib.geometry()
+    g = g.cpu().numpy()
+    k = k.cpu().numpy()
+    x, y, r, ct, st = O.scene_geometry(c1["N"], c1["S"])
+    assert np.array_equal(g[:, 0], r)
+    assert np.array_equal(g[:, 1], ct)
+    assert np.array_equal(g[:, 2], st)
+    for j in range(r.size):
+        kk, w, zero = O.radial_bracket(r[j], c1["radii"])
+        assert k[j] == kk and g[j, 3] == w, j
+
+
+def test_c1_library_columns(torch, psflib, c1, c1_oracle):
+    lib = _lib(torch, psflib, c1["cube"], c1["radii"], c1["N"], c1["S"])
+    A = lib.get_columns(np.arange(c1["N"] ** 2)).cpu().numpy().T
+    assert _rel_err_pos(A, c1_oracle) <= LIB_REL
+    tau = lib.column_sums().cpu().numpy()
+    ref = O.column_sums(c1_oracle)
+    assert _rel_err_pos(tau, ref) <= LIB_REL
+
+
+def test_c1_apply_adjoint_batched(torch, psflib, c1, c1_oracle):
+    lib = _lib(torch, psflib, c1["cube"], c1["radii"], c1["N"], c1["S"])
+    Z = c1["scene"]
+    img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = O.apply(c1_oracle, Z)
+    assert _rel_err_pos(img, ref) <= FP32_REL
+    # bitwise reproducible
+    img2 = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    assert np.array_equal(img, img2)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(c1["n"] ** 2).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
+    Gref = O.apply_adjoint(c1_oracle, g)
+    den = np.abs(c1_oracle).T @ np.abs(g.astype(np.float64))
+    assert np.max(np.abs(G - Gref) / np.maximum(den, 1e-300)) <= FP32_REL
+    Zb = synth.scene_batch(c1["N"], c1["S"], 5, config=1, rmax_mask=8.0)
+    imgs = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    refb = O.apply_batched(c1_oracle, Zb)
+    assert _rel_err_pos(imgs, refb) <= FP32_REL
+
+
+# ------------------------------------------------- invariants on GPU ------
+def test_point_source_reproduces_sample_and_quarter_turns(torch, psflib):
+    N, S, n = 33, 0.5, 32
+    radii = np.arange(17) * 0.5
+    rng = np.random.default_rng(11)
+    cube = rng.random((17, n, n)).astype(np.float32)
+    lib = _lib(torch, psflib, cube, radii, N, S)
+    C = N // 2
+    cols, want = [], []
+    for m in range(17):
+        for (p, q, rot) in [(C, C + m, 0), (C + m, C, -1), (C, C - m, 2), (C - m, C, 1)]:
+            if m == 0 and rot:
+                continue
+            cols.append(p * N + q)
+            want.append(np.rot90(cube[m], rot))
+    got = lib.get_columns(cols).cpu().numpy()
+    for t in range(len(cols)):
+        assert np.array_equal(got[t].reshape(n, n), want[t]), cols[t]
+    # quarter turns of an arbitrary (off-sample) column are exact too
+    j = (C + 3) * N + (C + 5)
+    jr = [(C + 5) * N + (C - 3), (C - 3) * N + (C - 5), (C - 5) * N + (C + 3)]
+    base = lib.get_columns([j]).cpu().numpy()[0].reshape(n, n)
+    rots = lib.get_columns(jr).cpu().numpy()
+    for t, rot in enumerate([-1, 2, 1]):
+        assert np.array_equal(rots[t].reshape(n, n), np.rot90(base, rot))
+
+
+def test_linearity_and_flux(torch, psflib, c1, c1_oracle):
+    lib = _lib(torch, psflib, c1["cube"], c1["radii"], c1["N"], c1["S"])
+    rng = np.random.default_rng(5)
+    Z1 = rng.random(c1["N"] ** 2).astype(np.float32)
+    Z2 = rng.random(c1["N"] ** 2).astype(np.float32)
+    a = lib.apply(torch.from_numpy(Z1).cuda()).cpu().numpy().astype(np.float64)
+    b = lib.apply(torch.from_numpy(Z2).cuda()).cpu().numpy().astype(np.float64)
+    ab = lib.apply(torch.from_numpy(Z1 + Z2).cuda()).cpu().numpy().astype(np.float64)
+    pos = (a + b) > 0
+    assert np.max(np.abs(ab - a - b)[pos] / (a + b)[pos]) <= 3 * FP32_REL
+    tau = lib.column_sums().cpu().numpy()
+    assert abs(a.sum() - tau @ Z1) <= 1e-5 * (tau @ Z1)
+
+
+# -------------------------------------------------- shapes and modes ------
+SHAPES = [
+    # n, N, S, K, radii kind, interp, oob
+    (33, 7, 0.37, 5, "nonuniform", "linear", "clamp"),
+    (20, 45, 0.21, 9, "linear", "nearest", "zero"),
+    (9, 1, 0.5, 3, "linear", "linear", "clamp"),
+    (16, 13, 0.6, 1, "linear", "linear", "zero"),
+    (64, 17, 0.25, 12, "nonuniform", "linear", "zero"),
+    (36, 36, 0.3, 8, "linear", "nearest", "clamp"),
+]
+
+
+def _shape_inputs(n, N, S, K, kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "nonuniform":
+        radii = np.concatenate([[0.0], np.cumsum(rng.uniform(0.05, 0.9, K - 1))])
+    else:
+        radii = np.linspace(0.0, N * S * 0.6, K)
+    cube = (rng.random((K, n, n)) ** 3).astype(np.float32)
+    return cube, radii, rng
+
+
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES)
+def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
+    cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N)
+    A = O.build_library(cube, radii, N, S, interp, oob)
+    lib = _lib(torch, psflib, cube, radii, N, S, interp=interp, oob=oob)
+    got = lib.get_columns(np.arange(N * N)).cpu().numpy().T
+    assert _rel_err_pos(got, A) <= LIB_REL
+    Z = rng.random(N * N).astype(np.float32)
+    img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    assert _rel_err_pos(img, O.apply(A, Z)) <= FP32_REL
+    g = rng.standard_normal(n * n).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
+    den = np.abs(A).T @ np.abs(g.astype(np.float64))
+    assert np.max(np.abs(G - O.apply_adjoint(A, g)) / np.maximum(den, 1e-300)) <= FP32_REL
+    for B in (0, 1, 3, 70):
+        Zb = rng.random((B, N * N)).astype(np.float32)
+        out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+        assert out.shape == (B, n * n)
+        if B:
+            assert _rel_err_pos(out, O.apply_batched(A, Zb)) <= FP32_REL
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
+    cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
+    A = O.build_library(cube, radii, N, S, interp, oob)
+    e_ref = O.pow2_exponents(O.column_max_bound(cube, radii, N, S, interp, oob))
+    lib = _lib(torch, psflib, cube, radii, N, S, interp=interp, oob=oob, storage=fmt)
+    assert np.array_equal(lib.exponents().cpu().numpy(), e_ref)
+    u = U16[fmt]
+    deq = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
+    # normal range: relative u; fp16 subnormals: absolute half-spacing 2^-25 * 2^e
+    tol = (u * (1 + 1e-5) + LIB_REL) * A + (2.0**-25) * np.ldexp(1.0, e_ref)[None, :]
+    assert np.all(np.abs(deq - A) <= tol)
+    assert np.all(deq[A == 0] == 0)
+    tau = lib.column_sums().cpu().numpy()
+    assert _rel_err_pos(tau, O.column_sums(A)) <= LIB_REL
+    Z = rng.random(N * N).astype(np.float32)
+    ref = O.apply(A, Z)
+    img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    big = ref > 1e-6 * ref.max()
+    assert np.max(np.abs(img - ref)[big] / ref[big]) <= u + FP32_REL
+    g = rng.standard_normal(n * n).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
+    den = np.abs(A).T @ np.abs(g.astype(np.float64))
+    assert np.max(np.abs(G - O.apply_adjoint(A, g)) / np.maximum(den, 1e-300)) <= u + FP32_REL
+    Zb = rng.random((5, N * N)).astype(np.float32)
+    refb = O.apply_batched(A, Zb)
+    outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    for b in range(5):
+        assert np.max(np.abs(outb[b] - refb[b])) <= 2 * u * np.max(np.abs(refb[b])) + 1e-30
