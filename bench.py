@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--cpu-sample-cols", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="time only the headline matvec")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the operator is "
@@ -159,6 +161,12 @@ def main():
     alg_bytes = lib_bytes + 4 * (M + ncols)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     print(f"[bench] fp32 apply {ms * 1e3:.1f} us/scene, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.empty(2**28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        t_copy = _timed(torch, lambda: dst.copy_(src), 20, 3)
+        rows["copy_probe_1GiB"] = {"ms": t_copy, "GB_per_s_read_plus_write": 2 * 2**30 / (t_copy * 1e-3) / 1e9}
+        del src, dst
 
     if not args.no_rows:
         # library build (a1-a3), rebuilt into the same buffer

@@ -4,119 +4,110 @@
 //
 // A is column-major (column j is contiguous), so the forward product is a sum
 // of scaled columns.  It is split over (row block, column chunk) workgroups:
-// each thread owns 4 consecutive rows, walks the chunk's columns with one
-// 16-byte non-temporal load per column, and writes a partial image; a second
-// kernel adds the partials in a fixed order.  Sums are blocked (16 columns per
-// inner sum) so every rounding chain stays short.  Results are bitwise
-// reproducible.
+// each thread owns 4 consecutive rows and walks the chunk's columns with 16
+// independent 16-byte non-temporal loads in flight, and writes a partial
+// image; the last workgroup of each row block adds the partials in a fixed
+// order.  Sums are blocked (16 columns per inner sum) so every rounding chain
+// stays short.  Results are bitwise reproducible.
 #include <math.h>
+#include <stdlib.h>
 
 #include "psflib_internal.h"
 
 namespace psflib {
 
 // ------------------------------------------------------------ forward -----
-// Split-K with the reduction fused into the same launch: every workgroup
-// writes its partial rows, then counts itself in per row block; the last
-// workgroup of a row block to arrive adds the partials of that block in chunk
-// order (so the result does not depend on which workgroup finishes last) and
-// resets the counter for the next call.
-__device__ __forceinline__ bool arrive_last(int32_t* counter, int expected) {
-  __shared__ int last;
-  __threadfence();  // publish this workgroup's partials device-wide
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1) == expected - 1);
-  __syncthreads();
-  if (last) __threadfence();  // see every other workgroup's partials
-  return last;
+// Split-K: workgroups own (row block, column chunk) tiles and write partial
+// images; a second kernel adds the partials of every row in chunk order, so
+// the result does not depend on scheduling.
+// Rows of one 16-column block: v[u] = A[j+u][i0..i0+3] (zero past M).
+template <bool FULL>
+__device__ __forceinline__ void load_block16(const float* __restrict__ A, int64_t M, int64_t i0,
+                                             int64_t j, f32x4* v) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const float* col = A + (j + u) * M + i0;
+    if constexpr (FULL) {
+      v[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[u][e] = (i0 + e < M) ? col[e] : 0.0f;
+    }
+  }
+}
+
+// sum_j A[j][i0..i0+3] Z[j] over [j0, j1), in three levels: 16 columns,
+// 16 blocks of 16, then the rest, so no rounding chain exceeds ~16 + 16 +
+// (j1-j0)/256 additions.
+template <bool FULL>
+__device__ __forceinline__ f32x4 matvec_rows(const float* __restrict__ A,
+                                             const float* __restrict__ Z, int64_t M, int64_t i0,
+                                             int64_t j0, int64_t j1) {
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 outer = zero, mid = zero;
+  int nblk = 0;
+  int64_t j = j0;
+  for (; j + 16 <= j1; j += 16) {
+    f32x4 v[16];
+    load_block16<FULL>(A, M, i0, j, v);
+    f32x4 inner = v[0] * Z[j];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) inner += v[u] * Z[j + u];
+    mid += inner;
+    if (++nblk == 16) {
+      outer += mid;
+      mid = zero;
+      nblk = 0;
+    }
+  }
+  f32x4 inner = zero;
+  for (; j < j1; ++j) {
+    const float* col = A + j * M + i0;
+    f32x4 v;
+    if constexpr (FULL) {
+      v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (i0 + e < M) ? col[e] : 0.0f;
+    }
+    inner += v * Z[j];
+  }
+  mid += inner;
+  return outer + mid;
 }
 
 template <bool VEC>
 __global__ __launch_bounds__(kMvThreads) void matvec_f32_kernel(const float* __restrict__ A,
                                                                 const float* __restrict__ Z,
                                                                 float* __restrict__ part,
-                                                                int32_t* __restrict__ counters,
                                                                 float* __restrict__ out,
-                                                                int64_t M, int64_t ncols) {
+                                                                int64_t M, int64_t ncols,
+                                                                int64_t chunk) {
   const int64_t i0 = ((int64_t)blockIdx.x * kMvThreads + threadIdx.x) * 4;
   const int64_t c = blockIdx.y;
   const int64_t nchunks = gridDim.y;
-  const int64_t j0 = c * kMvChunk;
-  const int64_t j1 = (j0 + kMvChunk < ncols) ? j0 + kMvChunk : ncols;
-  const bool active = i0 < M;
-  const bool full = VEC && (i0 + 4 <= M);
-  f32x4 outer = {0.f, 0.f, 0.f, 0.f};
-  f32x4 inner = {0.f, 0.f, 0.f, 0.f};
-  if (active) {
-    int64_t j = j0;
-    for (; j + 8 <= j1; j += 8) {
-      f32x4 v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float* col = A + (j + u) * M + i0;
-        if (full) {
-          v[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[u][e] = (i0 + e < M) ? col[e] : 0.0f;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) inner += v[u] * Z[j + u];
-      if (((j - j0) & 15) == 8) {
-        outer += inner;
-        inner = (f32x4){0.f, 0.f, 0.f, 0.f};
-      }
-    }
-    for (; j < j1; ++j) {
-      const float* col = A + j * M + i0;
-      f32x4 v;
-      if (full) {
-        v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (i0 + e < M) ? col[e] : 0.0f;
-      }
-      inner += v * Z[j];
-    }
-    outer += inner;
-  }
-  if (nchunks == 1) {
+  const int64_t j0 = c * chunk;
+  const int64_t j1 = (j0 + chunk < ncols) ? j0 + chunk : ncols;
+  // uniform across the workgroup: every row of the block is inside the image
+  const bool block_full = VEC && ((int64_t)(blockIdx.x + 1) * kMvThreads * 4 <= M);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (block_full)
+    acc = matvec_rows<true>(A, Z, M, i0, j0, j1);
+  else if (i0 < M)
+    acc = matvec_rows<false>(A, Z, M, i0, j0, j1);
+  float* dst = ((nchunks == 1) ? out : part + c * M) + i0;
+  if (block_full) {
+    *reinterpret_cast<f32x4*>(dst) = acc;
+  } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (i0 + e < M) out[i0 + e] = outer[e];
-    return;
+      if (i0 + e < M) dst[e] = acc[e];
   }
-  float* dst = part + c * M + i0;
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    if (i0 + e < M) dst[e] = outer[e];
-  if (!arrive_last(counters + blockIdx.x, (int)nchunks)) return;
-  if (active) {
-    f32x4 total = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t c0 = 0; c0 < nchunks; c0 += 16) {
-      f32x4 blk = {0.f, 0.f, 0.f, 0.f};
-      const int64_t c1 = (c0 + 16 < nchunks) ? c0 + 16 : nchunks;
-      for (int64_t cc = c0; cc < c1; ++cc) {
-        const float* src = part + cc * M + i0;
-        if (full) {
-          blk += *reinterpret_cast<const f32x4*>(src);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) blk[e] += (i0 + e < M) ? src[e] : 0.0f;
-        }
-      }
-      total += blk;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (i0 + e < M) out[i0 + e] = total[e];
-  }
-  if (threadIdx.x == 0) counters[blockIdx.x] = 0;
 }
 
 // 16-bit storage: element (i, j) at ((j/8)*M + i)*8 + j%8.  One thread per
-// row; one 16-byte load covers 8 columns.  Z_j is pre-scaled by 2^e_j.
+// row; one 16-byte load covers 8 columns.  The chunk's scene values, scaled by
+// 2^e_j, are staged in LDS and read as broadcasts.
 __device__ __forceinline__ float h16_to_f32(uint32_t h, bool bf16) {
   if (bf16) return __uint_as_float(h << 16);
   return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
@@ -124,14 +115,25 @@ __device__ __forceinline__ float h16_to_f32(uint32_t h, bool bf16) {
 
 template <bool BF16>
 __device__ __forceinline__ void unpack8(const u32x4 p, float* f) {
-  f[0] = h16_to_f32(p.x & 0xFFFFu, BF16);
-  f[1] = h16_to_f32(p.x >> 16, BF16);
-  f[2] = h16_to_f32(p.y & 0xFFFFu, BF16);
-  f[3] = h16_to_f32(p.y >> 16, BF16);
-  f[4] = h16_to_f32(p.z & 0xFFFFu, BF16);
-  f[5] = h16_to_f32(p.z >> 16, BF16);
-  f[6] = h16_to_f32(p.w & 0xFFFFu, BF16);
-  f[7] = h16_to_f32(p.w >> 16, BF16);
+  if constexpr (BF16) {
+    f[0] = __uint_as_float(p.x << 16);
+    f[1] = __uint_as_float(p.x & 0xFFFF0000u);
+    f[2] = __uint_as_float(p.y << 16);
+    f[3] = __uint_as_float(p.y & 0xFFFF0000u);
+    f[4] = __uint_as_float(p.z << 16);
+    f[5] = __uint_as_float(p.z & 0xFFFF0000u);
+    f[6] = __uint_as_float(p.w << 16);
+    f[7] = __uint_as_float(p.w & 0xFFFF0000u);
+  } else {
+    f[0] = h16_to_f32(p.x & 0xFFFFu, false);
+    f[1] = h16_to_f32(p.x >> 16, false);
+    f[2] = h16_to_f32(p.y & 0xFFFFu, false);
+    f[3] = h16_to_f32(p.y >> 16, false);
+    f[4] = h16_to_f32(p.z & 0xFFFFu, false);
+    f[5] = h16_to_f32(p.z >> 16, false);
+    f[6] = h16_to_f32(p.w & 0xFFFFu, false);
+    f[7] = h16_to_f32(p.w >> 16, false);
+  }
 }
 
 template <bool BF16>
@@ -139,93 +141,153 @@ __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* _
                                                                   const int32_t* __restrict__ exps,
                                                                   const float* __restrict__ Z,
                                                                   float* __restrict__ part,
-                                                                  int32_t* __restrict__ counters,
                                                                   float* __restrict__ out,
                                                                   int64_t M, int64_t ncols,
-                                                                  int64_t ngroups) {
-  const int64_t i = (int64_t)blockIdx.x * kMv16Threads + threadIdx.x;
+                                                                  int64_t ngroups, int64_t chunk_g) {
+  __shared__ f32x4 zs[kMv16MaxChunkGroups * 2];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kMv16Threads + tid;
   const int64_t c = blockIdx.y;
   const int64_t nchunks = gridDim.y;
-  const int64_t g0 = c * kMv16Groups;
-  const int64_t g1 = (g0 + kMv16Groups < ngroups) ? g0 + kMv16Groups : ngroups;
+  const int64_t g0 = c * chunk_g;
+  const int64_t g1 = (g0 + chunk_g < ngroups) ? g0 + chunk_g : ngroups;
+  const int64_t ng = g1 - g0;
+  float* zsf = reinterpret_cast<float*>(zs);
+  for (int64_t t = tid; t < ng * 8; t += kMv16Threads) {
+    const int64_t j = g0 * 8 + t;
+    zsf[t] = (j < ncols) ? ldexpf(Z[j], exps[j]) : 0.0f;
+  }
+  __syncthreads();
   const bool active = i < M;
-  float outer = 0.0f;
+  float outer = 0.0f, mid = 0.0f;
   if (active) {
-    for (int64_t g = g0; g < g1; g += 2) {
-      u32x4 p[2];
-      float zs[16];
+    int nblk = 0;
+    int64_t g = g0;
+    for (; g + 16 <= g1; g += 16) {
+      u32x4 p[16];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const bool ok = (g + t) < g1;
-        p[t] = ok ? __builtin_nontemporal_load(Mp + (g + t) * M + i) : (u32x4){0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int64_t j = (g + t) * 8 + u;
-          zs[t * 8 + u] = (ok && j < ncols) ? ldexpf(Z[j], exps[j]) : 0.0f;
-        }
-      }
+      for (int u = 0; u < 16; ++u) p[u] = __builtin_nontemporal_load(Mp + (g + u) * M + i);
       float inner = 0.0f;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int u = 0; u < 16; ++u) {
         float f[8];
-        unpack8<BF16>(p[t], f);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) inner = fmaf(f[u], zs[t * 8 + u], inner);
+        unpack8<BF16>(p[u], f);
+        const f32x4 za = zs[2 * (g - g0 + u)], zb = zs[2 * (g - g0 + u) + 1];
+        inner = fmaf(f[0], za.x, inner);
+        inner = fmaf(f[1], za.y, inner);
+        inner = fmaf(f[2], za.z, inner);
+        inner = fmaf(f[3], za.w, inner);
+        inner = fmaf(f[4], zb.x, inner);
+        inner = fmaf(f[5], zb.y, inner);
+        inner = fmaf(f[6], zb.z, inner);
+        inner = fmaf(f[7], zb.w, inner);
       }
-      outer += inner;
+      mid += inner;
+      if (++nblk == 8) {
+        outer += mid;
+        mid = 0.0f;
+        nblk = 0;
+      }
     }
-  }
-  if (nchunks == 1) {
-    if (active) out[i] = outer;
-    return;
-  }
-  if (active) part[c * M + i] = outer;
-  if (!arrive_last(counters + blockIdx.x, (int)nchunks)) return;
-  if (active) {
-    float total = 0.0f;
-    for (int64_t c0 = 0; c0 < nchunks; c0 += 16) {
-      float blk = 0.0f;
-      const int64_t c1 = (c0 + 16 < nchunks) ? c0 + 16 : nchunks;
-      for (int64_t cc = c0; cc < c1; ++cc) blk += part[cc * M + i];
-      total += blk;
+    float inner = 0.0f;
+    for (; g < g1; ++g) {
+      float f[8];
+      unpack8<BF16>(__builtin_nontemporal_load(Mp + g * M + i), f);
+      const f32x4 za = zs[2 * (g - g0)], zb = zs[2 * (g - g0) + 1];
+      inner = fmaf(f[0], za.x, inner);
+      inner = fmaf(f[1], za.y, inner);
+      inner = fmaf(f[2], za.z, inner);
+      inner = fmaf(f[3], za.w, inner);
+      inner = fmaf(f[4], zb.x, inner);
+      inner = fmaf(f[5], zb.y, inner);
+      inner = fmaf(f[6], zb.z, inner);
+      inner = fmaf(f[7], zb.w, inner);
     }
-    out[i] = total;
+    mid += inner;
+    outer += mid;
   }
-  if (threadIdx.x == 0) counters[blockIdx.x] = 0;
+  if (active) ((nchunks == 1) ? out : part + c * M)[i] = outer;
+}
+
+// out[i] = sum over chunks of part[chunk][i]: blocks of 16 partials loaded
+// together and added in chunk order, then the block sums in order.  One row
+// per thread, so the few megabytes of partials are spread over many waves.
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restrict__ part,
+                                                          int64_t nchunks, int64_t M,
+                                                          float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  float total = 0.0f;
+  for (int64_t c0 = 0; c0 < nchunks; c0 += 16) {
+    float p[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) p[u] = (c0 + u < nchunks) ? part[(c0 + u) * M + i] : 0.0f;
+    float blk = p[0];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) blk += p[u];
+    total += blk;
+  }
+  out[i] = total;
+}
+
+// Split-K shape: about kMvTargetWorkgroups{32,16} workgroups in all (two to
+// three per CU: enough loads in flight to saturate HBM, few partials).  The
+// value can be overridden with PSFLIB_MV_WORKGROUPS for tuning sweeps.
+static int64_t mv_target_workgroups(int storage) {
+  static const long env = [] {
+    const char* e = getenv("PSFLIB_MV_WORKGROUPS");
+    return e ? strtol(e, nullptr, 10) : 0L;
+  }();
+  if (env > 0) return env;
+  return storage == PSFLIB_FP32 ? kMvTargetWorkgroups32 : kMvTargetWorkgroups16;
+}
+
+struct MvShape {
+  int64_t rowblocks, chunk, nchunks;  // chunk: columns (FP32) or 8-column groups (16-bit)
+};
+
+static MvShape mv_shape(int storage, int64_t M, int64_t ncols, int64_t ncols_pad) {
+  MvShape sh;
+  const int64_t rows = (storage == PSFLIB_FP32) ? 4 * kMvThreads : kMv16Threads;
+  const int64_t units = (storage == PSFLIB_FP32) ? ncols : ncols_pad / 8;
+  sh.rowblocks = (M + rows - 1) / rows;
+  int64_t want = (mv_target_workgroups(storage) + sh.rowblocks - 1) / sh.rowblocks;
+  if (want < 1) want = 1;
+  int64_t chunk = (units + want - 1) / want;
+  chunk = (chunk + 15) / 16 * 16;
+  if (storage != PSFLIB_FP32 && chunk > kMv16MaxChunkGroups) chunk = kMv16MaxChunkGroups;
+  sh.chunk = chunk;
+  sh.nchunks = (units + chunk - 1) / chunk;
+  return sh;
 }
 
 int64_t matvec_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad) {
-  if (storage == PSFLIB_FP32) return ((ncols + kMvChunk - 1) / kMvChunk) * M;
-  const int64_t ngroups = ncols_pad / 8;
-  return ((ngroups + kMv16Groups - 1) / kMv16Groups) * M;
-}
-
-int64_t matvec_counters(int storage, int64_t M) {
-  if (storage == PSFLIB_FP32) return (M + 4 * kMvThreads - 1) / (4 * kMvThreads);
-  return (M + kMv16Threads - 1) / kMv16Threads;
+  const MvShape sh = mv_shape(storage, M, ncols, ncols_pad);
+  return sh.nchunks > 1 ? sh.nchunks * M : 0;
 }
 
 hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
-                         int64_t M, int64_t ncols, int64_t ncols_pad, float* partial,
-                         int32_t* counters, float* out, hipStream_t s) {
+                         int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
+                         hipStream_t s) {
+  const MvShape sh = mv_shape(storage, M, ncols, ncols_pad);
+  const dim3 grid((unsigned)sh.rowblocks, (unsigned)sh.nchunks);
   if (storage == PSFLIB_FP32) {
-    const int64_t nchunks = (ncols + kMvChunk - 1) / kMvChunk;
-    const dim3 grid((unsigned)matvec_counters(storage, M), (unsigned)nchunks);
     const float* A = reinterpret_cast<const float*>(lib);
     if (M % 4 == 0)
-      matvec_f32_kernel<true><<<grid, kMvThreads, 0, s>>>(A, Z, partial, counters, out, M, ncols);
+      matvec_f32_kernel<true><<<grid, kMvThreads, 0, s>>>(A, Z, partial, out, M, ncols, sh.chunk);
     else
-      matvec_f32_kernel<false><<<grid, kMvThreads, 0, s>>>(A, Z, partial, counters, out, M, ncols);
+      matvec_f32_kernel<false><<<grid, kMvThreads, 0, s>>>(A, Z, partial, out, M, ncols, sh.chunk);
   } else {
     const int64_t ngroups = ncols_pad / 8;
-    const int64_t nchunks = (ngroups + kMv16Groups - 1) / kMv16Groups;
-    const dim3 grid((unsigned)matvec_counters(storage, M), (unsigned)nchunks);
     const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
     if (storage == PSFLIB_BF16_POW2)
-      matvec_h16_kernel<true><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, counters, out, M, ncols, ngroups);
+      matvec_h16_kernel<true><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, out, M, ncols, ngroups, sh.chunk);
     else
-      matvec_h16_kernel<false><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, counters, out, M, ncols, ngroups);
+      matvec_h16_kernel<false><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, out, M, ncols, ngroups, sh.chunk);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || sh.nchunks == 1) return e;
+  reduce_rows_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(partial, sh.nchunks, M, out);
   return hipGetLastError();
 }
 

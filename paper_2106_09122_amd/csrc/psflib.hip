@@ -20,7 +20,6 @@ struct psflib_handle {
   double* radii_dev;
   float* pmax;
   float* mv_part;
-  int32_t* mv_count;   // arrival counters of the fused split-K reduction
   float* adj_part;
   std::vector<double> radii;  // host copy (source of the radii upload)
 };
@@ -163,8 +162,6 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   const size_t off_pmax = off;  off = align256(off + (size_t)K * 4);
   const size_t off_geo = off;   off = align256(off + (size_t)L.ncols_pad * sizeof(psflib::ColGeom));
   const size_t off_mv = off;    off = align256(off + (size_t)mv_floats * 4);
-  const int64_t ncount = psflib::matvec_counters(storage, L.M);
-  const size_t off_cnt = off;   off = align256(off + (size_t)ncount * 4);
   const size_t off_adj = off;   off = align256(off + (size_t)adj_floats * 4);
   e = hipMalloc(&h->ws, off);
   if (e != hipSuccess) {
@@ -177,7 +174,6 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   h->geo = reinterpret_cast<psflib::ColGeom*>(ws + off_geo);
   h->mv_part = reinterpret_cast<float*>(ws + off_mv);
   h->adj_part = reinterpret_cast<float*>(ws + off_adj);
-  h->mv_count = reinterpret_cast<int32_t*>(ws + off_cnt);
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* lib = reinterpret_cast<char*>(d_lib);
@@ -195,8 +191,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   };
   e = hipMemcpyAsync(h->radii_dev, h->radii.data(), (size_t)K * 8, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
-  e = hipMemsetAsync(h->mv_count, 0, (size_t)ncount * 4, s);
-  if (e != hipSuccess) return bail(e, "hipMemsetAsync(counters)");
+
   e = hipMallocAsync(&pairs, pair_bytes, s);
   if (e != hipSuccess) { pairs = nullptr; return bail(e, "hipMallocAsync(pairs)"); }
   e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(pairs), s);
@@ -225,7 +220,7 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   hipError_t e = psflib::launch_matvec(h->desc.storage, h->lib, exps, d_scene, h->L.M, h->L.ncols,
-                                       h->L.ncols_pad, h->mv_part, h->mv_count, d_image,
+                                       h->L.ncols_pad, h->mv_part, d_image,
                                        reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "matvec kernel");
   return PSFLIB_OK;

@@ -24,9 +24,10 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Launch-shape constants shared between the host code and the kernels.
 constexpr int kBuildThreads = 256;   // build kernel: one workgroup per group of 8 columns
 constexpr int kMvThreads = 256;      // FP32 matvec threads per workgroup (4 rows each)
-constexpr int kMvChunk = 128;        // columns per split-K chunk of the matvec
+constexpr int kMvTargetWorkgroups32 = 512;  // split-K FP32 matvec: workgroups per launch (about)
+constexpr int kMvTargetWorkgroups16 = 768;  // split-K 16-bit matvec: workgroups per launch (about)
 constexpr int kMv16Threads = 256;    // 16-bit matvec threads per workgroup (1 row each)
-constexpr int kMv16Groups = 16;      // 8-column groups per split-K chunk (128 columns)
+constexpr int kMv16MaxChunkGroups = 512;  // 16-bit matvec: 8-column groups per chunk, at most
 constexpr int kAdjThreads = 256;     // adjoint threads per workgroup
 constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 float4 per thread)
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
@@ -51,10 +52,9 @@ hipError_t launch_geometry(int N, double S, const double* radii, int K, int inte
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
-                         int64_t M, int64_t ncols, int64_t ncols_pad, float* partial,
-                         int32_t* counters, float* out, hipStream_t s);
+                         int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
+                         hipStream_t s);
 int64_t matvec_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad);
-int64_t matvec_counters(int storage, int64_t M);
 hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, const float* g,
                           int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                           hipStream_t s);
