@@ -47,6 +47,27 @@ def _timed(torch, fn, iters, warmup):
     return e0.elapsed_time(e1) / iters
 
 
+def _profiled_traffic():
+    """HBM bytes per matvec launch from the committed counter summary, if the
+    kernel source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "matvec_f32_128_hbm_counters.md")
+    try:
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith(("|", "*", "#", " ")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        src = os.path.join(ROOT, kv["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != kv["source_sha256"]:
+                return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _lscpu_model():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -235,7 +256,7 @@ def main():
                    "n": n, "N": N, "n_psf": K, "pixscale_lod": S, "library_bytes": lib_bytes,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _profiled_traffic(),
                      "kernel": "matvec_f32_kernel", "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "rows": rows,

@@ -62,7 +62,7 @@ int64_t adjoint_partial_floats(int storage, int64_t M, int64_t ncols, int64_t nc
 hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, const float* Z,
                           float* out, int64_t M, int64_t ncols, int64_t ncols_pad, int B,
                           void* scratch, size_t scratch_bytes, hipStream_t s);
-size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols_pad, int B);
+size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int B);
 hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
                               const int32_t* cols, int count, int64_t M, int64_t ncols,
                               float* out, hipStream_t s);
