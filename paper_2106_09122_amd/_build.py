@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG_DIR, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG_DIR, "libpsflib.so")
-SOURCES = ["psflib.hip", "geometry.hip", "build.hip", "apply.hip", "gemm.hip"]
+SOURCES = ["psflib.hip", "geometry.hip", "build.hip", "build_lds.hip", "apply.hip", "gemm.hip"]
 ARCH = "gfx950"
 
 
@@ -52,6 +52,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             print(r.stderr)
         return obj
 
+    # a failed build must not leave an older library looking current
+    if os.path.exists(LIB_PATH):
+        os.remove(LIB_PATH)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = LIB_PATH + ".tmp"

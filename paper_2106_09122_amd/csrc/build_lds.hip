@@ -1,0 +1,398 @@
+// Library build with the radial sample pair staged in LDS (Sec. 2; Eqs. (4)-(5)).
+//
+// Columns are grouped by their radial bracket k on the device (a counting sort:
+// histogram, scan, scatter), so a workgroup can stage the two sampled PSFs it
+// needs, P_k and P_{k+1}, once in LDS and build up to kLdsCols columns from
+// them.  The pair is stored interleaved (one 8-byte LDS read returns both
+// radial neighbours of a tap) inside a one-pixel zero border, so the bilinear
+// taps of the rotated sample need no per-tap bounds tests.  One wave builds one
+// column, row by row, lane l owning image columns l, l+64, l+128: every store
+// is a coalesced 256-byte run, and the column sum is a wave reduction.
+//
+// Coordinates follow the oracle's float64 operations exactly (same products,
+// no contraction): per column and lane the products cos*(b-c) and -sin*(b-c)
+// of the lane's image columns are formed once, per row sin*(a-c) and
+// cos*(a-c), and each element adds them.  The fractional offsets and their
+// complements are exact float64 values rounded once to float32; the bilinear
+// weights are their float32 products, the radial blend and the weighted sum
+// are float32 (relative error a few float32 units, as the entries are
+// non-negative combinations).
+//
+// The 16-bit storage forms are built as float32 into scratch and packed by a
+// second kernel (scale by 2^-e_j, round to nearest even, 8 columns per 16 B).
+#include <math.h>
+
+#include "psflib_internal.h"
+
+namespace psflib {
+
+// ------------------------------------------------------------ buckets -----
+// bucket of column j: its bracket k, or nb-1 for an identically zero column.
+// Counts are gathered in an LDS histogram per workgroup and added to the
+// global counts with one atomic per non-empty bucket (few buckets, many
+// columns: direct global atomics would serialise on a handful of addresses).
+__device__ __forceinline__ int bucket_of(const ColGeom* __restrict__ geo, int64_t j, int nb) {
+  const int k = geo[j].k;
+  return k >= 0 ? k : nb - 1;
+}
+
+__global__ __launch_bounds__(256) void bucket_count_kernel(const ColGeom* __restrict__ geo,
+                                                           int64_t ncols, int nb,
+                                                           int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // nb
+  for (int b = threadIdx.x; b < nb; b += 256) hist[b] = 0;
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < ncols) atomicAdd(hist + bucket_of(geo, j, nb), 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += 256)
+    if (hist[b]) atomicAdd(cnt + b, hist[b]);
+}
+
+// One workgroup: bucket starts (exclusive scan of the counts) and the work
+// items (bucket, first sorted position, length <= kLdsCols).
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(const int32_t* __restrict__ cnt, int nb,
+                                                           int32_t* __restrict__ bstart,
+                                                           int4* __restrict__ items,
+                                                           int32_t* __restrict__ nitems) {
+  __shared__ int32_t s_cols[1024], s_items[1024];
+  const int tid = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = tid * per, b1 = (b0 + per < nb) ? b0 + per : nb;
+  int my_cols = 0, my_items = 0;
+  for (int b = b0; b < b1; ++b) {
+    my_cols += cnt[b];
+    my_items += (cnt[b] + kLdsCols - 1) / kLdsCols;
+  }
+  s_cols[tid] = my_cols;
+  s_items[tid] = my_items;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of both arrays
+  for (int off = 1; off < 1024; off <<= 1) {
+    int c = 0, it = 0;
+    if (tid >= off) {
+      c = s_cols[tid - off];
+      it = s_items[tid - off];
+    }
+    __syncthreads();
+    s_cols[tid] += c;
+    s_items[tid] += it;
+    __syncthreads();
+  }
+  int col = s_cols[tid] - my_cols, item = s_items[tid] - my_items;
+  for (int b = b0; b < b1; ++b) {
+    bstart[b] = col;
+    for (int s = 0; s < cnt[b]; s += kLdsCols) {
+      const int len = (cnt[b] - s < kLdsCols) ? cnt[b] - s : kLdsCols;
+      items[item++] = make_int4(b, col + s, len, 0);
+    }
+    col += cnt[b];
+  }
+  if (tid == 1023) *nitems = s_items[1023];
+}
+
+// Positions: a local rank from LDS atomics, one global atomic per non-empty
+// bucket to reserve this workgroup's run of positions.  (The order inside a
+// bucket only decides which workgroup builds a column, not its values.)
+__global__ __launch_bounds__(256) void bucket_scatter_kernel(const ColGeom* __restrict__ geo,
+                                                             int64_t ncols, int nb,
+                                                             const int32_t* __restrict__ bstart,
+                                                             int32_t* __restrict__ cursor,
+                                                             int32_t* __restrict__ order) {
+  extern __shared__ int32_t sh[];  // nb local counts, then nb bases
+  int32_t* lcnt = sh;
+  int32_t* base = sh + nb;
+  for (int b = threadIdx.x; b < nb; b += 256) lcnt[b] = 0;
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int b = 0, r = 0;
+  if (j < ncols) {
+    b = bucket_of(geo, j, nb);
+    r = atomicAdd(lcnt + b, 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb; q += 256)
+    if (lcnt[q]) base[q] = bstart[q] + atomicAdd(cursor + q, lcnt[q]);
+  __syncthreads();
+  if (j < ncols) order[base[b] + r] = (int32_t)j;
+}
+
+// --------------------------------------------------------------- build -----
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Float64 coordinate work of one element, in the oracle's order:
+// sx = ct*ux + st*uy, sy = (-st)*ux + ct*uy, col = c + sx, row = c + sy.
+struct Tap {
+  int idx;           // LDS index of (r0, c0) in the bordered array
+  bool ok;           // all four taps inside the bordered array
+  float fx, gx, fy, gy;  // fx, 1-fx, fy, 1-fy (float32 of the float64 values)
+};
+
+__device__ __forceinline__ Tap tap_coords(double ctux, double mstux, double stuy, double ctuy,
+                                          double c, int n) {
+#pragma clang fp contract(off)
+  const double sx = ctux + stuy;
+  const double sy = mstux + ctuy;
+  const double colf = c + sx;
+  const double rowf = c + sy;
+  const double c0f = floor(colf);
+  const double r0f = floor(rowf);
+  const double fx = colf - c0f;
+  const double fy = rowf - r0f;
+  Tap t;
+  t.fx = (float)fx;
+  t.gx = (float)(1.0 - fx);
+  t.fy = (float)fy;
+  t.gy = (float)(1.0 - fy);
+  // |colf|, |rowf| < 3n, so the integer conversions are exact.  Taps r0, r0+1
+  // (c0, c0+1) lie in the bordered array iff -1 <= r0, c0 <= n-1.
+  const int c0 = (int)c0f, r0 = (int)r0f;
+  t.ok = ((unsigned)(r0 + 1) <= (unsigned)n) && ((unsigned)(c0 + 1) <= (unsigned)n);
+  t.idx = t.ok ? (r0 + 1) * (n + 2) + (c0 + 1) : 0;
+  return t;
+}
+
+template <int E, bool FULL>
+__global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict__ cube, int K,
+                                                         const ColGeom* __restrict__ geo,
+                                                         const int32_t* __restrict__ order,
+                                                         const int4* __restrict__ items,
+                                                         const int32_t* __restrict__ nitems,
+                                                         int nb, int n, int64_t M,
+                                                         float* __restrict__ A,
+                                                         double* __restrict__ tau) {
+  extern __shared__ float2 P2[];  // (n+2)^2 pairs (P_k, P_{k+1}) with a zero border
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, start = it.y, len = it.z;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int np = n + 2;
+  if (!zero_bucket) {
+    const float* Pk = cube + (int64_t)bkt * M;
+    const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+    // zero border
+    for (int idx = tid; idx < 4 * np; idx += 1024) {
+      const int side = idx / np, t = idx % np;
+      const int pos = side == 0 ? t : side == 1 ? (np - 1) * np + t
+                    : side == 2 ? t * np : t * np + np - 1;
+      P2[pos] = make_float2(0.0f, 0.0f);
+    }
+    // interior, 4 pixels (16 B of each PSF) per thread and step when rows allow
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(cube) & 15) == 0) {
+      const int nq = n >> 2;
+      for (int q = tid; q < n * nq; q += 1024) {
+        const int rr = q / nq, cc = 4 * (q - rr * nq);
+        const f32x4 a = *reinterpret_cast<const f32x4*>(Pk + rr * n + cc);
+        const f32x4 b = Pk1 ? *reinterpret_cast<const f32x4*>(Pk1 + rr * n + cc)
+                            : (f32x4){0.f, 0.f, 0.f, 0.f};
+        float2* dst = P2 + (rr + 1) * np + cc + 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = make_float2(a[e], b[e]);
+      }
+    } else {
+      for (int q = tid; q < n * n; q += 1024) {
+        const int rr = q / n, cc = q - rr * n;
+        P2[(rr + 1) * np + cc + 1] = make_float2(Pk[q], Pk1 ? Pk1[q] : 0.0f);
+      }
+    }
+  }
+  __syncthreads();
+  if (wave >= len) return;  // no barrier below
+  const int64_t j = order[start + wave];
+  float* col = A + j * M;
+  if (zero_bucket) {
+    for (int a = 0; a < n; ++a)
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        const int b = lane + 64 * v;
+        if (FULL || b < n) __builtin_nontemporal_store(0.0f, col + a * n + b);
+      }
+    if (lane == 0) tau[j] = 0.0;
+    return;
+  }
+  const ColGeom g = geo[j];
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  double ctux[E], mstux[E];
+#pragma unroll
+  for (int v = 0; v < E; ++v) {
+#pragma clang fp contract(off)
+    const double ux = (double)(lane + 64 * v) - c;
+    ctux[v] = g.ct * ux;
+    mstux[v] = (-g.st) * ux;
+  }
+  double tsum = 0.0;
+  for (int a = 0; a < n; ++a) {
+    double stuy, ctuy;
+    {
+#pragma clang fp contract(off)
+      const double uy = (double)a - c;
+      stuy = g.st * uy;
+      ctuy = g.ct * uy;
+    }
+    float rowsum = 0.0f;
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      const int b = lane + 64 * v;
+      if (FULL || b < n) {
+        const Tap t = tap_coords(ctux[v], mstux[v], stuy, ctuy, c, n);
+        const float2 p00 = P2[t.idx], p01 = P2[t.idx + 1];
+        const float2 p10 = P2[t.idx + np], p11 = P2[t.idx + np + 1];
+        const float q00 = fmaf(wk1, p00.y, wk0 * p00.x);
+        const float q01 = fmaf(wk1, p01.y, wk0 * p01.x);
+        const float q10 = fmaf(wk1, p10.y, wk0 * p10.x);
+        const float q11 = fmaf(wk1, p11.y, wk0 * p11.x);
+        float val = (t.gy * t.gx) * q00;
+        val = fmaf(t.gy * t.fx, q01, val);
+        val = fmaf(t.fy * t.gx, q10, val);
+        val = fmaf(t.fy * t.fx, q11, val);
+        val = t.ok ? val : 0.0f;
+        __builtin_nontemporal_store(val, col + a * n + b);
+        rowsum += val;
+      }
+    }
+    tsum += (double)rowsum;
+  }
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) tau[j] = tsum;
+}
+
+// 16-bit packing: M16[g][i][u] = RN16(A32[8g+u][i] * 2^-e), zeros past ncols.
+// Two rows per thread: 8 x 8-byte loads (one per column; 512 B per wave and
+// column) and 32 contiguous bytes stored.
+template <bool BF16>
+__global__ __launch_bounds__(256) void pack16_kernel(const float* __restrict__ A32,
+                                                     const ColGeom* __restrict__ geo,
+                                                     int64_t M, int64_t ncols,
+                                                     u32x4* __restrict__ Mp) {
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+  const int64_t grp = blockIdx.y;
+  if (i0 >= M) return;
+  const bool pair = (M % 2) == 0;  // then i0 + 1 < M and the 8-byte loads are aligned
+  float v[8][2];
+  int32_t ex[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t j = grp * 8 + u;
+    v[u][0] = v[u][1] = 0.0f;
+    ex[u] = 0;
+    if (j < ncols) {
+      ex[u] = geo[j].e;
+      const float* src = A32 + j * M + i0;
+      if (pair) {
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src));
+        v[u][0] = t.x;
+        v[u][1] = t.y;
+      } else {
+        v[u][0] = src[0];
+        v[u][1] = (i0 + 1 < M) ? src[1] : 0.0f;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (i0 + r >= M) break;
+    uint32_t h[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float x = ldexpf(v[u][r], -ex[u]);
+      if (BF16) {
+        uint32_t w = __float_as_uint(x);
+        w += 0x7FFFu + ((w >> 16) & 1u);
+        h[u] = w >> 16;
+      } else {
+        h[u] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+      }
+    }
+    u32x4 pk;
+    pk.x = h[0] | (h[1] << 16);
+    pk.y = h[2] | (h[3] << 16);
+    pk.z = h[4] | (h[5] << 16);
+    pk.w = h[6] | (h[7] << 16);
+    __builtin_nontemporal_store(pk, Mp + grp * M + i0 + r);
+  }
+}
+
+// ------------------------------------------------------------- launch -----
+static int lds_e(int n) { return (n + 63) / 64; }
+
+bool build_lds_supported(int n, int K) {
+  // the bordered pair must fit the LDS, and the bucket histograms (8 B per
+  // bucket) the sort kernels' LDS
+  return (size_t)(n + 2) * (n + 2) * sizeof(float2) <= (size_t)kLdsBuildMaxBytes && K <= 8192;
+}
+
+static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
+
+size_t build_lds_scratch_bytes(int storage, int K, int64_t M, int64_t ncols) {
+  const int64_t nb = nbuckets(K);
+  const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
+  size_t b = 0;
+  b += ((size_t)nb * 4 * 3 + 255) & ~(size_t)255;           // cnt, cursor, bstart
+  b += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;  // items + nitems
+  b += ((size_t)ncols * 4 + 255) & ~(size_t)255;            // order
+  if (storage != PSFLIB_FP32) b += (size_t)ncols * (size_t)M * 4;  // float32 columns
+  return b;
+}
+
+hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                            int64_t M, int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
+                            void* scratch, hipStream_t s) {
+  const int nb = nbuckets(K);
+  const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
+  char* p = reinterpret_cast<char*>(scratch);
+  int32_t* cnt = reinterpret_cast<int32_t*>(p);
+  int32_t* cursor = cnt + nb;
+  int32_t* bstart = cursor + nb;
+  p += ((size_t)nb * 4 * 3 + 255) & ~(size_t)255;
+  int4* items = reinterpret_cast<int4*>(p);
+  int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
+  p += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;
+  int32_t* order = reinterpret_cast<int32_t*>(p);
+  p += ((size_t)ncols * 4 + 255) & ~(size_t)255;
+  float* A32 = (storage == PSFLIB_FP32) ? reinterpret_cast<float*>(lib) : reinterpret_cast<float*>(p);
+
+  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)nb * 4 * 2, s);  // cnt and cursor
+  if (e != hipSuccess) return e;
+  const unsigned cgrid = (unsigned)((ncols + 255) / 256);
+  bucket_count_kernel<<<cgrid, 256, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt);
+  bucket_scan_kernel<<<1, 1024, 0, s>>>(cnt, nb, bstart, items, nitems);
+  bucket_scatter_kernel<<<cgrid, 256, (size_t)nb * 8, s>>>(geo, ncols, nb, bstart, cursor, order);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  const size_t lds = (size_t)(n + 2) * (n + 2) * sizeof(float2);
+  const unsigned grid = (unsigned)items_max;
+  const void* fn;
+  auto launch = [&](auto kern) -> hipError_t {
+    fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, M, A32, tau);
+    return hipSuccess;
+  };
+  const bool full = (n % 64) == 0;
+  switch (lds_e(n)) {
+    case 1: e = full ? launch(build_lds_kernel<1, true>) : launch(build_lds_kernel<1, false>); break;
+    case 2: e = full ? launch(build_lds_kernel<2, true>) : launch(build_lds_kernel<2, false>); break;
+    default: e = launch(build_lds_kernel<3, false>); break;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGetLastError();
+  if (e != hipSuccess || storage == PSFLIB_FP32) return e;
+  const dim3 pgrid((unsigned)((M + 511) / 512), (unsigned)(ncols_pad / 8));
+  u32x4* Mp = reinterpret_cast<u32x4*>(lib);
+  if (storage == PSFLIB_BF16_POW2)
+    pack16_kernel<true><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+  else
+    pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+  return hipGetLastError();
+}
+
+}  // namespace psflib

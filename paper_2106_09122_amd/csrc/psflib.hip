@@ -179,23 +179,24 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   char* lib = reinterpret_cast<char*>(d_lib);
   double* tau = reinterpret_cast<double*>(lib + L.off_tau);
   int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
-  const size_t pair_bytes = (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
-  void* pairs = nullptr;
+  // Small PSFs (the bordered pair fits the LDS): bucketed LDS build; larger
+  // ones gather from a pair-interleaved copy of the cube.
+  const bool lds = psflib::build_lds_supported(desc->n, K);
+  const size_t tmp_bytes = lds ? psflib::build_lds_scratch_bytes(storage, K, L.M, L.ncols)
+                               : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
+  void* tmp = nullptr;
   auto bail = [&](hipError_t err, const char* what) {
     psflib_status r = device_fail(err, what);
     (void)hipDeviceSynchronize();
-    if (pairs) (void)hipFree(pairs);
+    if (tmp) (void)hipFree(tmp);
     (void)hipFree(h->ws);
     delete h;
     return r;
   };
   e = hipMemcpyAsync(h->radii_dev, h->radii.data(), (size_t)K * 8, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
-
-  e = hipMallocAsync(&pairs, pair_bytes, s);
-  if (e != hipSuccess) { pairs = nullptr; return bail(e, "hipMallocAsync(pairs)"); }
-  e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(pairs), s);
-  if (e != hipSuccess) return bail(e, "pair_cube kernel");
+  e = hipMallocAsync(&tmp, tmp_bytes, s);
+  if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipMallocAsync(build scratch)"); }
   if (storage != PSFLIB_FP32) {
     e = psflib::launch_cube_max(d_cube, K, L.M, h->pmax, s);
     if (e != hipSuccess) return bail(e, "cube_max kernel");
@@ -204,11 +205,19 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
-  e = psflib::launch_build(storage, reinterpret_cast<const float*>(pairs), h->geo, desc->n, L.M,
-                           L.ncols, L.ncols_pad, d_lib, tau, s);
-  if (e != hipSuccess) return bail(e, "build kernel");
-  e = hipFreeAsync(pairs, s);
-  if (e != hipSuccess) { pairs = nullptr; return bail(e, "hipFreeAsync(pairs)"); }
+  if (lds) {
+    e = psflib::launch_build_lds(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
+                                 d_lib, tau, tmp, s);
+    if (e != hipSuccess) return bail(e, "LDS build kernels");
+  } else {
+    e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(tmp), s);
+    if (e != hipSuccess) return bail(e, "pair_cube kernel");
+    e = psflib::launch_build(storage, reinterpret_cast<const float*>(tmp), h->geo, desc->n, L.M,
+                             L.ncols, L.ncols_pad, d_lib, tau, s);
+    if (e != hipSuccess) return bail(e, "build kernel");
+  }
+  e = hipFreeAsync(tmp, s);
+  if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipFreeAsync(build scratch)"); }
   *out = h;
   return PSFLIB_OK;
 }

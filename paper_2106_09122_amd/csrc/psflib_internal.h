@@ -33,6 +33,8 @@ constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 floa
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
 constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
 constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
+constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
+constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 
 struct Layout {
   int64_t M;          // n*n image pixels (rows of A)
@@ -51,6 +53,11 @@ hipError_t launch_geometry(int N, double S, const double* radii, int K, int inte
                            int32_t* exps, hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
+bool build_lds_supported(int n, int K);
+size_t build_lds_scratch_bytes(int storage, int K, int64_t M, int64_t ncols);
+hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                            int64_t M, int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
+                            void* scratch, hipStream_t s);
 hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
                          int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                          hipStream_t s);

@@ -158,6 +158,8 @@ SHAPES = [
     (16, 13, 0.6, 1, "linear", "linear", "zero"),
     (64, 17, 0.25, 12, "nonuniform", "linear", "zero"),
     (36, 36, 0.3, 8, "linear", "nearest", "clamp"),
+    # PSFs too large for the LDS-staged build take the gather path
+    (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
 ]
 
 
@@ -194,7 +196,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[-1:] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
