@@ -208,6 +208,19 @@ def main():
                 "ms": t_b, "scenes_per_s": B / (t_b * 1e-3), "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
                 "frac_mfma_fp32": fl / (t_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
             del Zb, out
+        # differentiation: one fitting step (render disk, simulate, chi-square,
+        # backward through the adjoint and the renderer) on the 128^2 library
+        from paper_2106_09122_amd import fit
+        Ztrue = fit.render_disk(torch.tensor(synth.DISK_TRUE, dtype=torch.float64, device=dev),
+                                N, S, 8.0)
+        counts, Kc, var = synth.noisy_counts(lib.apply(Ztrue).cpu().numpy(), 2e4,
+                                             synth.rng_for(4, synth.STREAM_NOISE))
+        ct = torch.from_numpy(counts).to(dev)
+        vt = torch.from_numpy(var).to(dev)
+        th0 = torch.tensor(synth.DISK_START, dtype=torch.float64, device=dev)
+        t_fit = _timed(torch, lambda: fit.loss_and_grad(lib, th0, ct, vt, Kc, 8.0), 50, 5)
+        rows["fit_step_fp32"] = {"ms": t_fit, "steps_per_s": 1e3 / t_fit,
+                                 "note": "render + A Z + chi2 + A^T g + render gradient"}
         for fmt in ("bf16", "fp16"):
             lh = psflib.Library(cube, d["radii"], N, S, storage=fmt)
             torch.cuda.synchronize()

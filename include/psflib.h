@@ -164,6 +164,26 @@ psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void*
  * last sample).  Either output pointer may be NULL. */
 psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_t* d_k, void* stream);
 
+/* ---- Fitting model -------------------------------------------------------
+ * A smooth parametric exozodi disk on the scene grid of Eqs. (2)-(3), the
+ * model that is fitted through the operator (Sec. 5 plans the retrieval of
+ * disk parameters from simulated images; these two calls supply the model and
+ * its gradient, psflib_apply_adjoint the operator's).
+ *   d_theta  float64 [5] in device memory: (incl [rad], r0, width, gamma, flux)
+ *   Z_j = flux (rho/r0)^gamma exp(-(rho - r0)^2 / (2 width^2)),
+ *   rho = sqrt(x^2 + (y / cos incl)^2); Z_j = 0 where rho = 0 or where the
+ *   pixel's sky radius exceeds rmax.  Evaluated in float64.
+ * N in [1, 46340], S > 0 and finite, rmax not NaN. */
+psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
+                                 const double* d_theta, float* d_scene, void* stream);
+
+/* d_dtheta[k] = sum_j d_dscene[j] * dZ_j/dtheta_k (float64 [5]), accumulated in
+ * float64 in a fixed order (one workgroup; intended for scenes up to ~1e6
+ * pixels). */
+psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double rmax,
+                                      const double* d_theta, const float* d_dscene,
+                                      double* d_dtheta, void* stream);
+
 /* Release the handle and its workspace.  Waits for the device to finish work
  * that uses the workspace.  NULL is ignored. */
 void psflib_destroy(psflib_handle* h);

@@ -53,7 +53,7 @@ __all__ = [
     "scene_geometry", "radial_bracket", "interpolate_radial", "rotate_bilinear",
     "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
     "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
-    "quantize_library", "scale_exponent",
+    "quantize_library", "scale_exponent", "render_disk", "render_disk_grad",
 ]
 
 
@@ -284,3 +284,45 @@ def quantize_library(A: np.ndarray, e: np.ndarray, fmt: str) -> np.ndarray:
     float64 (exact)."""
     A = np.asarray(A, dtype=np.float64)
     return round_to_format(A * np.ldexp(1.0, -np.asarray(e, dtype=np.int64))[None, :], fmt)
+
+
+# ------------------------------------------------ fitting model (disk) ----
+# A smooth parametric exozodi disk, the model fitted through the operator
+# (the gradient analogue of the retrieval the paper's conclusions plan).
+# Parameters theta = (incl [rad], r0, width, gamma, flux):
+#   rho = sqrt(x^2 + (y / cos incl)^2)       (deprojected radius, x on the major axis)
+#   Z   = flux * (rho/r0)^gamma * exp(-(rho - r0)^2 / (2 width^2))
+# on the scene meshgrid of Eqs. (2)-(3); Z = 0 where rho == 0 or where the sky
+# radius exceeds rmax (the paper masks scenes outside the working angle).
+
+def render_disk(N: int, S: float, rmax: float, theta) -> np.ndarray:
+    """Disk scene Z (float64 [N*N]) for parameters theta."""
+    incl, r0, w, g, F = (float(t) for t in theta)
+    x, y, r, _, _ = scene_geometry(N, S)
+    ci = math.cos(incl)
+    rho = np.sqrt(x * x + (y / ci) ** 2)
+    Z = np.zeros_like(rho)
+    m = (rho > 0) & (r <= rmax)
+    u = rho[m] / r0
+    Z[m] = F * u**g * np.exp(-((rho[m] - r0) ** 2) / (2 * w * w))
+    return Z
+
+
+def render_disk_grad(N: int, S: float, rmax: float, theta, dZ) -> np.ndarray:
+    """Chain rule through the renderer: sum_j dZ_j * dZ_j/dtheta (float64 [5])."""
+    incl, r0, w, g, F = (float(t) for t in theta)
+    x, y, r, _, _ = scene_geometry(N, S)
+    ci, si = math.cos(incl), math.sin(incl)
+    rho = np.sqrt(x * x + (y / ci) ** 2)
+    m = (rho > 0) & (r <= rmax)
+    rho, y, d = rho[m], y[m], np.asarray(dZ, dtype=np.float64)[m]
+    Z = F * (rho / r0) ** g * np.exp(-((rho - r0) ** 2) / (2 * w * w))
+    dZ_drho = Z * (g / rho - (rho - r0) / (w * w))
+    drho_dincl = y * y * si / (ci**3 * rho)
+    out = np.empty(5)
+    out[0] = np.sum(d * dZ_drho * drho_dincl)
+    out[1] = np.sum(d * Z * (-g / r0 + (rho - r0) / (w * w)))
+    out[2] = np.sum(d * Z * (rho - r0) ** 2 / w**3)
+    out[3] = np.sum(d * Z * np.log(rho / r0))
+    out[4] = np.sum(d * Z / F)
+    return out

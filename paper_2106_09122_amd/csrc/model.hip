@@ -1,0 +1,107 @@
+// Parametric exozodi disk rendered on the scene grid, and its parameter
+// gradient: the model side of fitting a disk through the operator (the
+// gradient analogue of the parameter retrieval the paper's conclusions plan).
+//
+// theta = (incl [rad], r0, width, gamma, flux), float64 in device memory:
+//   rho = sqrt(x^2 + (y / cos incl)^2),  x = (q - (N-1)/2) S, y = (p - (N-1)/2) S
+//   Z   = flux (rho/r0)^gamma exp(-(rho - r0)^2 / (2 width^2))
+// and Z = 0 where rho = 0 or where the sky radius sqrt(x^2 + y^2) > rmax.
+// Everything is evaluated in float64; the scene is stored as float32.
+#include <math.h>
+
+#include "psflib_internal.h"
+
+namespace psflib {
+
+struct DiskTerms {
+  bool live;
+  double Z, dZdrho, rho, y;
+};
+
+__device__ __forceinline__ DiskTerms disk_terms(int64_t j, int N, double S, double rmax,
+                                                const double* th) {
+  DiskTerms d;
+  const int64_t p = j / N, q = j - p * N;
+  const double C = (double)(N - 1) * 0.5;
+  const double x = ((double)q - C) * S, y = ((double)p - C) * S;
+  const double ci = cos(th[0]);
+  const double yc = y / ci;
+  const double rho = sqrt(x * x + yc * yc);
+  const double r = sqrt(x * x + y * y);
+  d.live = rho > 0.0 && r <= rmax;
+  d.rho = rho;
+  d.y = y;
+  d.Z = 0.0;
+  d.dZdrho = 0.0;
+  if (d.live) {
+    const double r0 = th[1], w = th[2], g = th[3], F = th[4];
+    const double dr = rho - r0;
+    d.Z = F * exp(g * log(rho / r0) - dr * dr / (2.0 * w * w));
+    d.dZdrho = d.Z * (g / rho - dr / (w * w));
+  }
+  return d;
+}
+
+__global__ __launch_bounds__(256) void render_disk_kernel(int N, double S, double rmax,
+                                                          const double* __restrict__ theta,
+                                                          float* __restrict__ Z) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= (int64_t)N * N) return;
+  double th[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) th[k] = theta[k];
+  Z[j] = (float)disk_terms(j, N, S, rmax, th).Z;
+}
+
+// One workgroup: dtheta_k = sum_j dZ_j dZ_j/dtheta_k, float64, fixed order
+// (each thread a strided set of pixels, then a tree).
+__global__ __launch_bounds__(1024) void render_disk_grad_kernel(int N, double S, double rmax,
+                                                                const double* __restrict__ theta,
+                                                                const float* __restrict__ dZ,
+                                                                double* __restrict__ dtheta) {
+  __shared__ double red[5][1024];
+  double th[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) th[k] = theta[k];
+  const double ci = cos(th[0]), si = sin(th[0]);
+  const double r0 = th[1], w = th[2], g = th[3], F = th[4];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t npix = (int64_t)N * N;
+  for (int64_t j = threadIdx.x; j < npix; j += 1024) {
+    const DiskTerms d = disk_terms(j, N, S, rmax, th);
+    if (!d.live) continue;
+    const double gz = (double)dZ[j] * d.Z;
+    const double dr = d.rho - r0;
+    acc[0] += (double)dZ[j] * d.dZdrho * (d.y * d.y * si / (ci * ci * ci * d.rho));
+    acc[1] += gz * (-g / r0 + dr / (w * w));
+    acc[2] += gz * dr * dr / (w * w * w);
+    acc[3] += gz * log(d.rho / r0);
+    acc[4] += gz / F;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) dtheta[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,
+                              hipStream_t s) {
+  const int64_t npix = (int64_t)N * N;
+  render_disk_kernel<<<(unsigned)((npix + 255) / 256), 256, 0, s>>>(N, S, rmax, theta, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
+                                   const float* dZ, double* dtheta, hipStream_t s) {
+  render_disk_grad_kernel<<<1, 1024, 0, s>>>(N, S, rmax, theta, dZ, dtheta);
+  return hipGetLastError();
+}
+
+}  // namespace psflib

@@ -326,6 +326,37 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
   return PSFLIB_OK;
 }
 
+static psflib_status check_model_args(int32_t N, double S, double rmax, const void* a,
+                                      const void* b) {
+  if (N < 1 || N > kMaxScene) return fail(PSFLIB_ERR_INVALID_ARG, "N must be in [1, 46340]");
+  if (!(S > 0.0) || !isfinite(S)) return fail(PSFLIB_ERR_INVALID_ARG, "scene_pixscale must be finite and > 0");
+  if (isnan(rmax)) return fail(PSFLIB_ERR_INVALID_ARG, "rmax must not be NaN");
+  if (!a || !b) return fail(PSFLIB_ERR_INVALID_ARG, "device pointers must be non-NULL");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
+                                 const double* d_theta, float* d_scene, void* stream) {
+  psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_scene);
+  if (st != PSFLIB_OK) return st;
+  hipError_t e = psflib::launch_render_disk(N, scene_pixscale, rmax, d_theta, d_scene,
+                                            reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "render_disk kernel");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double rmax,
+                                      const double* d_theta, const float* d_dscene,
+                                      double* d_dtheta, void* stream) {
+  psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_dscene);
+  if (st != PSFLIB_OK) return st;
+  if (!d_dtheta) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be non-NULL");
+  hipError_t e = psflib::launch_render_disk_grad(N, scene_pixscale, rmax, d_theta, d_dscene,
+                                                 d_dtheta, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "render_disk_grad kernel");
+  return PSFLIB_OK;
+}
+
 void psflib_destroy(psflib_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();

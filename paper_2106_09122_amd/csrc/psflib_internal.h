@@ -73,6 +73,10 @@ size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncol
 hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
                               const int32_t* cols, int count, int64_t M, int64_t ncols,
                               float* out, hipStream_t s);
+hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,
+                              hipStream_t s);
+hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
+                                   const float* dZ, double* dtheta, hipStream_t s);
 hipError_t launch_export_geometry(const ColGeom* geo, int64_t ncols, double* geom, int32_t* k,
                                   hipStream_t s);
 

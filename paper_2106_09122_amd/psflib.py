@@ -69,6 +69,8 @@ def _load():
         "psflib_get_columns": (I32, [P, P, I32, P, P]),
         "psflib_get_exponents": (I32, [P, P, P]),
         "psflib_get_geometry": (I32, [P, P, P, P]),
+        "psflib_render_disk": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P]),
+        "psflib_render_disk_grad": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P, P]),
         "psflib_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -85,6 +87,7 @@ SYMBOLS = (
     "psflib_status_string", "psflib_last_error", "psflib_library_bytes", "psflib_build",
     "psflib_apply", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
+    "psflib_render_disk", "psflib_render_disk_grad",
 )
 
 
@@ -160,6 +163,20 @@ def get_exponents(h: int, d_exp: int, stream: int):
 def get_geometry(h: int, d_geom: int, d_k: int, stream: int):
     _check(_lib.psflib_get_geometry(ctypes.c_void_p(h), ctypes.c_void_p(d_geom), ctypes.c_void_p(d_k),
                                     ctypes.c_void_p(stream)), "psflib_get_geometry")
+
+
+def render_disk(N: int, S: float, rmax: float, d_theta: int, d_scene: int, stream: int):
+    _check(_lib.psflib_render_disk(ctypes.c_int32(N), ctypes.c_double(S), ctypes.c_double(rmax),
+                                   ctypes.c_void_p(d_theta), ctypes.c_void_p(d_scene),
+                                   ctypes.c_void_p(stream)), "psflib_render_disk")
+
+
+def render_disk_grad(N: int, S: float, rmax: float, d_theta: int, d_dscene: int, d_dtheta: int,
+                     stream: int):
+    _check(_lib.psflib_render_disk_grad(ctypes.c_int32(N), ctypes.c_double(S), ctypes.c_double(rmax),
+                                        ctypes.c_void_p(d_theta), ctypes.c_void_p(d_dscene),
+                                        ctypes.c_void_p(d_dtheta), ctypes.c_void_p(stream)),
+           "psflib_render_disk_grad")
 
 
 def destroy(h: int):

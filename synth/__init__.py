@@ -10,5 +10,5 @@ from .inputs import (  # noqa: F401
     SEED_ROOT, STREAM_ABERR, STREAM_DISK, STREAM_PLANETS, STREAM_NOISE,
     STREAM_SUBSAMPLE, STREAM_BATCH, CONFIGS, rng_for, radii_linspace,
     radii_nonuniform, throughput, psf_cube, ring_scene, planets, add_planets,
-    random_ring_params, scene_batch, config_inputs,
+    random_ring_params, scene_batch, config_inputs, DISK_TRUE, DISK_START, noisy_counts,
 )

@@ -222,3 +222,20 @@ def config_inputs(config: int, *, with_cube: bool = True) -> dict:
         scene = add_planets(scene, pl)
     out["scene"] = scene.ravel()
     return out
+
+
+# ------------------------------------------------------ fitting data -------
+DISK_TRUE = (1.0471975511965976, 5.0, 1.2, -1.4, 3e-8)  # (60 deg, r0, width, gamma, flux)
+DISK_START = (0.9, 5.6, 1.5, -1.1, 2e-8)
+
+
+def noisy_counts(image, peak_counts: float, rng: np.random.Generator, read_noise: float = 3.0):
+    """Detector counts for a simulated image: Poisson(K * image) + N(0, read_noise^2),
+    with K chosen so the brightest pixel expects `peak_counts`.  Returns
+    (counts float64, K, variance estimate max(counts, 1) + read_noise^2)."""
+    image = np.asarray(image, dtype=np.float64)
+    K = peak_counts / image.max()
+    lam = np.clip(K * image, 0.0, None)
+    counts = rng.poisson(lam).astype(np.float64) + rng.normal(0.0, read_noise, size=lam.shape)
+    var = np.maximum(counts, 1.0) + read_noise**2
+    return counts, K, var

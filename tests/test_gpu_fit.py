@@ -1,0 +1,115 @@
+"""Differentiation through the operator (GPU): the disk renderer and its
+gradient against the FP64 oracle, the chi-square gradient through
+render -> A Z -> chi2 (backward through the adjoint kernel) against the FP64
+oracle chain, a directional finite difference, and a short fit.
+
+Data for the chi-square come from the oracle's image of the true disk plus
+seeded Poisson and Gaussian noise, so no expected value depends on the HIP
+path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RMAX = 8.0
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def setup(torch):
+    from paper_2106_09122_amd import psflib
+    d = synth.config_inputs(1)
+    lib = psflib.Library(torch.from_numpy(d["cube"]).cuda(), d["radii"], d["N"], d["S"])
+    A = O.build_library(d["cube"], d["radii"], d["N"], d["S"])
+    Ztrue = O.render_disk(d["N"], d["S"], RMAX, synth.DISK_TRUE)
+    counts, K, var = synth.noisy_counts(A @ Ztrue, 2e4, synth.rng_for(4, synth.STREAM_NOISE))
+    return d, lib, A, counts, K, var
+
+
+def test_render_matches_oracle(torch, setup):
+    from paper_2106_09122_amd import fit
+    d = setup[0]
+    for th in (synth.DISK_TRUE, synth.DISK_START, (0.0, 3.0, 0.5, -2.0, 1.0)):
+        t = torch.tensor(th, dtype=torch.float64, device="cuda")
+        Z = fit.render_disk(t, d["N"], d["S"], RMAX).cpu().numpy().astype(np.float64)
+        ref = O.render_disk(d["N"], d["S"], RMAX, th)
+        pos = ref > 0
+        assert np.all(Z[~pos] == 0)
+        assert np.max(np.abs(Z[pos] - ref[pos]) / ref[pos]) <= 1e-6
+
+
+def test_render_grad_matches_oracle(torch, setup):
+    from paper_2106_09122_amd import psflib
+    d = setup[0]
+    N, S = d["N"], d["S"]
+    rng = np.random.default_rng(31)
+    dZ = rng.standard_normal(N * N).astype(np.float32)
+    th = torch.tensor(synth.DISK_START, dtype=torch.float64, device="cuda")
+    dZt = torch.from_numpy(dZ).cuda()
+    out = torch.empty(5, dtype=torch.float64, device="cuda")
+    psflib.render_disk_grad(N, S, RMAX, th.data_ptr(), dZt.data_ptr(), out.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    ref = O.render_disk_grad(N, S, RMAX, synth.DISK_START, dZ.astype(np.float64))
+    scale = O.render_disk_grad(N, S, RMAX, synth.DISK_START, np.abs(dZ.astype(np.float64)))
+    got = out.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-9 * np.abs(scale) + 1e-300), (got, ref)
+
+
+def _oracle_chi2_grad(A, d, theta, counts, var, K):
+    Z = O.render_disk(d["N"], d["S"], RMAX, theta)
+    S = O.apply(A, Z)
+    r = K * S - counts
+    L = float(np.sum(r * r / var))
+    dS = 2.0 * K * r / var
+    return L, O.render_disk_grad(d["N"], d["S"], RMAX, theta, O.apply_adjoint(A, dS))
+
+
+def test_chi2_gradient_matches_oracle_and_fd(torch, setup):
+    from paper_2106_09122_amd import fit
+    d, lib, A, counts, K, var = setup
+    ct = torch.from_numpy(counts).cuda()
+    vt = torch.from_numpy(var).cuda()
+    th = torch.tensor(synth.DISK_START, dtype=torch.float64, device="cuda")
+    L, g = fit.loss_and_grad(lib, th, ct, vt, K, RMAX)
+    Lref, gref = _oracle_chi2_grad(A, d, synth.DISK_START, counts, var, K)
+    assert abs(float(L) - Lref) <= 1e-4 * Lref
+    g = g.cpu().numpy()
+    assert np.linalg.norm(g - gref) <= 2e-3 * np.linalg.norm(gref), (g, gref)
+    # directional central difference of the GPU loss
+    v = np.array([0.02, 0.05, 0.03, 0.04, 0.0]) * np.array([1, 1, 1, 1, 1])
+    h = 1.0
+    tp = torch.tensor(np.array(synth.DISK_START) + h * v, dtype=torch.float64, device="cuda")
+    tm = torch.tensor(np.array(synth.DISK_START) - h * v, dtype=torch.float64, device="cuda")
+    Lp, _ = fit.loss_and_grad(lib, tp, ct, vt, K, RMAX)
+    Lm, _ = fit.loss_and_grad(lib, tm, ct, vt, K, RMAX)
+    # exact directional derivative of the FP64 oracle loss along v (smooth in theta)
+    Lp_ref, _ = _oracle_chi2_grad(A, d, tuple(np.array(synth.DISK_START) + 1e-4 * v), counts, var, K)
+    Lm_ref, _ = _oracle_chi2_grad(A, d, tuple(np.array(synth.DISK_START) - 1e-4 * v), counts, var, K)
+    dd_ref = (Lp_ref - Lm_ref) / 2e-4
+    assert abs(float(g @ v) - dd_ref) <= 2e-3 * abs(dd_ref)
+    # the wide GPU difference agrees to its truncation error
+    assert abs(float(Lp - Lm) / (2 * h) - dd_ref) <= 0.1 * abs(dd_ref)
+
+
+def test_fit_reduces_chi2_and_moves_towards_truth(torch, setup):
+    from paper_2106_09122_amd import fit
+    d, lib, A, counts, K, var = setup
+    ct = torch.from_numpy(counts).cuda()
+    vt = torch.from_numpy(var).cuda()
+    theta, losses = fit.fit_disk(lib, ct, vt, K, synth.DISK_START, RMAX, steps=64)
+    assert losses[-1] < 0.25 * losses[0]
+    t = theta.cpu().numpy()
+    tt, t0 = np.array(synth.DISK_TRUE), np.array(synth.DISK_START)
+    for k in (0, 1, 2):  # geometry parameters move towards the truth
+        assert abs(t[k] - tt[k]) < abs(t0[k] - tt[k]), (k, t, tt, t0)

@@ -380,3 +380,36 @@ def test_scale_exponent_and_bound():
     bound = O.column_max_bound(cube, radii, 9, 0.4)
     A = O.build_library(cube, radii, 9, 0.4)
     assert np.all(A.max(axis=0) <= bound * (1 + 1e-15))
+
+
+# ------------------------------------------------------ fitting model ------
+THETA = (math.radians(55.0), 5.0, 1.2, -1.4, 3e-8)
+
+
+def test_disk_gradient_matches_central_differences():
+    """The chain-rule gradient of the disk renderer against central finite
+    differences of the renderer itself (FP64), for a random linear functional."""
+    N, S, rmax = 33, 0.5, 8.0
+    rng = np.random.default_rng(21)
+    dZ = rng.standard_normal(N * N)
+    g = O.render_disk_grad(N, S, rmax, THETA, dZ)
+    for k in range(5):
+        h = 1e-6 * max(abs(THETA[k]), 1e-3)
+        tp, tm = list(THETA), list(THETA)
+        tp[k] += h
+        tm[k] -= h
+        fd = (dZ @ O.render_disk(N, S, rmax, tp) - dZ @ O.render_disk(N, S, rmax, tm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * (abs(fd) + abs(g[k])) + 1e-30, (k, fd, g[k])
+
+
+def test_disk_face_on_is_radial_and_peaks_near_r0():
+    N, S = 65, 0.25
+    th = (0.0, 5.0, 0.6, -1.0, 1.0)
+    Z = O.render_disk(N, S, 100.0, th).reshape(N, N)
+    assert np.allclose(Z, Z.T) and np.allclose(Z, Z[::-1, :])
+    x, y, r, _, _ = O.scene_geometry(N, S)
+    rr = r.reshape(N, N)
+    peak = rr.ravel()[np.argmax(Z)]
+    # maximum of u^g exp(-(rho-r0)^2/2w^2): g/rho = (rho - r0)/w^2
+    rho_star = (5.0 + math.sqrt(25.0 + 4 * 0.36 * -1.0)) / 2
+    assert abs(peak - rho_star) <= S
