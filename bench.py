@@ -221,6 +221,27 @@ def main():
         t_fit = _timed(torch, lambda: fit.loss_and_grad(lib, th0, ct, vt, Kc, 8.0), 50, 5)
         rows["fit_step_fp32"] = {"ms": t_fit, "steps_per_s": 1e3 / t_fit,
                                  "note": "render + A Z + chi2 + A^T g + render gradient"}
+        # mixed sizes and wavelengths: 256 scenes over 33 libraries, one graph launch
+        libs_m, scene_lib, scenes_m = synth.mixed_workload()
+        Zm = [torch.from_numpy(z).to(dev) for z in scenes_m]
+        for fmt in ("fp32", "fp16"):
+            Ls = [psflib.Library(torch.from_numpy(l["cube"]).to(dev), l["radii"], l["N"], l["S"],
+                                 storage=fmt) for l in libs_m]
+            torch.cuda.synchronize()
+            gp = psflib.Grouped(Ls, scene_lib, Zm, autotune=True)
+            t_g = _timed(torch, lambda: gp.run(), 20, 3)
+            used = sorted(set(scene_lib))
+            nbytes = sum(Ls[L].M * (Ls[L].ncols if fmt == "fp32" else (Ls[L].ncols + 63) // 64 * 64)
+                         * (4 if fmt == "fp32" else 2) for L in used)
+            rows[f"grouped_{fmt}"] = {"ms": t_g, "scenes_per_s": len(scene_lib) / (t_g * 1e-3),
+                                      "GB_per_s": nbytes / (t_g * 1e-3) / 1e9,
+                                      "libraries": len(used), "scenes": len(scene_lib),
+                                      "chunk": gp.chunk()[0]}
+            gp.close()
+            for Lb in Ls:
+                Lb.close()
+            del Ls, gp
+        del Zm
         for fmt in ("bf16", "fp16"):
             lh = psflib.Library(cube, d["radii"], N, S, storage=fmt)
             torch.cuda.synchronize()

@@ -164,6 +164,43 @@ psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void*
  * last sample).  Either output pointer may be NULL. */
 psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_t* d_k, void* stream);
 
+/* ---- Grouped simulation --------------------------------------------------
+ * Many scenes, each simulated with its own library (libraries of different
+ * sizes or wavelengths), as one graph launch (Sec. 5: simulating many
+ * complex scenes at once).  A plan lists work tiles over every (library,
+ * group of up to 8 of its scenes, row block, column chunk); a persistent
+ * kernel streams each library once from HBM and multiplies it with all the
+ * scenes assigned to it; a second kernel adds the chunk partials in a fixed
+ * order (bitwise reproducible).  Both launches are captured in a HIP graph.
+ *   h_libs          host array of nlibs built handles; all share one storage
+ *                   form and device, and must outlive the plan.
+ *   h_lib_of_scene  host int32 [B]: the library of each scene.
+ *   h_scenes        host array of B device pointers, scene b float32 [N_L^2]
+ *                   of its library L; h_images: B device pointers, image b
+ *                   float32 [n_L^2].  The pointers are fixed into the plan:
+ *                   refill the buffers and run again; do not free them first.
+ *   autotune        non-zero: time each candidate chunk length on this plan
+ *                   (running the graph, which writes the images) and keep the
+ *                   fastest; the choice is cached per plan shape for the
+ *                   process.  Zero: use the cached or default choice.
+ * Synchronises `stream` once (libraries built on it must be complete) and
+ * allocates the plan's device tables and partials (hipMalloc). */
+typedef struct psflib_grouped psflib_grouped;
+psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t nlibs,
+                                    const int32_t* h_lib_of_scene, const float* const* h_scenes,
+                                    float* const* h_images, int32_t B, int32_t autotune,
+                                    void* stream, psflib_grouped** out);
+
+/* Run the plan: one hipGraphLaunch on `stream`. */
+psflib_status psflib_grouped_run(const psflib_grouped* g, void* stream);
+
+/* The plan's chunk length (columns for FP32, 8-column groups for 16-bit) and,
+ * if it was autotuned, the measured time of one run in ms (else 0). */
+psflib_status psflib_grouped_chunk(const psflib_grouped* g, int64_t* chunk, float* tuned_ms);
+
+/* Free the plan (waits for the device).  NULL is ignored. */
+void psflib_grouped_destroy(psflib_grouped* g);
+
 /* ---- Fitting model -------------------------------------------------------
  * A smooth parametric exozodi disk on the scene grid of Eqs. (2)-(3), the
  * model that is fitted through the operator (Sec. 5 plans the retrieval of

@@ -72,6 +72,22 @@ psflib_status check_handle(const psflib_handle* h) {
 
 namespace psflib {
 
+psflib_status fail_status(psflib_status s, const char* msg) { return fail(s, msg); }
+psflib_status device_fail_status(hipError_t e, const char* what) { return device_fail(e, what); }
+
+void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
+                 int64_t* ncols, int64_t* ncols_pad, int* storage, int* device) {
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  *A = h->lib;
+  *exps = (h->desc.storage == PSFLIB_FP32) ? nullptr
+                                          : reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  *M = h->L.M;
+  *ncols = h->L.ncols;
+  *ncols_pad = h->L.ncols_pad;
+  *storage = h->desc.storage;
+  *device = h->device;
+}
+
 bool compute_layout(const psflib_desc& d, Layout* L) {
   const int64_t M = (int64_t)d.n * d.n;
   const int64_t ncols = (int64_t)d.N * d.N;

@@ -33,6 +33,8 @@ constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 floa
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
 constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
 constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
+constexpr int kGrpMaxChunkGroups = 128;  // grouped 16-bit apply: 8-column groups per chunk, at most
+constexpr int kGrpMaxChunkCols = 1024;   // grouped FP32 apply: columns per chunk, at most
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 
@@ -44,6 +46,13 @@ struct Layout {
 };
 
 bool compute_layout(const psflib_desc& d, Layout* L);
+
+// Error helpers of the ABI layer (record the message for psflib_last_error).
+psflib_status fail_status(psflib_status s, const char* msg);
+psflib_status device_fail_status(hipError_t e, const char* what);
+// Read-only view of a built library for the grouped apply.
+void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
+                 int64_t* ncols, int64_t* ncols_pad, int* storage, int* device);
 
 // ---- kernel launchers (each returns hipGetLastError() after its launch) ----
 hipError_t launch_cube_max(const float* cube, int K, int64_t M, float* pmax, hipStream_t s);

@@ -70,6 +70,10 @@ def _load():
         "psflib_get_exponents": (I32, [P, P, P]),
         "psflib_get_geometry": (I32, [P, P, P, P]),
         "psflib_render_disk": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P]),
+        "psflib_grouped_create": (I32, [P, I32, P, P, P, I32, I32, P, ctypes.POINTER(P)]),
+        "psflib_grouped_run": (I32, [P, P]),
+        "psflib_grouped_chunk": (I32, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_float)]),
+        "psflib_grouped_destroy": (None, [P]),
         "psflib_render_disk_grad": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P, P]),
         "psflib_destroy": (None, [P]),
     }
@@ -87,7 +91,8 @@ SYMBOLS = (
     "psflib_status_string", "psflib_last_error", "psflib_library_bytes", "psflib_build",
     "psflib_apply", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
-    "psflib_render_disk", "psflib_render_disk_grad",
+    "psflib_render_disk", "psflib_render_disk_grad", "psflib_grouped_create",
+    "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_destroy",
 )
 
 
@@ -181,6 +186,82 @@ def render_disk_grad(N: int, S: float, rmax: float, d_theta: int, d_dscene: int,
 
 def destroy(h: int):
     _lib.psflib_destroy(ctypes.c_void_p(h))
+
+
+def grouped_create(handles, lib_of_scene, scene_ptrs, image_ptrs, autotune: bool, stream: int) -> int:
+    nl = len(handles)
+    B = len(lib_of_scene)
+    H = (ctypes.c_void_p * nl)(*handles)
+    LS = (ctypes.c_int32 * max(B, 1))(*lib_of_scene)
+    SP = (ctypes.c_void_p * max(B, 1))(*scene_ptrs)
+    IP = (ctypes.c_void_p * max(B, 1))(*image_ptrs)
+    g = ctypes.c_void_p()
+    _check(_lib.psflib_grouped_create(H, nl, LS, SP, IP, B, 1 if autotune else 0,
+                                      ctypes.c_void_p(stream), ctypes.byref(g)),
+           "psflib_grouped_create")
+    return int(g.value)
+
+
+def grouped_run(g: int, stream: int):
+    _check(_lib.psflib_grouped_run(ctypes.c_void_p(g), ctypes.c_void_p(stream)), "psflib_grouped_run")
+
+
+def grouped_chunk(g: int):
+    c = ctypes.c_int64(0)
+    t = ctypes.c_float(0.0)
+    _check(_lib.psflib_grouped_chunk(ctypes.c_void_p(g), ctypes.byref(c), ctypes.byref(t)),
+           "psflib_grouped_chunk")
+    return int(c.value), float(t.value)
+
+
+def grouped_destroy(g: int):
+    _lib.psflib_grouped_destroy(ctypes.c_void_p(g))
+
+
+class Grouped:
+    """A grouped simulation plan over several :class:`Library` objects.
+
+    ``scenes[b]`` (float32 CUDA, N_L^2 elements) is simulated with
+    ``libs[lib_of_scene[b]]`` into ``images[b]`` (allocated here) by one graph
+    launch per :meth:`run`."""
+
+    def __init__(self, libs, lib_of_scene, scenes, autotune=True, stream=None):
+        import torch
+        self.torch = torch
+        self.libs = list(libs)  # keep the libraries alive
+        self.scenes = [s.contiguous() for s in scenes]
+        self.images = [torch.empty(self.libs[L].M, dtype=torch.float32, device=s.device)
+                       for L, s in zip(lib_of_scene, self.scenes)]
+        for L, s in zip(lib_of_scene, self.scenes):
+            if s.numel() != self.libs[L].ncols or s.dtype != torch.float32:
+                raise ValueError("scene size does not match its library")
+        st = self._stream(stream)
+        self.g = grouped_create([lib.h for lib in self.libs], list(lib_of_scene),
+                                [s.data_ptr() for s in self.scenes],
+                                [im.data_ptr() for im in self.images], autotune, st)
+
+    def _stream(self, stream):
+        if stream is None:
+            return self.torch.cuda.current_stream().cuda_stream
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+    def run(self, stream=None):
+        grouped_run(self.g, self._stream(stream))
+        return self.images
+
+    def chunk(self):
+        return grouped_chunk(self.g)
+
+    def close(self):
+        if getattr(self, "g", None):
+            grouped_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------- torch wrapper -----

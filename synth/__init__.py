@@ -11,4 +11,5 @@ from .inputs import (  # noqa: F401
     STREAM_SUBSAMPLE, STREAM_BATCH, CONFIGS, rng_for, radii_linspace,
     radii_nonuniform, throughput, psf_cube, ring_scene, planets, add_planets,
     random_ring_params, scene_batch, config_inputs, DISK_TRUE, DISK_START, noisy_counts,
+    MIXED_SIZES, MIXED_WAVELENGTHS, mixed_workload,
 )

@@ -239,3 +239,40 @@ def noisy_counts(image, peak_counts: float, rng: np.random.Generator, read_noise
     counts = rng.poisson(lam).astype(np.float64) + rng.normal(0.0, read_noise, size=lam.shape)
     var = np.maximum(counts, 1.0) + read_noise**2
     return counts, K, var
+
+
+# ------------------------------------------------ mixed-size workload ------
+MIXED_SIZES = (64, 96, 128)
+MIXED_WAVELENGTHS = tuple(0.95 + 0.01 * w for w in range(11))  # lambda/lambda0, 575 nm centre, 10% band
+
+
+def mixed_workload(B: int = 256, sizes=MIXED_SIZES, wavelengths=MIXED_WAVELENGTHS, config: int = 3):
+    """Scenes of mixed sizes and wavelengths, each simulated with the library of
+    its (size, wavelength).  Libraries: n = N, s = S = 16/n lambda0/D, K = n/2
+    offsets on [0, 8] lambda0/D, PSFs dilated by lambda/lambda0.  Scenes: seeded
+    ring disks masked beyond 8 lambda0/D.
+
+    Returns (libs, scene_lib, scenes): libs is a list of dict(n, N, S, radii,
+    cube, wavelength_ratio); scene_lib[b] indexes libs; scenes[b] is float32
+    [N*N] of that library's N."""
+    rng = rng_for(config, STREAM_BATCH)
+    libs, index = [], {}
+    aberr = rng_for(config, STREAM_ABERR)
+    seeds = aberr.integers(0, 2**31, size=len(sizes))
+    for si, n in enumerate(sizes):
+        for ell in wavelengths:
+            radii = radii_linspace(n // 2, 8.0)
+            s = 16.0 / n
+            cube = psf_cube(n, s, radii, rng=np.random.default_rng(int(seeds[si])),
+                            wavelength_ratio=ell)
+            index[(n, ell)] = len(libs)
+            libs.append(dict(n=n, N=n, S=s, radii=radii, cube=cube, wavelength_ratio=ell))
+    scene_lib, scenes = [], []
+    for _ in range(B):
+        n = sizes[int(rng.integers(0, len(sizes)))]
+        ell = wavelengths[int(rng.integers(0, len(wavelengths)))]
+        L = index[(n, ell)]
+        p = random_ring_params(rng)
+        scene_lib.append(L)
+        scenes.append(ring_scene(n, 16.0 / n, rmax_mask=8.0, **p).ravel())
+    return libs, scene_lib, scenes

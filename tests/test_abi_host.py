@@ -104,6 +104,18 @@ def test_calls_on_null_handle_rejected():
     psflib.destroy(0)  # NULL is ignored
 
 
+def test_grouped_and_model_validation_without_device():
+    with pytest.raises(psflib.PsflibError) as e:
+        psflib.grouped_create([], [], [], [], False, 0)
+    assert e.value.status == psflib.ERR_INVALID_ARG
+    assert _err(psflib.grouped_run, 0, 0) == psflib.ERR_INVALID_ARG
+    psflib.grouped_destroy(0)
+    assert _err(psflib.render_disk, 0, 0.5, 8.0, FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.render_disk, 8, -0.5, 8.0, FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.render_disk, 8, 0.5, float("nan"), FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.render_disk_grad, 8, 0.5, 8.0, FAKE, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+
+
 def test_largest_library_size_is_representable():
     d = psflib.make_desc(8192, 2, 46340, 1.0)
     b = psflib.library_bytes(d)
