@@ -22,11 +22,13 @@
 // stay short.
 //
 // 16-bit: a workgroup of 4 waves computes a 256 x 128 tile; each wave owns 64
-// image rows and all 128 scenes (2 x 4 accumulators of 32 x 32).  Library
-// fragments go straight from HBM into registers (each is used by one wave
-// only, for 4 MFMAs), one K stage ahead; scene fragments are shared by the 4
-// waves through a double-buffered LDS tile of 64 K.  The 16-bit rounding of
-// the inputs dominates the error, so accumulation is a single float32 level.
+// image rows and all 128 scenes (2 x 4 accumulators of 32 x 32).  K advances
+// in stages of 32 columns through a 4-slot ring, three stages ahead of use:
+// library fragments (each used by one wave only) go from HBM straight into
+// registers, and the scene tile (shared by the 4 waves) is copied from a
+// group-major packed copy of the scenes into LDS by the buffer unit, with no
+// register staging.  The 16-bit rounding of the inputs dominates the error,
+// so accumulation is a single float32 level.
 #include <math.h>
 #include <stdlib.h>
 
@@ -41,7 +43,7 @@ constexpr int kGK32 = 16; // FP32: K per tile
 constexpr int kMidTiles = 32;
 constexpr int kHM = 256;  // 16-bit: image rows per workgroup tile (64 per wave)
 constexpr int kHN = 128;  // 16-bit: scenes per workgroup tile
-constexpr int kHG = 8;    // 16-bit: 8-column groups per K stage (64 columns)
+constexpr int kHG = 4;    // 16-bit: 8-column groups per K stage (32 columns)
 constexpr int kMaxBatchChunk = 1024;  // scenes per internal pass (bounds the scratch)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -185,10 +187,13 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(const float* __r
 }
 
 // ------------------------------------------------------------- 16-bit -----
-// Scene preparation: Zp[b][j] = RN16(Z[b][j] * 2^(e_j + f_b)), with f_b
-// making max_j |Z[b][j]| 2^e_j land in [2^14, 2^15); padding columns are 0.
-// One workgroup per scene; each thread handles whole 8-column groups (two
-// 16-byte loads of Z and of the exponents, one 16-byte store).
+// Scene preparation, in two passes over the fp32 scenes:
+//   f_b:  max_j |Z[b][j]| 2^(e_j + f_b) lands in [2^14, 2^15)  (0 for an empty
+//         scene), so no scene underflows or overflows the 16-bit format
+//         whatever its units
+//   Zg[g][b] = RN16(Z[b][8g .. 8g+7] * 2^(e_j + f_b)), 16 bytes per (group, scene),
+// stored group-major with the batch padded to whole 128-scene tiles (zeros), so
+// one K stage of a scene tile is a contiguous run the GEMM copies straight to LDS.
 __device__ __forceinline__ uint32_t to16(float s, bool bf16) {
   if (bf16) {
     uint32_t u = __float_as_uint(s);
@@ -198,44 +203,47 @@ __device__ __forceinline__ uint32_t to16(float s, bool bf16) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)s);
 }
 
-template <bool BF16, bool VEC>
-__global__ __launch_bounds__(256) void prep_scenes_kernel(const float* __restrict__ Z,
-                                                          const int32_t* __restrict__ exps,
-                                                          int64_t ncols, int64_t ncols_pad,
-                                                          uint16_t* __restrict__ Zp,
-                                                          int32_t* __restrict__ fexp) {
+// 8 values and column exponents of group g of one scene (zeros past ncols)
+template <bool VEC>
+__device__ __forceinline__ void load_group(const float* __restrict__ z,
+                                           const int32_t* __restrict__ exps, int64_t ncols,
+                                           int64_t g, float* v, int32_t* e) {
+  const int64_t j0 = g * 8;
+  if (VEC && j0 + 8 <= ncols) {
+    const f32x4 v0 = *reinterpret_cast<const f32x4*>(z + j0);
+    const f32x4 v1 = *reinterpret_cast<const f32x4*>(z + j0 + 4);
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 e0 = *reinterpret_cast<const i32x4*>(exps + j0);
+    const i32x4 e1 = *reinterpret_cast<const i32x4*>(exps + j0 + 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = v0[q]; v[4 + q] = v1[q];
+      e[q] = e0[q]; e[4 + q] = e1[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool in = j0 + q < ncols;
+      v[q] = in ? z[j0 + q] : 0.0f;
+      e[q] = in ? exps[j0 + q] : 0;
+    }
+  }
+}
+
+// One workgroup per scene.
+template <bool VEC>
+__global__ __launch_bounds__(256) void scene_exponent_kernel(const float* __restrict__ Z,
+                                                             const int32_t* __restrict__ exps,
+                                                             int64_t ncols, int64_t ngroups,
+                                                             int32_t* __restrict__ fexp) {
   __shared__ double red[256];
   const int64_t b = blockIdx.x;
   const float* z = Z + b * ncols;
-  const int64_t ngroups = ncols_pad / 8;
-  // group g of this scene, values and exponents (zeros past ncols)
-  auto load8 = [&](int64_t g, float* v, int32_t* e) {
-    const int64_t j0 = g * 8;
-    if (VEC && j0 + 8 <= ncols) {
-      const f32x4 v0 = *reinterpret_cast<const f32x4*>(z + j0);
-      const f32x4 v1 = *reinterpret_cast<const f32x4*>(z + j0 + 4);
-      typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-      const i32x4 e0 = *reinterpret_cast<const i32x4*>(exps + j0);
-      const i32x4 e1 = *reinterpret_cast<const i32x4*>(exps + j0 + 4);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        v[q] = v0[q]; v[4 + q] = v1[q];
-        e[q] = e0[q]; e[4 + q] = e1[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const bool in = j0 + q < ncols;
-        v[q] = in ? z[j0 + q] : 0.0f;
-        e[q] = in ? exps[j0 + q] : 0;
-      }
-    }
-  };
   double m = 0.0;
   for (int64_t g = threadIdx.x; g < ngroups; g += 256) {
     float v[8];
     int32_t e[8];
-    load8(g, v, e);
+    load_group<VEC>(z, exps, ncols, g, v, e);
 #pragma unroll
     for (int q = 0; q < 8; ++q) m = fmax(m, ldexp((double)fabsf(v[q]), e[q]));
   }
@@ -245,28 +253,45 @@ __global__ __launch_bounds__(256) void prep_scenes_kernel(const float* __restric
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  int f = 0;
-  if (red[0] > 0.0) {
-    int E;
-    (void)frexp(red[0], &E);
-    f = 15 - E;
+  if (threadIdx.x == 0) {
+    int f = 0;
+    if (red[0] > 0.0) {
+      int E;
+      (void)frexp(red[0], &E);
+      f = 15 - E;
+    }
+    fexp[b] = f;
   }
-  if (threadIdx.x == 0) fexp[b] = f;
-  u32x4* zp = reinterpret_cast<u32x4*>(Zp + b * ncols_pad);
-  for (int64_t g = threadIdx.x; g < ngroups; g += 256) {
+}
+
+// Thread = (group g, scene n): 8 lanes cover one group of 8 consecutive
+// scenes, so each wave reads 8 runs of 256 contiguous bytes (8 groups of 8
+// scenes) and writes 8 whole 128-byte lines of Zg.
+template <bool BF16, bool VEC>
+__global__ __launch_bounds__(256) void pack_scenes_kernel(const float* __restrict__ Z,
+                                                          const int32_t* __restrict__ exps,
+                                                          const int32_t* __restrict__ fexp,
+                                                          int64_t ncols, int64_t ngroups,
+                                                          int64_t bc, int64_t Bp,
+                                                          u32x4* __restrict__ Zg) {
+  const int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (g >= ngroups) return;
+  const int64_t n = (int64_t)blockIdx.y * 8 + (threadIdx.x & 7);
+  u32x4 pk = {0u, 0u, 0u, 0u};
+  if (n < bc) {
     float v[8];
     int32_t e[8];
-    load8(g, v, e);
+    load_group<VEC>(Z + n * ncols, exps, ncols, g, v, e);
+    const int f = fexp[n];
     uint32_t h[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) h[q] = to16(ldexpf(v[q], e[q] + f), BF16);
-    u32x4 pk;
     pk.x = h[0] | (h[1] << 16);
     pk.y = h[2] | (h[3] << 16);
     pk.z = h[4] | (h[5] << 16);
     pk.w = h[6] | (h[7] << 16);
-    zp[g] = pk;
   }
+  Zg[g * Bp + n] = pk;
 }
 
 template <bool BF16>
@@ -279,51 +304,70 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 a, const u32x4 b, const f32
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+// The 16-bit GEMM.  Workgroup = 4 waves, tile 256 image rows x 128 scenes,
+// K stages of 32 columns (4 groups); each wave owns 64 rows and all 128 scenes
+// (2 x 4 accumulators of 32 x 32).  Operands of a stage travel on two paths
+// into a 4-slot ring, three stages ahead of use:
+//   library fragments (each used by one wave only) go from memory straight to
+//   registers, 4 x 16 bytes per lane per stage;
+//   the scene tile (shared by the 4 waves) is copied from memory into LDS by
+//   the buffer unit (buffer_load ... lds), 2 KiB per wave per stage, with no
+//   register staging.
+// Each lane issues exactly 6 vector-memory operations per stage, and those
+// complete in issue order, so "at most 12 outstanding" means this wave's
+// copies for the stage about to be used have landed; the barrier after that
+// wait makes every wave's copies visible and also ends all LDS reads of the
+// slot the next copy overwrites.  Scene fragments are read with ds_read_b128
+// in asm blocks that wait for their own results; the compiler tracks the
+// library-fragment registers itself.
+constexpr int kHRing = 4;    // ring slots
+constexpr int kHUnroll = 16; // stages per main-loop iteration (a multiple of kHRing)
+
 template <bool BF16>
 __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
-    const u32x4* __restrict__ Mp, const u32x4* __restrict__ Zp, const int32_t* __restrict__ fexp,
-    float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t mblocks,
+    const u32x4* Mp, const u32x4* Zg, const int32_t* __restrict__ fexp,
+    float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t Bp, int64_t mblocks,
     int64_t nblocks, int64_t splits, int64_t stages_per_split) {
-  __shared__ u32x4 Bs[2][kHG][kHN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ u32x4 Bs[kHRing][kHG][kHN];  // [slot][group][scene], 8 KiB per slot
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t tile = xcd_tile(blockIdx.x, mblocks * nblocks * splits);
   const int64_t nb = tile % nblocks, mb = (tile / nblocks) % mblocks, sp = tile / (nblocks * mblocks);
   const int64_t m0 = mb * kHM, n0 = nb * kHN;
   const int64_t nstages = ngroups / kHG;  // ngroups is a multiple of 8
   const int64_t st0 = sp * stages_per_split;
-  int64_t st1 = st0 + stages_per_split;
-  if (st1 > nstages) st1 = nstages;
+  const int64_t ns = (nstages - st0 < stages_per_split ? nstages - st0 : stages_per_split);
   float* dst = out + sp * B * M;
-  const u32x4 z4 = {0u, 0u, 0u, 0u};
 
-  // this lane's library rows (one per 32-row MFMA tile) and their validity
-  const int64_t row0 = m0 + 64 * wave + (lane & 31);
-  const bool ok0 = row0 < M, ok1 = row0 + 32 < M;
-  const int half = lane >> 5;  // which 8-group of a 16-wide K step this lane feeds
+  // library rows of this lane (one per 32-row MFMA tile); rows past M read
+  // row M-1 (valid addresses; those results are never stored)
+  int64_t row0 = m0 + 64 * wave + (lane & 31), row1 = row0 + 32;
+  if (row0 > M - 1) row0 = M - 1;
+  if (row1 > M - 1) row1 = M - 1;
+  const int half = lane >> 5;  // which group of a 16-wide K step this lane feeds
+  const uint32_t offa0 = (uint32_t)((half * M + row0) * 16);
+  const uint32_t offa1 = (uint32_t)((half * M + row1) * 16);
+  const char* Ab = reinterpret_cast<const char*>(Mp);
+  // this wave copies group `wave` of each stage: scenes n0 .. n0+127
+  const char* Zb = reinterpret_cast<const char*>(Zg + (int64_t)wave * Bp + n0);
+  const int offb = lane * 16;
 
-  // A fragments of one stage: [k16 step][m tile]
-  u32x4 a_cur[4][2], a_nxt[4][2];
-  auto load_a = [&](int64_t st, u32x4 (&a)[4][2]) {
+  u32x4 a[kHRing][2][2];  // [slot][k16 step][m tile]
+  auto issue = [&](int64_t ls, int slot) {  // local stage ls of this K slice
+    const int64_t st = st0 + ls;
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int64_t g = st * kHG + 2 * ks + half;
-      const u32x4* src = Mp + g * M + row0;
-      a[ks][0] = ok0 ? src[0] : z4;  // cached: the XCD's other scene blocks re-read it
-      a[ks][1] = ok1 ? src[32] : z4;
+    for (int ks = 0; ks < 2; ++ks) {
+      const char* base = Ab + (st * kHG + 2 * ks) * M * 16;
+      a[slot][ks][0] = *reinterpret_cast<const u32x4*>(base + offa0);
+      a[slot][ks][1] = *reinterpret_cast<const u32x4*>(base + offa1);
     }
-  };
-  // scene tile of one stage: thread -> scene n = tid / 2, groups 4*(tid%2) .. +3
-  u32x4 b_reg[4];
-  const int bn = tid >> 1, bg = (tid & 1) * 4;
-  const bool bok = n0 + bn < B;
-  auto load_b = [&](int64_t st) {
-    const u32x4* src = Zp + (n0 + bn) * ngroups + st * kHG + bg;
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Zb + st * kHG * Bp * 16), (short)0, 0x7FFFFFFF, 0x00020000);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) b_reg[q] = bok ? src[q] : z4;
-  };
-  auto store_b = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Bs[buf][bg + q][bn] = b_reg[q];
+    for (int h = 0; h < 2; ++h)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (void __attribute__((address_space(3)))*)(&Bs[slot][wave][64 * h]), 16,
+          offb + 1024 * h, 0, 0, 0);
   };
 
   const f32x16 zero16 = {};
@@ -333,39 +377,48 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[t][u] = zero16;
 
-  if (st0 < st1) {
-    load_a(st0, a_cur);
-    load_b(st0);
-    store_b(0);
-  }
-  __syncthreads();
-  for (int64_t st = st0; st < st1; ++st) {
-    const int cur = (int)((st - st0) & 1);
-    const bool more = st + 1 < st1;
-    if (more) {
-      load_a(st + 1, a_nxt);
-      load_b(st + 1);
-    }
+  const uint32_t lds_b = (uint32_t)(uintptr_t)(&Bs[0][half][lane & 31]);
+  auto compute = [&](int slot) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      u32x4 bf[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) bf[u] = Bs[cur][2 * ks + half][32 * u + (lane & 31)];
+    for (int ks = 0; ks < 2; ++ks) {
+      u32x4 bf[4];  // scenes 32u + lane%32 of group 2ks + half
+      asm volatile(
+          "ds_read_b128 %0, %4 offset:%5\n\t"
+          "ds_read_b128 %1, %4 offset:%6\n\t"
+          "ds_read_b128 %2, %4 offset:%7\n\t"
+          "ds_read_b128 %3, %4 offset:%8\n\t"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3])
+          : "v"(lds_b), "i"(slot * 8192 + ks * 4096), "i"(slot * 8192 + ks * 4096 + 512),
+            "i"(slot * 8192 + ks * 4096 + 1024), "i"(slot * 8192 + ks * 4096 + 1536));
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = mfma16<BF16>(a_cur[ks][t], bf[u], acc[t][u]);
+        for (int u = 0; u < 4; ++u) acc[t][u] = mfma16<BF16>(a[slot][ks][t], bf[u], acc[t][u]);
     }
-    if (more) {
-      store_b(cur ^ 1);
+  };
+  // stage ls: issue stage ls + 3 (clamped to the last one: the extra copies
+  // land in a slot nobody reads again) and multiply stage ls
+  auto step = [&](int64_t ls, int j) {
+    asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory");
+    const int64_t nx = ls + kHRing - 1;
+    issue(nx < ns ? nx : ns - 1, (j + kHRing - 1) % kHRing);
+    compute(j % kHRing);
+  };
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        a_cur[ks][0] = a_nxt[ks][0];
-        a_cur[ks][1] = a_nxt[ks][1];
-      }
-    }
-    __syncthreads();
+  for (int s = 0; s < kHRing - 1; ++s) issue(s < ns ? s : ns - 1, s);
+  int64_t l0 = 0;
+  for (; l0 + kHUnroll <= ns; l0 += kHUnroll) {
+#pragma unroll
+    for (int j = 0; j < kHUnroll; ++j) step(l0 + j, j);
   }
+  for (; l0 < ns; l0 += kHRing) {
+#pragma unroll
+    for (int j = 0; j < kHRing; ++j)
+      if (l0 + j < ns) step(l0 + j, j);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no copy into LDS outlives the workgroup
+
   // Without a K split the per-scene power of two is undone here; with one,
   // the slice-reduction kernel does it.
   const bool split = splits > 1;
@@ -373,118 +426,6 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      store_acc(acc[t][u], dst, M, B, m0 + 64 * wave + 32 * t, n0 + 32 * u, lane, fexp, !split);
-}
-
-// Large batches: a 256 x 256 tile per workgroup, one workgroup per CU.  Each
-// wave owns 64 image rows and all 256 scenes (2 x 8 accumulators of 32 x 32,
-// held in the accumulation registers); library fragments are prefetched one
-// K stage ahead into registers; the scene tile of the next stage is staged
-// through registers, half a stage at a time, into the other half of a
-// double-buffered LDS tile (2 x 32 KiB).  Scene fragments are double-buffered
-// across the four 16-wide K steps of a stage so LDS reads overlap the MFMAs.
-// Per flop it moves half the L2 traffic of the 256 x 128 tile.
-template <bool BF16>
-__global__ __launch_bounds__(kGemmThreads, 1) void gemm_h16_wide_kernel(
-    const u32x4* __restrict__ Mp, const u32x4* __restrict__ Zp, const int32_t* __restrict__ fexp,
-    float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t mblocks,
-    int64_t nblocks, int64_t splits, int64_t stages_per_split) {
-  constexpr int TN = 2 * kHN;  // 256 scenes
-  __shared__ u32x4 Bs[2][kHG][TN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t tile = xcd_tile(blockIdx.x, mblocks * nblocks * splits);
-  const int64_t nb = tile % nblocks, mb = (tile / nblocks) % mblocks, sp = tile / (nblocks * mblocks);
-  const int64_t m0 = mb * kHM, n0 = nb * TN;
-  const int64_t nstages = ngroups / kHG;
-  const int64_t st0 = sp * stages_per_split;
-  int64_t st1 = st0 + stages_per_split;
-  if (st1 > nstages) st1 = nstages;
-  float* dst = out + sp * B * M;
-  const u32x4 z4 = {0u, 0u, 0u, 0u};
-
-  const int64_t row0 = m0 + 64 * wave + (lane & 31);
-  const bool ok0 = row0 < M, ok1 = row0 + 32 < M;
-  const int half = lane >> 5;
-
-  u32x4 a_cur[4][2], a_nxt[4][2];
-  auto load_a = [&](int64_t st, u32x4 (&a)[4][2]) {
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int64_t g = st * kHG + 2 * ks + half;
-      const u32x4* src = Mp + g * M + row0;
-      a[ks][0] = ok0 ? src[0] : z4;
-      a[ks][1] = ok1 ? src[32] : z4;
-    }
-  };
-  u32x4 b_reg[kHG / 2];  // scene n = tid, 4 of the 8 groups of a stage
-  const bool bok = n0 + tid < B;
-  auto load_b = [&](int64_t st, int h) {
-    const u32x4* src = Zp + (n0 + tid) * ngroups + st * kHG + 4 * h;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b_reg[q] = bok ? src[q] : z4;
-  };
-  auto store_b = [&](int buf, int h) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Bs[buf][4 * h + q][tid] = b_reg[q];
-  };
-
-  const f32x16 zero16 = {};
-  f32x16 acc[2][8];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[t][u] = zero16;
-
-  if (st0 < st1) {
-    load_a(st0, a_cur);
-    load_b(st0, 0);
-    store_b(0, 0);
-    load_b(st0, 1);
-    store_b(0, 1);
-  }
-  __syncthreads();
-  for (int64_t st = st0; st < st1; ++st) {
-    const int cur = (int)((st - st0) & 1);
-    const bool more = st + 1 < st1;
-    if (more) {
-      load_a(st + 1, a_nxt);
-      load_b(st + 1, 0);
-    }
-    u32x4 bfr[2][8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) bfr[0][u] = Bs[cur][half][32 * u + (lane & 31)];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      if (ks < 3) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          bfr[(ks + 1) & 1][u] = Bs[cur][2 * (ks + 1) + half][32 * u + (lane & 31)];
-      }
-      if (ks == 1 && more) {
-        store_b(cur ^ 1, 0);
-        load_b(st + 1, 1);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        acc[0][u] = mfma16<BF16>(a_cur[ks][0], bfr[ks & 1][u], acc[0][u]);
-        acc[1][u] = mfma16<BF16>(a_cur[ks][1], bfr[ks & 1][u], acc[1][u]);
-      }
-    }
-    if (more) {
-      store_b(cur ^ 1, 1);
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        a_cur[ks][0] = a_nxt[ks][0];
-        a_cur[ks][1] = a_nxt[ks][1];
-      }
-    }
-    __syncthreads();
-  }
-  const bool split = splits > 1;
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
       store_acc(acc[t][u], dst, M, B, m0 + 64 * wave + 32 * t, n0 + 32 * u, lane, fexp, !split);
 }
 
@@ -503,23 +444,17 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float* __restr
 // ------------------------------------------------------------ launch ------
 struct GemmPlan {
   int64_t mblocks, nblocks, kunits, splits, per;  // kunits: K tiles (FP32) or K stages (16-bit)
-  bool wide;  // 16-bit: 256 x 256 tiles, one workgroup per CU
 };
 
 static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int64_t bc) {
   GemmPlan p;
   const bool f32 = storage == PSFLIB_FP32;
-  static const long wide_env = [] {
-    const char* e = getenv("PSFLIB_GEMM_WIDE");  // tuning override: 0 off, 1 on
-    return e ? strtol(e, nullptr, 10) : -1L;
-  }();
-  p.wide = !f32 && bc > kHN && wide_env == 1;
-  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? kGN : (p.wide ? 2 * kHN : kHN);
+  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? kGN : kHN;
   p.mblocks = (M + tm - 1) / tm;
   p.nblocks = (bc + tn - 1) / tn;
   p.kunits = f32 ? (ncols + kGK32 - 1) / kGK32 : (ncols_pad / 8) / kHG;
-  // about two workgroups per CU (512), split K if the tile grid is smaller
-  const int64_t want = f32 ? 1024 : (p.wide ? 256 : 512);
+  // about two workgroups per CU, split K if the tile grid is smaller
+  const int64_t want = f32 ? 1024 : 512;
   const int64_t tiles = p.mblocks * p.nblocks;
   int64_t s = (want + tiles - 1) / tiles;
   if (s > 16) s = 16;
@@ -533,6 +468,9 @@ static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_p
 
 static int64_t chunk_of(int B) { return B < kMaxBatchChunk ? B : kMaxBatchChunk; }
 
+// scenes per group row of the packed 16-bit scene copy (whole scene tiles)
+static int64_t padded_batch(int64_t bc) { return (bc + kHN - 1) / kHN * kHN; }
+
 static size_t split_partial_bytes(int storage, int64_t M, int64_t ncols, int64_t ncols_pad,
                                   int64_t bc) {
   const GemmPlan p = plan_gemm(storage, M, ncols, ncols_pad, bc);
@@ -541,14 +479,14 @@ static size_t split_partial_bytes(int storage, int64_t M, int64_t ncols, int64_t
 
 size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int B) {
   // Passes run over up to kMaxBatchChunk scenes each: for the 16-bit forms the
-  // prepared scenes and their exponents, then the K-split partial images of
+  // packed scenes and their exponents, then the K-split partial images of
   // the largest pass (a short final pass may split K more finely).
   if (B <= 0) return 0;
   const int64_t bc = chunk_of(B);
   size_t bytes = 0;
   if (storage != PSFLIB_FP32) {
-    bytes += ((size_t)bc * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;  // Zp
-    bytes += ((size_t)bc * 4 + 255) & ~(size_t)255;                      // fexp
+    bytes += ((size_t)padded_batch(bc) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;  // Zg
+    bytes += ((size_t)bc * 4 + 255) & ~(size_t)255;                                    // fexp
   }
   size_t part = split_partial_bytes(storage, M, ncols, ncols_pad, bc);
   const int64_t rem = B % bc;
@@ -564,13 +502,13 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
                           void* scratch, size_t scratch_bytes, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   char* sp = reinterpret_cast<char*>(scratch);
-  uint16_t* Zp = nullptr;
+  u32x4* Zg = nullptr;
   int32_t* fexp = nullptr;
   const int64_t bcmax = chunk_of(B);
   size_t off = 0;
   if (storage != PSFLIB_FP32) {
-    Zp = reinterpret_cast<uint16_t*>(sp);
-    off += ((size_t)bcmax * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
+    Zg = reinterpret_cast<u32x4*>(sp);
+    off += ((size_t)padded_batch(bcmax) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
     fexp = reinterpret_cast<int32_t*>(sp + off);
     off += ((size_t)bcmax * 4 + 255) & ~(size_t)255;
   }
@@ -594,30 +532,30 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
     } else {
       const bool bf = storage == PSFLIB_BF16_POW2;
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
-      if (bf && vec)
-        prep_scenes_kernel<true, true><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ncols_pad, Zp, fexp);
-      else if (bf)
-        prep_scenes_kernel<true, false><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ncols_pad, Zp, fexp);
-      else if (vec)
-        prep_scenes_kernel<false, true><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ncols_pad, Zp, fexp);
+      const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
+      if (vec)
+        scene_exponent_kernel<true><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
       else
-        prep_scenes_kernel<false, false><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ncols_pad, Zp, fexp);
+        scene_exponent_kernel<false><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      const int64_t ngroups = ncols_pad / 8;
-      const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
-      const u32x4* Zq = reinterpret_cast<const u32x4*>(Zp);
-      if (p.wide && bf)
-        gemm_h16_wide_kernel<true><<<grid, kGemmThreads, 0, s>>>(Mp, Zq, fexp, dst, M, ngroups, bc,
-                                                                 p.mblocks, p.nblocks, p.splits, p.per);
-      else if (p.wide)
-        gemm_h16_wide_kernel<false><<<grid, kGemmThreads, 0, s>>>(Mp, Zq, fexp, dst, M, ngroups, bc,
-                                                                  p.mblocks, p.nblocks, p.splits, p.per);
+      const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
+      if (bf && vec)
+        pack_scenes_kernel<true, true><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
       else if (bf)
-        gemm_h16_kernel<true><<<grid, kGemmThreads, 0, s>>>(Mp, Zq, fexp, dst, M, ngroups, bc,
+        pack_scenes_kernel<true, false><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
+      else if (vec)
+        pack_scenes_kernel<false, true><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
+      else
+        pack_scenes_kernel<false, false><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
+      if (bf)
+        gemm_h16_kernel<true><<<grid, kGemmThreads, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, bc, Bp,
                                                             p.mblocks, p.nblocks, p.splits, p.per);
       else
-        gemm_h16_kernel<false><<<grid, kGemmThreads, 0, s>>>(Mp, Zq, fexp, dst, M, ngroups, bc,
+        gemm_h16_kernel<false><<<grid, kGemmThreads, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, bc, Bp,
                                                              p.mblocks, p.nblocks, p.splits, p.per);
       e = hipGetLastError();
     }
