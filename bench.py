@@ -202,7 +202,7 @@ def main():
         for B in (64, 256):
             Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
             out = torch.empty((B, M), device=dev, dtype=torch.float32)
-            t_b = _timed(torch, lambda: lib.apply_batched(Zb, out=out), 5, 2)
+            t_b = _timed(torch, lambda: lib.apply_batched(Zb, out=out), 10, 3)
             fl = 2.0 * M * ncols * B
             rows[f"batched_fp32_B{B}"] = {
                 "ms": t_b, "scenes_per_s": B / (t_b * 1e-3), "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
@@ -253,10 +253,10 @@ def main():
                    "GB_per_s": (M * ((ncols + 63) // 64 * 64) * 2 + 4 * (M + 2 * ncols)) / (ms16 * 1e-3) / 1e9,
                    "speedup_vs_fp32": ms / ms16,
                    "peak_normalised_error_vs_fp32": err}
-            for B in (256, 1024):
+            for B in (256, 512, 1024):
                 Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
                 out = torch.empty((B, M), device=dev, dtype=torch.float32)
-                t_b = _timed(torch, lambda: lh.apply_batched(Zb, out=out), 5, 2)
+                t_b = _timed(torch, lambda: lh.apply_batched(Zb, out=out), 10, 3)
                 fl = 2.0 * M * ncols * B
                 ent[f"batched_B{B}"] = {"ms": t_b, "scenes_per_s": B / (t_b * 1e-3),
                                         "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,

@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,6 +40,40 @@ psflib_status device_fail(hipError_t e, const char* what) {
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Stream-ordered scratch (build temporaries, packed scenes, K-split partial
+// images) comes from a memory pool the library owns, one per device, which
+// keeps freed blocks for reuse: after the first call of a given size no call
+// pays for a fresh device allocation.  The pools live until the process ends.
+hipError_t scratch_alloc(void** p, size_t bytes, int dev, hipStream_t s) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  hipMemPool_t pool;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = pools.find(dev);
+    if (it == pools.end()) {
+      hipMemPoolProps props;
+      memset(&props, 0, sizeof(props));
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipError_t e = hipMemPoolCreate(&pool, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = ~(uint64_t)0;
+      e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return e;
+      }
+      pools[dev] = pool;
+    } else {
+      pool = it->second;
+    }
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
 
 constexpr int32_t kMaxN = 8192;   // image side: n^2 rows fit comfortably in 32-bit pixel indices
 constexpr int32_t kMaxScene = 46340;  // scene side: N^2 < 2^31 columns
@@ -203,16 +239,16 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   void* tmp = nullptr;
   auto bail = [&](hipError_t err, const char* what) {
     psflib_status r = device_fail(err, what);
+    if (tmp) (void)hipFreeAsync(tmp, s);
     (void)hipDeviceSynchronize();
-    if (tmp) (void)hipFree(tmp);
     (void)hipFree(h->ws);
     delete h;
     return r;
   };
   e = hipMemcpyAsync(h->radii_dev, h->radii.data(), (size_t)K * 8, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
-  e = hipMallocAsync(&tmp, tmp_bytes, s);
-  if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipMallocAsync(build scratch)"); }
+  e = scratch_alloc(&tmp, tmp_bytes, dev, s);
+  if (e != hipSuccess) { tmp = nullptr; return bail(e, "scratch allocation (build)"); }
   if (storage != PSFLIB_FP32) {
     e = psflib::launch_cube_max(d_cube, K, L.M, h->pmax, s);
     if (e != hipSuccess) return bail(e, "cube_max kernel");
@@ -277,8 +313,8 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
   void* scratch = nullptr;
   hipError_t e;
   if (bytes > 0) {
-    e = hipMallocAsync(&scratch, bytes, s);
-    if (e != hipSuccess) return device_fail(e, "hipMallocAsync(batched scratch)");
+    e = scratch_alloc(&scratch, bytes, h->device, s);
+    if (e != hipSuccess) return device_fail(e, "scratch allocation (batched)");
   }
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
