@@ -199,6 +199,16 @@ def main():
         t_adj = _timed(torch, lambda: lib.apply_adjoint(g, out=grad), args.steps // 2, 10)
         rows["adjoint_fp32"] = {"us": t_adj * 1e3, "GB_per_s": alg_bytes / (t_adj * 1e-3) / 1e9}
         ref_img = lib.apply(scene).double()
+        # the linear-vs-nearest comparison of the paper's Sec. 4.2, on this workload:
+        # |S_linear - S_nearest| in percent of the image peak
+        ln = psflib.Library(cube, d["radii"], N, S, interp="nearest", storage="fp32")
+        t_bn = _time_build(torch, psflib, ln.desc, cube, d["radii"], ln.buf, ln.nbytes)
+        pct = 100.0 * (ln.apply(scene).double() - ref_img).abs() / ref_img.abs().max()
+        rows["nearest_vs_linear_fp32"] = {"build_ms": t_bn, "build_ratio_vs_linear": t_bn / t_build,
+                                          "max_pct_of_peak": float(pct.max()),
+                                          "mean_pct_of_peak": float(pct.mean())}
+        ln.close()
+        del ln, pct
         for B in (64, 256):
             Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
             out = torch.empty((B, M), device=dev, dtype=torch.float32)

@@ -30,7 +30,8 @@ the repository's design notes):
 * rotation turns the +x-axis PSF so that its core lands on the field point
   (with y increasing with row index), about the array centre ((n-1)/2,
   (n-1)/2), keeping the n x n frame; the rotated image is sampled bilinearly
-  with zero padding outside the array;
+  with zero padding outside the array, or (the paper's rotate() default) by
+  the cubic B-spline that interpolates the PSF extended by zeros;
 * offsets beyond the last sample either hold the last PSF (``clamp``) or give
   an all-zero column (``zero``); offsets below the first sample hold the
   first PSF;
@@ -51,6 +52,7 @@ import numpy as np
 
 __all__ = [
     "scene_geometry", "radial_bracket", "interpolate_radial", "rotate_bilinear",
+    "spline_prefilter_1d", "spline_coefficients", "bspline3", "rotate_cubic",
     "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
     "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
     "quantize_library", "scale_exponent", "render_disk", "render_disk_grad",
@@ -162,7 +164,102 @@ def rotate_bilinear(Q: np.ndarray, ct: float, st: float) -> np.ndarray:
             + fy * fx * tap(r0 + 1, c0 + 1))
 
 
-def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp") -> np.ndarray:
+# ------------------------------------------ a3, cubic-spline rotation ----
+# The paper rotates with SciPy's rotate(), whose default interpolation is a
+# cubic spline.  The PSF is extended by zeros outside its frame; the spline
+# that interpolates the extended image is f(x) = sum_m c_m beta3(x - m) with
+# beta3 the cubic B-spline.  Its coefficients are computed on the frame
+# padded by SPLINE_PAD zero pixels per side with the exact recursive filter
+# for a mirror-symmetric extension of that padded array (the pole is
+# sqrt(3) - 2, so the padding leaves the frame's own coefficients within
+# (2 - sqrt(3))^12 ~ 1e-7 of the infinite-extension values), and taken as zero
+# beyond the padded array.
+SPLINE_PAD = 12
+_SPLINE_POLE = math.sqrt(3.0) - 2.0
+
+
+def spline_prefilter_1d(s) -> np.ndarray:
+    """Cubic B-spline interpolation coefficients of the 1-D samples s under a
+    mirror-symmetric extension: gain 6, then one causal and one anticausal
+    first-order recursion with pole z = sqrt(3) - 2 (the standard B-spline
+    interpolation filter).  The causal start value sums the mirrored signal
+    over one full period, so the result is exact for the periodic mirror
+    extension."""
+    z = _SPLINE_POLE
+    c = 6.0 * np.asarray(s, dtype=np.float64)
+    N = c.size
+    if N == 1:
+        return c / 6.0
+    k = np.arange(1, N - 1)
+    start = (c[0] + z ** (N - 1) * c[N - 1]
+             + np.sum((z ** k + z ** (2 * N - 2 - k)) * c[1:N - 1])) / (1.0 - z ** (2 * N - 2))
+    cp = np.empty(N)
+    cp[0] = start
+    for i in range(1, N):
+        cp[i] = c[i] + z * cp[i - 1]
+    cm = np.empty(N)
+    cm[N - 1] = (z / (z * z - 1.0)) * (cp[N - 1] + z * cp[N - 2])
+    for i in range(N - 2, -1, -1):
+        cm[i] = z * (cm[i + 1] - cp[i])
+    return cm
+
+
+def spline_coefficients(Q, pad: int = SPLINE_PAD) -> np.ndarray:
+    """Coefficients of the cubic spline interpolating Q extended by zeros:
+    Q padded with `pad` zero pixels per side, filtered along each column,
+    then along each row.  Returns float64 [(n + 2 pad)][(n + 2 pad)]."""
+    Q = np.asarray(Q, dtype=np.float64)
+    n = Q.shape[0]
+    P = np.zeros((n + 2 * pad, n + 2 * pad))
+    P[pad:pad + n, pad:pad + n] = Q
+    C = np.apply_along_axis(spline_prefilter_1d, 0, P)
+    return np.apply_along_axis(spline_prefilter_1d, 1, C)
+
+
+def bspline3(t) -> np.ndarray:
+    """The centred cubic B-spline: 2/3 - t^2 + |t|^3/2 on |t| < 1,
+    (2 - |t|)^3 / 6 on 1 <= |t| < 2, 0 beyond."""
+    t = np.abs(np.asarray(t, dtype=np.float64))
+    return np.where(t < 1.0, 2.0 / 3.0 - t * t + t * t * t / 2.0,
+                    np.where(t < 2.0, (2.0 - t) ** 3 / 6.0, 0.0))
+
+
+def rotate_cubic(Q: np.ndarray, ct: float, st: float, pad: int = SPLINE_PAD) -> np.ndarray:
+    """Rotate like rotate_bilinear (same source coordinates), sampling the
+    cubic spline of Q extended by zeros: the 4 x 4 coefficients around the
+    source point, weighted by beta3 of the distances along rows and columns;
+    coefficients outside the padded array count as zero."""
+    Q = np.asarray(Q, dtype=np.float64)
+    n = Q.shape[0]
+    c = (n - 1) / 2.0
+    C = spline_coefficients(Q, pad)
+    Mp = n + 2 * pad
+    a, b = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64),
+                       indexing="ij")
+    ux = b - c
+    uy = a - c
+    sx = ct * ux + st * uy
+    sy = (-st) * ux + ct * uy
+    col = c + sx + pad  # coordinates in the padded array
+    row = c + sy + pad
+    r0 = np.floor(row).astype(np.int64)
+    c0 = np.floor(col).astype(np.int64)
+    out = np.zeros_like(col)
+    for dr in (-1, 0, 1, 2):
+        rr = r0 + dr
+        wy = bspline3(row - rr)
+        for dc in (-1, 0, 1, 2):
+            cc = c0 + dc
+            wx = bspline3(col - cc)
+            ok = (rr >= 0) & (rr < Mp) & (cc >= 0) & (cc < Mp)
+            v = np.zeros_like(col)
+            v[ok] = C[rr[ok], cc[ok]]
+            out += wy * wx * v
+    return out
+
+
+def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp",
+                   rotate="bilinear") -> np.ndarray:
     """One library column I_j: radial interpolation, rotation, flattening
     (Sec. 2, one iteration of the field-point loop)."""
     cube = np.asarray(cube)
@@ -171,11 +268,15 @@ def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp") -> np.n
     if zero:
         return np.zeros(n * n, dtype=np.float64)
     Q = interpolate_radial(cube, k, w)
+    if rotate == "cubic":
+        return rotate_cubic(Q, ct, st).ravel()
+    if rotate != "bilinear":
+        raise ValueError("rotate must be 'bilinear' or 'cubic'")
     return rotate_bilinear(Q, ct, st).ravel()
 
 
 def build_library(cube, radii, N: int, S: float, interp: str = "linear", oob: str = "clamp",
-                  columns=None) -> np.ndarray:
+                  columns=None, rotate: str = "bilinear") -> np.ndarray:
     """The library matrix A (Sec. 3, Eqs. (4)-(5)): n^2 rows, one column per
     scene pixel, column j the flattened interpolated-and-rotated PSF of field
     point j.  ``columns`` selects a subset of j (returned in that order).
@@ -191,7 +292,7 @@ def build_library(cube, radii, N: int, S: float, interp: str = "linear", oob: st
     cols = np.arange(N * N) if columns is None else np.asarray(columns, dtype=np.int64)
     A = np.empty((n * n, cols.size), dtype=np.float64)
     for t, j in enumerate(cols):
-        A[:, t] = library_column(cube, radii, r[j], ct[j], st[j], interp, oob)
+        A[:, t] = library_column(cube, radii, r[j], ct[j], st[j], interp, oob, rotate)
     return A
 
 
@@ -227,12 +328,19 @@ def scale_exponent(m: float) -> int:
     return E - 15
 
 
-def column_max_bound(cube, radii, N: int, S: float, interp="linear", oob="clamp") -> np.ndarray:
-    """Per-column upper bound on max_i A_ij that needs no column values:
-    (1-w) max(P_k) + w max(P_{k+1}).  Bilinear rotation is a convex
-    combination of Q's pixels (or zero), so the column never exceeds it."""
+def column_max_bound(cube, radii, N: int, S: float, interp="linear", oob="clamp",
+                     rotate="bilinear") -> np.ndarray:
+    """Per-column upper bound on max_i |A_ij| that needs no column values:
+    (1-w) m_k + w m_{k+1}.  Bilinear rotation is a convex combination of Q's
+    pixels (or zero), so with m_k = max(P_k) (the cube is non-negative) the
+    column never exceeds it.  The cubic spline is a convex combination of
+    coefficients, and Q's coefficients are (1-w) C_k + w C_{k+1} (the
+    prefilter is linear), so m_k = max |C_k| bounds it."""
     cube = np.asarray(cube, dtype=np.float64)
-    pmax = cube.reshape(cube.shape[0], -1).max(axis=1)
+    if rotate == "cubic":
+        pmax = np.array([np.abs(spline_coefficients(P)).max() for P in cube])
+    else:
+        pmax = cube.reshape(cube.shape[0], -1).max(axis=1)
     _, _, r, _, _ = scene_geometry(N, S)
     out = np.empty(r.size, dtype=np.float64)
     for j in range(r.size):
