@@ -209,6 +209,15 @@ def main():
                                           "mean_pct_of_peak": float(pct.mean())}
         ln.close()
         del ln, pct
+        # cubic-spline rotation (the interpolation of the paper's rotate() calls)
+        lc = psflib.Library(cube, d["radii"], N, S, rotate="cubic", storage="fp32")
+        t_bc = _time_build(torch, psflib, lc.desc, cube, d["radii"], lc.buf, lc.nbytes)
+        pct = 100.0 * (lc.apply(scene).double() - ref_img).abs() / ref_img.abs().max()
+        rows["cubic_rotation_fp32"] = {"build_ms": t_bc, "build_ratio_vs_bilinear": t_bc / t_build,
+                                       "max_pct_of_peak_vs_bilinear": float(pct.max()),
+                                       "mean_pct_of_peak_vs_bilinear": float(pct.mean())}
+        lc.close()
+        del lc, pct
         for B in (64, 256):
             Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
             out = torch.empty((B, M), device=dev, dtype=torch.float32)

@@ -75,6 +75,20 @@ typedef enum { PSFLIB_OOB_CLAMP = 0, PSFLIB_OOB_ZERO = 1 } psflib_oob;
  *             Products accumulate in float32. */
 typedef enum { PSFLIB_FP32 = 0, PSFLIB_BF16_POW2 = 1, PSFLIB_FP16_POW2 = 2 } psflib_storage;
 
+/* Interpolation of the rotation step (Sec. 2, the rotate() call).
+ *  BILINEAR  four-neighbour bilinear sampling of the radially interpolated
+ *            PSF Q, neighbours outside the n x n frame counting as zero.
+ *  CUBIC     the cubic B-spline interpolating Q extended by zeros (the
+ *            interpolation order the paper's rotate() uses by default): the
+ *            spline coefficients of Q padded by 12 zero pixels per side (exact
+ *            recursive filter, mirror boundary at the padded edge), sampled
+ *            with the 4 x 4 cubic B-spline weights; coefficients beyond the
+ *            padded array count as zero.  Entries can be slightly negative
+ *            (spline overshoot); the 16-bit exponent bound then uses the
+ *            largest |coefficient| of each sampled PSF in place of its largest
+ *            value. */
+typedef enum { PSFLIB_ROTATE_BILINEAR = 0, PSFLIB_ROTATE_CUBIC = 1 } psflib_rotate;
+
 typedef struct {
   int32_t n;             /* PSF side = image side (pixels); the image has n*n pixels */
   int32_t n_psf;         /* K >= 1 sampled off-axis PSFs, sources on +x */
@@ -83,6 +97,8 @@ typedef struct {
   double scene_pixscale; /* S > 0, in the unit of the radii (Eqs. (2)-(3)) */
   int32_t oob;           /* psflib_oob */
   int32_t storage;       /* psflib_storage */
+  int32_t rotate;        /* psflib_rotate */
+  int32_t reserved;      /* must be 0 */
 } psflib_desc;
 
 typedef struct psflib_handle psflib_handle;

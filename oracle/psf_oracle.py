@@ -52,7 +52,7 @@ import numpy as np
 
 __all__ = [
     "scene_geometry", "radial_bracket", "interpolate_radial", "rotate_bilinear",
-    "spline_prefilter_1d", "spline_coefficients", "bspline3", "rotate_cubic",
+    "spline_prefilter", "spline_prefilter_1d", "spline_coefficients", "bspline3", "rotate_cubic",
     "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
     "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
     "quantize_library", "scale_exponent", "render_disk", "render_disk_grad",
@@ -178,30 +178,37 @@ SPLINE_PAD = 12
 _SPLINE_POLE = math.sqrt(3.0) - 2.0
 
 
-def spline_prefilter_1d(s) -> np.ndarray:
-    """Cubic B-spline interpolation coefficients of the 1-D samples s under a
-    mirror-symmetric extension: gain 6, then one causal and one anticausal
-    first-order recursion with pole z = sqrt(3) - 2 (the standard B-spline
-    interpolation filter).  The causal start value sums the mirrored signal
-    over one full period, so the result is exact for the periodic mirror
-    extension."""
+def spline_prefilter(a, axis: int = 0) -> np.ndarray:
+    """Cubic B-spline interpolation coefficients of the samples in `a` along
+    `axis`, under a mirror-symmetric extension: gain 6, then one causal and
+    one anticausal first-order recursion with pole z = sqrt(3) - 2 (the
+    standard B-spline interpolation filter).  The causal start value sums
+    the mirrored signal over one full period, so the result is exact for
+    the periodic mirror extension.  Every line along `axis` is filtered
+    independently (the recursion runs over `axis`, vectorised across the
+    other axes)."""
     z = _SPLINE_POLE
-    c = 6.0 * np.asarray(s, dtype=np.float64)
-    N = c.size
+    c = 6.0 * np.moveaxis(np.asarray(a, dtype=np.float64), axis, 0)
+    N = c.shape[0]
     if N == 1:
-        return c / 6.0
-    k = np.arange(1, N - 1)
+        return np.moveaxis(c / 6.0, 0, axis)
+    k = np.arange(1, N - 1).reshape((-1,) + (1,) * (c.ndim - 1))
     start = (c[0] + z ** (N - 1) * c[N - 1]
-             + np.sum((z ** k + z ** (2 * N - 2 - k)) * c[1:N - 1])) / (1.0 - z ** (2 * N - 2))
-    cp = np.empty(N)
+             + np.sum((z ** k + z ** (2 * N - 2 - k)) * c[1:N - 1], axis=0)) / (1.0 - z ** (2 * N - 2))
+    cp = np.empty_like(c)
     cp[0] = start
     for i in range(1, N):
         cp[i] = c[i] + z * cp[i - 1]
-    cm = np.empty(N)
+    cm = np.empty_like(c)
     cm[N - 1] = (z / (z * z - 1.0)) * (cp[N - 1] + z * cp[N - 2])
     for i in range(N - 2, -1, -1):
         cm[i] = z * (cm[i + 1] - cp[i])
-    return cm
+    return np.moveaxis(cm, 0, axis)
+
+
+def spline_prefilter_1d(s) -> np.ndarray:
+    """spline_prefilter of a single line."""
+    return spline_prefilter(np.asarray(s, dtype=np.float64), 0)
 
 
 def spline_coefficients(Q, pad: int = SPLINE_PAD) -> np.ndarray:
@@ -212,8 +219,7 @@ def spline_coefficients(Q, pad: int = SPLINE_PAD) -> np.ndarray:
     n = Q.shape[0]
     P = np.zeros((n + 2 * pad, n + 2 * pad))
     P[pad:pad + n, pad:pad + n] = Q
-    C = np.apply_along_axis(spline_prefilter_1d, 0, P)
-    return np.apply_along_axis(spline_prefilter_1d, 1, C)
+    return spline_prefilter(spline_prefilter(P, 0), 1)
 
 
 def bspline3(t) -> np.ndarray:

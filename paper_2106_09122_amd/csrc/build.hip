@@ -1,4 +1,6 @@
 // Library build: gather, interpolate and rotate (Sec. 2; Eqs. (4)-(5)).
+// This file holds the gather form (PSFs too large to stage in LDS) and the
+// cubic-spline rotation (any size), which gathers 4 x 4 coefficient pairs.
 //
 // Column j of A is the datacube interpolated to the field point's offset,
 // Q = (1-w) P_k + w P_{k+1}, rotated about the array centre to the field
@@ -87,7 +89,47 @@ __device__ __forceinline__ uint32_t f32_to_f16_rne(float f) {
   return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-template <int STORE>
+// Cubic B-spline weight (float64, the oracle's expressions).
+__device__ __forceinline__ double bspline3(double t) {
+#pragma clang fp contract(off)
+  t = fabs(t);
+  if (t < 1.0) return 2.0 / 3.0 - t * t + t * t * t / 2.0;
+  if (t < 2.0) {
+    const double u = 2.0 - t;
+    return u * u * u / 6.0;
+  }
+  return 0.0;
+}
+
+// Cubic-spline rotation: the same source point as the bilinear form, in the
+// coordinates of the spline coefficients (padded by kSplinePad), sampled with
+// the 4 x 4 B-spline weights; each tap blends the coefficient pair of the
+// column's bracket, and taps outside the padded array are zero.
+__device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int Np, double c,
+                                                    double ux, double uy) {
+#pragma clang fp contract(off)
+  const double sx = cp.ct * ux + cp.st * uy;
+  const double sy = (-cp.st) * ux + cp.ct * uy;
+  const double colf = c + sx + (double)kSplinePad;
+  const double rowf = c + sy + (double)kSplinePad;
+  const int c0 = (int)floor(colf);
+  const int r0 = (int)floor(rowf);
+  double wy[4], wx[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    wy[d] = bspline3(rowf - (double)(r0 + d - 1));
+    wx[d] = bspline3(colf - (double)(c0 + d - 1));
+  }
+  float v = 0.0f;
+#pragma unroll
+  for (int dr = 0; dr < 4; ++dr)
+#pragma unroll
+    for (int dc = 0; dc < 4; ++dc)
+      v = fmaf((float)(wy[dr] * wx[dc]), tap(cp.src, Np, r0 + dr - 1, c0 + dc - 1, cp.wk0, cp.wk1), v);
+  return v;
+}
+
+template <int STORE, bool CUBIC>
 __global__ __launch_bounds__(kBuildThreads) void build_kernel(const float2* __restrict__ pairs,
                                                               const ColGeom* __restrict__ geo,
                                                               int n, int64_t M, int64_t ncols,
@@ -110,7 +152,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(const float2* __re
       const ColGeom g = geo[j];
       if (g.k >= 0 && j < ncols) {
         cp[u].live = true;
-        cp[u].src = pairs + (int64_t)g.k * M;
+        cp[u].src = pairs + (int64_t)g.k * (CUBIC ? (int64_t)(n + 2 * kSplinePad) * (n + 2 * kSplinePad) : M);
         cp[u].ct = g.ct;
         cp[u].st = g.st;
         cp[u].wk0 = (float)(1.0 - g.w);
@@ -133,7 +175,10 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(const float2* __re
     float v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      v[u] = cp[u].live ? column_value(cp[u], n, c, ux, uy) : 0.0f;
+      if constexpr (CUBIC)
+        v[u] = cp[u].live ? column_value_cubic(cp[u], n + 2 * kSplinePad, c, ux, uy) : 0.0f;
+      else
+        v[u] = cp[u].live ? column_value(cp[u], n, c, ux, uy) : 0.0f;
       tacc[u] += (double)v[u];
     }
     if constexpr (STORE == PSFLIB_FP32) {
@@ -178,24 +223,37 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(const float2* __re
   if (tid < 8 && j0 + tid < ncols) tau[j0 + tid] = red[tid][0];
 }
 
-hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
-                        int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s) {
+template <bool CUBIC>
+static hipError_t launch_build_t(int storage, const float* pairs, const ColGeom* geo, int n,
+                                 int64_t M, int64_t ncols, int64_t ncols_pad, void* lib,
+                                 double* tau, hipStream_t s) {
   const int64_t groups = (ncols_pad + 7) / 8;
   const float2* P = reinterpret_cast<const float2*>(pairs);
   // gridDim.x is limited to 2^31-1 groups: far above any library that fits in memory.
   const dim3 grid((unsigned)groups);
   switch (storage) {
     case PSFLIB_FP32:
-      build_kernel<PSFLIB_FP32><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
+      build_kernel<PSFLIB_FP32, CUBIC><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
       break;
     case PSFLIB_BF16_POW2:
-      build_kernel<PSFLIB_BF16_POW2><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
+      build_kernel<PSFLIB_BF16_POW2, CUBIC><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
       break;
     default:
-      build_kernel<PSFLIB_FP16_POW2><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
+      build_kernel<PSFLIB_FP16_POW2, CUBIC><<<grid, kBuildThreads, 0, s>>>(P, geo, n, M, ncols, ncols_pad, lib, tau);
       break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
+                        int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s) {
+  return launch_build_t<false>(storage, pairs, geo, n, M, ncols, ncols_pad, lib, tau, s);
+}
+
+hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
+                              int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
+                              hipStream_t s) {
+  return launch_build_t<true>(storage, pairs, geo, n, M, ncols, ncols_pad, lib, tau, s);
 }
 
 }  // namespace psflib

@@ -91,6 +91,9 @@ psflib_status check_desc(const psflib_desc* d) {
     return fail(PSFLIB_ERR_INVALID_ARG, "unknown oob mode");
   if (d->storage != PSFLIB_FP32 && d->storage != PSFLIB_BF16_POW2 && d->storage != PSFLIB_FP16_POW2)
     return fail(PSFLIB_ERR_INVALID_ARG, "unknown storage");
+  if (d->rotate != PSFLIB_ROTATE_BILINEAR && d->rotate != PSFLIB_ROTATE_CUBIC)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unknown rotate mode");
+  if (d->reserved != 0) return fail(PSFLIB_ERR_INVALID_ARG, "reserved must be 0");
   return PSFLIB_OK;
 }
 
@@ -231,11 +234,15 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   char* lib = reinterpret_cast<char*>(d_lib);
   double* tau = reinterpret_cast<double*>(lib + L.off_tau);
   int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
-  // Small PSFs (the bordered pair fits the LDS): bucketed LDS build; larger
-  // ones gather from a pair-interleaved copy of the cube.
-  const bool lds = psflib::build_lds_supported(desc->n, K);
-  const size_t tmp_bytes = lds ? psflib::build_lds_scratch_bytes(storage, K, L.M, L.ncols)
-                               : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
+  // Cubic-spline rotation: spline coefficients of the cube, then a gather
+  // build over coefficient pairs.  Bilinear: small PSFs (the bordered pair
+  // fits the LDS) take the bucketed LDS build; larger ones gather from a
+  // pair-interleaved copy of the cube.
+  const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
+  const bool lds = !cubic && psflib::build_lds_supported(desc->n, K);
+  const size_t tmp_bytes = cubic ? psflib::spline_scratch_bytes(K, desc->n)
+                           : lds ? psflib::build_lds_scratch_bytes(storage, K, L.M, L.ncols)
+                                 : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
   void* tmp = nullptr;
   auto bail = [&](hipError_t err, const char* what) {
     psflib_status r = device_fail(err, what);
@@ -249,7 +256,12 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
   e = scratch_alloc(&tmp, tmp_bytes, dev, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "scratch allocation (build)"); }
-  if (storage != PSFLIB_FP32) {
+  if (cubic) {
+    // the 16-bit exponent bound takes the largest |coefficient| per PSF
+    e = psflib::launch_spline_pairs(d_cube, K, desc->n, tmp,
+                                    storage != PSFLIB_FP32 ? h->pmax : nullptr, s);
+    if (e != hipSuccess) return bail(e, "spline coefficient kernels");
+  } else if (storage != PSFLIB_FP32) {
     e = psflib::launch_cube_max(d_cube, K, L.M, h->pmax, s);
     if (e != hipSuccess) return bail(e, "cube_max kernel");
   }
@@ -257,7 +269,11 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
-  if (lds) {
+  if (cubic) {
+    e = psflib::launch_build_cubic(storage, psflib::spline_pairs_of(tmp, K, desc->n), h->geo,
+                                   desc->n, L.M, L.ncols, L.ncols_pad, d_lib, tau, s);
+    if (e != hipSuccess) return bail(e, "cubic build kernel");
+  } else if (lds) {
     e = psflib::launch_build_lds(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
                                  d_lib, tau, tmp, s);
     if (e != hipSuccess) return bail(e, "LDS build kernels");

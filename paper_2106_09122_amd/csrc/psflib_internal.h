@@ -37,6 +37,7 @@ constexpr int kGrpMaxChunkGroups = 128;  // grouped 16-bit apply: 8-column group
 constexpr int kGrpMaxChunkCols = 1024;   // grouped FP32 apply: columns per chunk, at most
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
+constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter
 
 struct Layout {
   int64_t M;          // n*n image pixels (rows of A)
@@ -60,6 +61,17 @@ hipError_t launch_pair_cube(const float* cube, int K, int64_t M, float* pairs, h
 hipError_t launch_geometry(int N, double S, const double* radii, int K, int interp, int oob,
                            const float* pmax, bool want_exp, ColGeom* geo, int64_t ncols_pad,
                            int32_t* exps, hipStream_t s);
+// Cubic-spline rotation: coefficients of every sampled PSF padded by
+// kSplinePad zeros per side ([K][Np][Np], Np = n + 2 kSplinePad) as
+// radial pairs (float2 [max(K-1,1)][Np*Np]) and their largest magnitude per
+// PSF; scratch must hold spline_scratch_bytes(K, n) bytes.
+size_t spline_scratch_bytes(int K, int n);
+hipError_t launch_spline_pairs(const float* cube, int K, int n, void* scratch, float* cmax,
+                               hipStream_t s);
+const float* spline_pairs_of(const void* scratch, int K, int n);
+hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
+                              int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
+                              hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K);

@@ -23,6 +23,7 @@ OK, ERR_INVALID_ARG, ERR_RADII, ERR_SIZE, ERR_UNSUPPORTED, ERR_DEVICE = range(6)
 INTERP = {"linear": 0, "nearest": 1}
 OOB = {"clamp": 0, "zero": 1}
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+ROTATE = {"bilinear": 0, "cubic": 1}
 
 
 class PsflibError(RuntimeError):
@@ -41,6 +42,8 @@ class Desc(ctypes.Structure):
         ("scene_pixscale", ctypes.c_double),
         ("oob", ctypes.c_int32),
         ("storage", ctypes.c_int32),
+        ("rotate", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -106,13 +109,15 @@ def _check(status: int, where: str):
 
 
 def make_desc(n: int, n_psf: int, N: int, scene_pixscale: float, interp="linear", oob="clamp",
-              storage="fp32") -> Desc:
+              storage="fp32", rotate="bilinear") -> Desc:
     d = Desc()
     d.n, d.n_psf, d.N = int(n), int(n_psf), int(N)
     d.scene_pixscale = float(scene_pixscale)
     d.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
     d.oob = OOB[oob] if isinstance(oob, str) else int(oob)
     d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    d.rotate = ROTATE[rotate] if isinstance(rotate, str) else int(rotate)
+    d.reserved = 0
     return d
 
 
@@ -275,7 +280,7 @@ class Library:
     """
 
     def __init__(self, cube, radii, N: int, S: float, interp="linear", oob="clamp",
-                 storage="fp32", stream=None):
+                 storage="fp32", stream=None, rotate="bilinear"):
         import torch
         if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32):
             raise TypeError("cube must be a float32 CUDA tensor [K][n][n]")
@@ -287,7 +292,7 @@ class Library:
         self.N, self.S = int(N), float(S)
         self.storage = storage
         self.radii = np.asarray(radii, dtype=np.float64)
-        self.desc = make_desc(self.n, self.K, self.N, self.S, interp, oob, storage)
+        self.desc = make_desc(self.n, self.K, self.N, self.S, interp, oob, storage, rotate)
         self.nbytes = library_bytes(self.desc)
         self.device = cube.device
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)

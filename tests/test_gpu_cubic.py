@@ -1,0 +1,147 @@
+"""Cubic-spline rotation (GPU, through the C ABI) against the FP64 oracle.
+
+The cubic library mixes signs (the spline overshoots next to sharp PSF
+features), so errors are bounded against magnitudes rather than values:
+  * entries: |dA_ij| <= 1e-6 * b_j, with b_j = (1-w) max|C_k| + w max|C_{k+1}|
+    the oracle's bound on the column (float32 coefficients, float32 blend of
+    the pair and a 16-tap float32 sum, each weight and term bounded by b_j);
+  * column sums: |dtau_j| <= 1e-6 * b_j * n^2;
+  * images and batched images: |dS_i| <= 1e-5 (|A| |Z|)_i + 1e-6 (B |Z|)_i
+    (B the matrix of column bounds), the adjoint likewise with |A|^T |g|;
+  * 16-bit: entries within u |A| + 1e-6 b_j + half the FP16 subnormal
+    spacing, exponents obey the rule for the oracle's bound to 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U16 = {"bf16": 2.0**-8, "fp16": 2.0**-11}
+ENTRY = 1e-6
+IMG = 1e-5
+
+CASES = [
+    # n, N, S, K, radii kind, interp, oob
+    (32, 32, 0.5, 16, "c1", "linear", "clamp"),
+    (33, 7, 0.37, 5, "nonuniform", "linear", "clamp"),
+    (20, 45, 0.21, 9, "linear", "nearest", "zero"),
+    (16, 13, 0.6, 1, "linear", "linear", "zero"),
+    (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _inputs(n, N, S, K, kind, seed):
+    if kind == "c1":
+        d = synth.config_inputs(1)
+        return d["cube"], d["radii"], np.random.default_rng(seed)
+    rng = np.random.default_rng(seed)
+    if kind == "nonuniform":
+        radii = np.concatenate([[0.0], np.cumsum(rng.uniform(0.05, 0.9, K - 1))])
+    else:
+        radii = np.linspace(0.0, N * S * 0.6, K)
+    cube = (rng.random((K, n, n)) ** 3).astype(np.float32)
+    return cube, radii, rng
+
+
+_cache = {}
+
+
+def _oracle(case):
+    if case not in _cache:
+        n, N, S, K, kind, interp, oob = case
+        cube, radii, _ = _inputs(n, N, S, K, kind, n * 1000 + N + 11)
+        A = O.build_library(cube, radii, N, S, interp, oob, rotate="cubic")
+        b = O.column_max_bound(cube, radii, N, S, interp, oob, rotate="cubic")
+        _cache[case] = (cube, radii, A, b)
+    return _cache[case]
+
+
+def _lib(torch, cube, radii, N, S, **kw):
+    from paper_2106_09122_amd import psflib
+    return psflib.Library(torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float32)).cuda(),
+                          radii, N, S, rotate="cubic", **kw)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_cubic_fp32(torch, case):
+    n, N, S, K, kind, interp, oob = case
+    cube, radii, A, b = _oracle(case)
+    rng = np.random.default_rng(n + N)
+    lib = _lib(torch, cube, radii, N, S, interp=interp, oob=oob)
+    got = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
+    assert np.all(np.abs(got - A) <= ENTRY * b[None, :] + 1e-300)
+    assert np.all(got[:, b == 0] == 0)
+    tau = lib.column_sums().cpu().numpy()
+    assert np.all(np.abs(tau - A.sum(axis=0)) <= ENTRY * b * n * n + 1e-300)
+    Z = rng.random(N * N).astype(np.float32)
+    img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    den = np.abs(A) @ Z.astype(np.float64) + ENTRY * (b @ Z.astype(np.float64))
+    assert np.all(np.abs(img - O.apply(A, Z)) <= IMG * den + 1e-300)
+    g = rng.standard_normal(n * n).astype(np.float32)
+    G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
+    gd = np.abs(g.astype(np.float64))
+    den = np.abs(A).T @ gd + ENTRY * b * gd.sum()
+    assert np.all(np.abs(G - O.apply_adjoint(A, g)) <= IMG * den + 1e-300)
+    Zb = rng.random((6, N * N)).astype(np.float32)
+    out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    den = (np.abs(A) @ Zb.T.astype(np.float64)).T + ENTRY * (Zb.astype(np.float64) @ b)[:, None]
+    assert np.all(np.abs(out - O.apply_batched(A, Zb)) <= IMG * den + 1e-300)
+    lib.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("case", CASES[:3])
+def test_cubic_16bit(torch, fmt, case):
+    n, N, S, K, kind, interp, oob = case
+    cube, radii, A, b = _oracle(case)
+    lib = _lib(torch, cube, radii, N, S, interp=interp, oob=oob, storage=fmt)
+    e = lib.exponents().cpu().numpy().astype(np.int64)
+    live = b > 0
+    scaled = b[live] * np.ldexp(1.0, -e[live])
+    assert np.all((scaled >= 2.0**14 * (1 - 1e-6)) & (scaled < 2.0**15 * (1 + 1e-6)))
+    assert np.all(e[~live] == 0)
+    u = U16[fmt]
+    deq = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
+    tol = u * (1 + 1e-5) * np.abs(A) + ENTRY * b[None, :] + (2.0**-25) * np.ldexp(1.0, e)[None, :]
+    assert np.all(np.abs(deq - A) <= tol)
+    rng = np.random.default_rng(n * 3 + N)
+    Zb = rng.random((5, N * N)).astype(np.float32)
+    refb = O.apply_batched(A, Zb)
+    outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    absb = (np.abs(A) @ Zb.T.astype(np.float64)).T
+    for i in range(5):
+        assert np.max(np.abs(outb[i] - refb[i])) <= 2 * u * np.max(absb[i]) + 1e-30
+    img = lib.apply(torch.from_numpy(Zb[0]).cuda()).cpu().numpy()
+    assert np.all(np.abs(img - refb[0]) <= (u + IMG) * absb[0] + ENTRY * (Zb[0].astype(np.float64) @ b) + 1e-30)
+    lib.close()
+
+
+def test_cubic_and_bilinear_agree_on_axes(torch):
+    """Field points on the +x axis at sampled offsets are the samples under
+    either rotation (the spline interpolates its nodes), so the two GPU
+    libraries agree there to float32 rounding."""
+    n = N = 33
+    S = 0.5
+    radii = np.arange(0.0, 8.0, 0.5)
+    rng = np.random.default_rng(77)
+    cube = (rng.random((radii.size, n, n)) ** 2).astype(np.float32)
+    x, y, r, _, _ = O.scene_geometry(N, S)
+    on = np.nonzero((np.abs(y) < 1e-12) & (x >= 0) & (x <= radii[-1]))[0]
+    cub = _lib(torch, cube, radii, N, S)
+    from paper_2106_09122_amd import psflib
+    bil = psflib.Library(torch.from_numpy(cube).cuda(), radii, N, S)
+    gc = cub.get_columns(on).cpu().numpy()
+    gb = bil.get_columns(on).cpu().numpy()
+    assert np.max(np.abs(gc - gb)) <= 1e-5 * np.abs(gb).max()
+    cub.close()
+    bil.close()
