@@ -35,6 +35,8 @@ the repository's design notes):
 * offsets beyond the last sample either hold the last PSF (``clamp``) or give
   an all-zero column (``zero``); offsets below the first sample hold the
   first PSF;
+* optionally (flux="preserve") each column is rescaled to the total of the
+  radially interpolated PSF before rotation;
 * nearest-neighbour radial interpolation rounds ties to the lower sample;
 * the operator applies no normalisation of its own (Sec. 3 leaves PSF
   normalisation to the user); column sums are reported instead.
@@ -265,9 +267,14 @@ def rotate_cubic(Q: np.ndarray, ct: float, st: float, pad: int = SPLINE_PAD) -> 
 
 
 def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp",
-                   rotate="bilinear") -> np.ndarray:
+                   rotate="bilinear", flux="none") -> np.ndarray:
     """One library column I_j: radial interpolation, rotation, flattening
-    (Sec. 2, one iteration of the field-point loop)."""
+    (Sec. 2, one iteration of the field-point loop).
+
+    flux="preserve" rescales the column so that it sums to the flux of the
+    radially interpolated PSF Q before rotation (the part of Q that the
+    rotation carries out of the frame, or the spline's overshoot, no longer
+    changes the column's total); a column that sums to zero is left as is."""
     cube = np.asarray(cube)
     n = cube.shape[1]
     k, w, zero = radial_bracket(r, radii, interp, oob)
@@ -275,14 +282,22 @@ def library_column(cube, radii, r, ct, st, interp="linear", oob="clamp",
         return np.zeros(n * n, dtype=np.float64)
     Q = interpolate_radial(cube, k, w)
     if rotate == "cubic":
-        return rotate_cubic(Q, ct, st).ravel()
-    if rotate != "bilinear":
+        col = rotate_cubic(Q, ct, st).ravel()
+    elif rotate == "bilinear":
+        col = rotate_bilinear(Q, ct, st).ravel()
+    else:
         raise ValueError("rotate must be 'bilinear' or 'cubic'")
-    return rotate_bilinear(Q, ct, st).ravel()
+    if flux == "preserve":
+        tau = col.sum()
+        if tau != 0.0:
+            col = col * (Q.sum() / tau)
+    elif flux != "none":
+        raise ValueError("flux must be 'none' or 'preserve'")
+    return col
 
 
 def build_library(cube, radii, N: int, S: float, interp: str = "linear", oob: str = "clamp",
-                  columns=None, rotate: str = "bilinear") -> np.ndarray:
+                  columns=None, rotate: str = "bilinear", flux: str = "none") -> np.ndarray:
     """The library matrix A (Sec. 3, Eqs. (4)-(5)): n^2 rows, one column per
     scene pixel, column j the flattened interpolated-and-rotated PSF of field
     point j.  ``columns`` selects a subset of j (returned in that order).
@@ -298,7 +313,7 @@ def build_library(cube, radii, N: int, S: float, interp: str = "linear", oob: st
     cols = np.arange(N * N) if columns is None else np.asarray(columns, dtype=np.int64)
     A = np.empty((n * n, cols.size), dtype=np.float64)
     for t, j in enumerate(cols):
-        A[:, t] = library_column(cube, radii, r[j], ct[j], st[j], interp, oob, rotate)
+        A[:, t] = library_column(cube, radii, r[j], ct[j], st[j], interp, oob, rotate, flux)
     return A
 
 

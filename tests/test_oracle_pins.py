@@ -215,6 +215,32 @@ def test_cubic_column_bound():
         np.testing.assert_allclose(A[:, j], cube[k].ravel(), atol=1e-13, rtol=0)
 
 
+# ------------------------------------------------ flux-preserving rescale ----
+def test_flux_preserving_columns():
+    """flux='preserve': quarter-turn field points (bilinear rotation there is a
+    permutation of pixels, no flux lost) are unchanged; elsewhere the column is
+    scipy's rotation of the interpolated PSF scaled to the PSF's own total,
+    which leaves the frame partly for field points far off-axis."""
+    n, N, S = 15, 9, 0.7
+    rng = np.random.default_rng(31)
+    cube = rng.random((4, n, n)) ** 2
+    radii = np.array([0.0, 1.0, 2.5, 4.0])
+    x, y, r, ct, st = O.scene_geometry(N, S)
+    A0 = O.build_library(cube, radii, N, S)
+    A1 = O.build_library(cube, radii, N, S, flux="preserve")
+    axes = np.nonzero((np.abs(x) < 1e-12) | (np.abs(y) < 1e-12))[0]
+    np.testing.assert_allclose(A1[:, axes], A0[:, axes], rtol=1e-13, atol=0)
+    for j in (0, 10, 23, 40, 80):
+        k, w, _ = O.radial_bracket(r[j], radii)
+        Q = (1 - w) * cube[k] + w * cube[k + 1]
+        deg = math.degrees(math.atan2(y[j], x[j]))
+        rot = ndimage.rotate(Q, -deg, reshape=False, order=1, mode="grid-constant", cval=0.0)
+        ref = (rot * (Q.sum() / rot.sum())).ravel()
+        np.testing.assert_allclose(A1[:, j], ref, rtol=1e-10, atol=1e-13)
+    lost = A0.sum(axis=0) < 0.999 * A1.sum(axis=0)
+    assert lost.any()  # some field points do lose flux to the frame edge
+
+
 def _gauss_cube(n, radii_px, sigma):
     c = (n - 1) / 2.0
     a, b = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
