@@ -218,6 +218,17 @@ def main():
                                        "mean_pct_of_peak_vs_bilinear": float(pct.mean())}
         lc.close()
         del lc, pct
+        # flux-preserving columns: build time and the spread of the column scales
+        lf = psflib.Library(cube, d["radii"], N, S, flux="preserve", storage="fp32")
+        t_bf = _time_build(torch, psflib, lf.desc, cube, d["radii"], lf.buf, lf.nbytes)
+        t0, t1 = lib.column_sums(), lf.column_sums()
+        live = t0 != 0
+        sc = (t1[live] / t0[live]).cpu().numpy()
+        rows["flux_preserve_fp32"] = {"build_ms": t_bf, "build_ratio_vs_plain": t_bf / t_build,
+                                      "column_scale_min": float(sc.min()),
+                                      "column_scale_max": float(sc.max())}
+        lf.close()
+        del lf
         for B in (64, 256):
             Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
             out = torch.empty((B, M), device=dev, dtype=torch.float32)

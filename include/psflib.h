@@ -89,6 +89,18 @@ typedef enum { PSFLIB_FP32 = 0, PSFLIB_BF16_POW2 = 1, PSFLIB_FP16_POW2 = 2 } psf
  *            value. */
 typedef enum { PSFLIB_ROTATE_BILINEAR = 0, PSFLIB_ROTATE_CUBIC = 1 } psflib_rotate;
 
+/* Column normalisation.
+ *  NONE      columns are the rotated PSFs as sampled (the default; the column
+ *            sums tau_j are reported by psflib_column_sums).
+ *  PRESERVE  column j is rescaled so that it sums to the flux of the radially
+ *            interpolated PSF before rotation, (1-w) sum(P_k) + w sum(P_{k+1}):
+ *            the part of the PSF that the rotation carries out of the frame
+ *            (and the spline's overshoot) no longer changes the total.  A
+ *            column that sums to zero is left as is.  The 16-bit forms are
+ *            built in float32, rescaled, then rounded, with the column
+ *            exponent taken from the rescaled bound. */
+typedef enum { PSFLIB_FLUX_NONE = 0, PSFLIB_FLUX_PRESERVE = 1 } psflib_flux;
+
 typedef struct {
   int32_t n;             /* PSF side = image side (pixels); the image has n*n pixels */
   int32_t n_psf;         /* K >= 1 sampled off-axis PSFs, sources on +x */
@@ -98,7 +110,7 @@ typedef struct {
   int32_t oob;           /* psflib_oob */
   int32_t storage;       /* psflib_storage */
   int32_t rotate;        /* psflib_rotate */
-  int32_t reserved;      /* must be 0 */
+  int32_t flux;          /* psflib_flux */
 } psflib_desc;
 
 typedef struct psflib_handle psflib_handle;

@@ -18,8 +18,10 @@
 // are float32 (relative error a few float32 units, as the entries are
 // non-negative combinations).
 //
-// The 16-bit storage forms are built as float32 into scratch and packed by a
-// second kernel (scale by 2^-e_j, round to nearest even, 8 columns per 16 B).
+// The kernel writes float32 columns; the 16-bit storage forms are built into
+// scratch and packed by a second kernel (scale by 2^-e_j, round to nearest
+// even, 8 columns per 16 B), which the gather builds also use when a column
+// needs float32 post-processing (the flux-preserving rescale).
 #include <math.h>
 
 #include "psflib_internal.h"
@@ -341,20 +343,29 @@ bool build_lds_supported(int n, int K) {
 
 static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
 
-size_t build_lds_scratch_bytes(int storage, int K, int64_t M, int64_t ncols) {
+size_t build_lds_scratch_bytes(int K, int64_t ncols) {
   const int64_t nb = nbuckets(K);
   const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
   size_t b = 0;
   b += ((size_t)nb * 4 * 3 + 255) & ~(size_t)255;           // cnt, cursor, bstart
   b += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;  // items + nitems
   b += ((size_t)ncols * 4 + 255) & ~(size_t)255;            // order
-  if (storage != PSFLIB_FP32) b += (size_t)ncols * (size_t)M * 4;  // float32 columns
   return b;
 }
 
-hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom* geo, int n,
-                            int64_t M, int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
-                            void* scratch, hipStream_t s) {
+hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int64_t M,
+                         int64_t ncols, int64_t ncols_pad, void* lib, hipStream_t s) {
+  const dim3 pgrid((unsigned)((M + 511) / 512), (unsigned)(ncols_pad / 8));
+  u32x4* Mp = reinterpret_cast<u32x4*>(lib);
+  if (storage == PSFLIB_BF16_POW2)
+    pack16_kernel<true><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+  else
+    pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
+                            int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s) {
   const int nb = nbuckets(K);
   const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
   char* p = reinterpret_cast<char*>(scratch);
@@ -366,8 +377,6 @@ hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom
   int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
   p += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;
   int32_t* order = reinterpret_cast<int32_t*>(p);
-  p += ((size_t)ncols * 4 + 255) & ~(size_t)255;
-  float* A32 = (storage == PSFLIB_FP32) ? reinterpret_cast<float*>(lib) : reinterpret_cast<float*>(p);
 
   hipError_t e = hipMemsetAsync(cnt, 0, (size_t)nb * 4 * 2, s);  // cnt and cursor
   if (e != hipSuccess) return e;
@@ -396,14 +405,6 @@ hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom
     default: e = launch(build_lds_kernel<3, false>); break;
   }
   if (e != hipSuccess) return e;
-  e = hipGetLastError();
-  if (e != hipSuccess || storage == PSFLIB_FP32) return e;
-  const dim3 pgrid((unsigned)((M + 511) / 512), (unsigned)(ncols_pad / 8));
-  u32x4* Mp = reinterpret_cast<u32x4*>(lib);
-  if (storage == PSFLIB_BF16_POW2)
-    pack16_kernel<true><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
-  else
-    pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
   return hipGetLastError();
 }
 

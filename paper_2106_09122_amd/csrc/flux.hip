@@ -1,0 +1,97 @@
+// Optional flux-preserving column rescale.
+//
+// Rotating the radially interpolated PSF Q inside a fixed n x n frame (Sec. 2)
+// loses the part of Q carried out of the frame, and a cubic spline's
+// overshoot changes the total slightly.  With PSFLIB_FLUX_PRESERVE each
+// column is scaled by t_j / tau_j, where t_j = (1-w) sum(P_k) + w sum(P_{k+1})
+// is the flux of Q and tau_j the column's own sum, so the column carries the
+// flux of the PSF it was interpolated from.  The scale is applied to the
+// float32 column (one rounding), the column sum is recomputed from the
+// stored values, and for the 16-bit forms the column exponent is recomputed
+// from the rescaled bound before the column is rounded.
+#include <math.h>
+
+#include "psflib_internal.h"
+
+namespace psflib {
+
+namespace {
+
+__device__ inline int32_t exponent_of(double m) {  // m * 2^-e in [2^14, 2^15), 0 for m == 0
+  if (m == 0.0) return 0;
+  int E;
+  (void)frexp(m, &E);
+  return E - 15;
+}
+
+// sums[k] = sum_p P_k[p] in float64, fixed-order tree; one workgroup per PSF.
+__global__ __launch_bounds__(256) void psf_sums_kernel(const float* __restrict__ cube, int64_t M,
+                                                       double* __restrict__ sums) {
+  __shared__ double red[256];
+  const float* P = cube + (int64_t)blockIdx.x * M;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < M; i += 256) acc += (double)P[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// One workgroup per column.
+__global__ __launch_bounds__(256) void flux_rescale_kernel(
+    float* __restrict__ A32, ColGeom* __restrict__ geo, int K, const double* __restrict__ sums,
+    const float* __restrict__ pmax, int64_t M, double* __restrict__ tau,
+    int32_t* __restrict__ exps, int want_exp) {
+  __shared__ double red[256];
+  const int64_t j = blockIdx.x;
+  const ColGeom g = geo[j];
+  if (g.k < 0) return;  // identically zero column: nothing to scale
+  const double t = (K == 1) ? sums[0] : (1.0 - g.w) * sums[g.k] + g.w * sums[g.k + 1];
+  const double old = tau[j];
+  const double scale = (old != 0.0) ? t / old : 1.0;
+  const float sf = (float)scale;
+  float* col = A32 + j * M;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < M; i += 256) {
+    const float v = col[i] * sf;
+    col[i] = v;
+    acc += (double)v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tau[j] = red[0];
+    if (want_exp) {
+      const double bound = (K == 1) ? (double)pmax[0]
+                                    : (1.0 - g.w) * (double)pmax[g.k] + g.w * (double)pmax[g.k + 1];
+      const int32_t e = exponent_of(bound * fabs((double)sf));
+      geo[j].e = e;
+      exps[j] = e;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_psf_sums(const float* cube, int K, int64_t M, double* sums, hipStream_t s) {
+  psf_sums_kernel<<<K, 256, 0, s>>>(cube, M, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_rescale(float* A32, ColGeom* geo, int K, const double* sums,
+                               const float* pmax, int64_t M, int64_t ncols, double* tau,
+                               int32_t* exps, bool want_exp, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  flux_rescale_kernel<<<(unsigned)ncols, 256, 0, s>>>(A32, geo, K, sums, pmax, M, tau, exps,
+                                                      want_exp ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace psflib

@@ -93,7 +93,8 @@ psflib_status check_desc(const psflib_desc* d) {
     return fail(PSFLIB_ERR_INVALID_ARG, "unknown storage");
   if (d->rotate != PSFLIB_ROTATE_BILINEAR && d->rotate != PSFLIB_ROTATE_CUBIC)
     return fail(PSFLIB_ERR_INVALID_ARG, "unknown rotate mode");
-  if (d->reserved != 0) return fail(PSFLIB_ERR_INVALID_ARG, "reserved must be 0");
+  if (d->flux != PSFLIB_FLUX_NONE && d->flux != PSFLIB_FLUX_PRESERVE)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unknown flux mode");
   return PSFLIB_OK;
 }
 
@@ -237,12 +238,19 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // Cubic-spline rotation: spline coefficients of the cube, then a gather
   // build over coefficient pairs.  Bilinear: small PSFs (the bordered pair
   // fits the LDS) take the bucketed LDS build; larger ones gather from a
-  // pair-interleaved copy of the cube.
+  // pair-interleaved copy of the cube.  The LDS build writes float32 columns,
+  // and so does every build when the flux-preserving rescale follows; the
+  // 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
+  const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
   const bool lds = !cubic && psflib::build_lds_supported(desc->n, K);
-  const size_t tmp_bytes = cubic ? psflib::spline_scratch_bytes(K, desc->n)
-                           : lds ? psflib::build_lds_scratch_bytes(storage, K, L.M, L.ncols)
-                                 : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8;
+  const bool stage32 = storage != PSFLIB_FP32 && (lds || flux);
+  const size_t path_bytes = align256(cubic ? psflib::spline_scratch_bytes(K, desc->n)
+                                     : lds ? psflib::build_lds_scratch_bytes(K, L.ncols)
+                                           : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
+  const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
+  const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
+  const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
   void* tmp = nullptr;
   auto bail = [&](hipError_t err, const char* what) {
     psflib_status r = device_fail(err, what);
@@ -256,9 +264,16 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
   e = scratch_alloc(&tmp, tmp_bytes, dev, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "scratch allocation (build)"); }
+  char* tp = reinterpret_cast<char*>(tmp);
+  void* path_tmp = tp;
+  float* A32 = stage32 ? reinterpret_cast<float*>(tp + path_bytes) : reinterpret_cast<float*>(d_lib);
+  double* sums = flux ? reinterpret_cast<double*>(tp + path_bytes + stage_bytes) : nullptr;
+  // the format the build kernel writes, and where
+  const int bstore = stage32 ? PSFLIB_FP32 : storage;
+  void* bdst = stage32 ? reinterpret_cast<void*>(A32) : d_lib;
   if (cubic) {
     // the 16-bit exponent bound takes the largest |coefficient| per PSF
-    e = psflib::launch_spline_pairs(d_cube, K, desc->n, tmp,
+    e = psflib::launch_spline_pairs(d_cube, K, desc->n, path_tmp,
                                     storage != PSFLIB_FP32 ? h->pmax : nullptr, s);
     if (e != hipSuccess) return bail(e, "spline coefficient kernels");
   } else if (storage != PSFLIB_FP32) {
@@ -270,19 +285,30 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
   if (cubic) {
-    e = psflib::launch_build_cubic(storage, psflib::spline_pairs_of(tmp, K, desc->n), h->geo,
-                                   desc->n, L.M, L.ncols, L.ncols_pad, d_lib, tau, s);
+    e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
+                                   desc->n, L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "cubic build kernel");
   } else if (lds) {
-    e = psflib::launch_build_lds(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
-                                 d_lib, tau, tmp, s);
+    e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, L.M, L.ncols,
+                                 reinterpret_cast<float*>(bdst), tau, path_tmp, s);
     if (e != hipSuccess) return bail(e, "LDS build kernels");
   } else {
-    e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(tmp), s);
+    e = psflib::launch_pair_cube(d_cube, K, L.M, reinterpret_cast<float*>(path_tmp), s);
     if (e != hipSuccess) return bail(e, "pair_cube kernel");
-    e = psflib::launch_build(storage, reinterpret_cast<const float*>(tmp), h->geo, desc->n, L.M,
-                             L.ncols, L.ncols_pad, d_lib, tau, s);
+    e = psflib::launch_build(bstore, reinterpret_cast<const float*>(path_tmp), h->geo, desc->n,
+                             L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "build kernel");
+  }
+  if (flux) {
+    e = psflib::launch_psf_sums(d_cube, K, L.M, sums, s);
+    if (e != hipSuccess) return bail(e, "psf sums kernel");
+    e = psflib::launch_flux_rescale(reinterpret_cast<float*>(bdst), h->geo, K, sums, h->pmax, L.M,
+                                    L.ncols, tau, exps, storage != PSFLIB_FP32, s);
+    if (e != hipSuccess) return bail(e, "flux rescale kernel");
+  }
+  if (stage32) {
+    e = psflib::launch_pack16(storage, A32, h->geo, L.M, L.ncols, L.ncols_pad, d_lib, s);
+    if (e != hipSuccess) return bail(e, "16-bit packing kernel");
   }
   e = hipFreeAsync(tmp, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipFreeAsync(build scratch)"); }

@@ -75,10 +75,20 @@ hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* ge
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K);
-size_t build_lds_scratch_bytes(int storage, int K, int64_t M, int64_t ncols);
-hipError_t launch_build_lds(int storage, const float* cube, int K, const ColGeom* geo, int n,
-                            int64_t M, int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
-                            void* scratch, hipStream_t s);
+size_t build_lds_scratch_bytes(int K, int64_t ncols);
+// float32 columns (A32[j*M + i]) and their float64 sums
+hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
+                            int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s);
+// 16-bit storage from float32 columns with the exponents in geo
+hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int64_t M,
+                         int64_t ncols, int64_t ncols_pad, void* lib, hipStream_t s);
+// Flux-preserving rescale of float32 columns: sums[k] = sum(P_k) (float64),
+// column j scaled by t_j / tau_j, tau_j recomputed; with want_exp the 16-bit
+// exponents (geo[j].e and exps[j]) follow the rescaled bound.
+hipError_t launch_psf_sums(const float* cube, int K, int64_t M, double* sums, hipStream_t s);
+hipError_t launch_flux_rescale(float* A32, ColGeom* geo, int K, const double* sums,
+                               const float* pmax, int64_t M, int64_t ncols, double* tau,
+                               int32_t* exps, bool want_exp, hipStream_t s);
 hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
                          int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                          hipStream_t s);

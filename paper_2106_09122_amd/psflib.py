@@ -24,6 +24,7 @@ INTERP = {"linear": 0, "nearest": 1}
 OOB = {"clamp": 0, "zero": 1}
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
 ROTATE = {"bilinear": 0, "cubic": 1}
+FLUX = {"none": 0, "preserve": 1}
 
 
 class PsflibError(RuntimeError):
@@ -43,7 +44,7 @@ class Desc(ctypes.Structure):
         ("oob", ctypes.c_int32),
         ("storage", ctypes.c_int32),
         ("rotate", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
     ]
 
 
@@ -109,7 +110,7 @@ def _check(status: int, where: str):
 
 
 def make_desc(n: int, n_psf: int, N: int, scene_pixscale: float, interp="linear", oob="clamp",
-              storage="fp32", rotate="bilinear") -> Desc:
+              storage="fp32", rotate="bilinear", flux="none") -> Desc:
     d = Desc()
     d.n, d.n_psf, d.N = int(n), int(n_psf), int(N)
     d.scene_pixscale = float(scene_pixscale)
@@ -117,7 +118,7 @@ def make_desc(n: int, n_psf: int, N: int, scene_pixscale: float, interp="linear"
     d.oob = OOB[oob] if isinstance(oob, str) else int(oob)
     d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     d.rotate = ROTATE[rotate] if isinstance(rotate, str) else int(rotate)
-    d.reserved = 0
+    d.flux = FLUX[flux] if isinstance(flux, str) else int(flux)
     return d
 
 
@@ -280,7 +281,7 @@ class Library:
     """
 
     def __init__(self, cube, radii, N: int, S: float, interp="linear", oob="clamp",
-                 storage="fp32", stream=None, rotate="bilinear"):
+                 storage="fp32", stream=None, rotate="bilinear", flux="none"):
         import torch
         if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32):
             raise TypeError("cube must be a float32 CUDA tensor [K][n][n]")
@@ -292,7 +293,7 @@ class Library:
         self.N, self.S = int(N), float(S)
         self.storage = storage
         self.radii = np.asarray(radii, dtype=np.float64)
-        self.desc = make_desc(self.n, self.K, self.N, self.S, interp, oob, storage, rotate)
+        self.desc = make_desc(self.n, self.K, self.N, self.S, interp, oob, storage, rotate, flux)
         self.nbytes = library_bytes(self.desc)
         self.device = cube.device
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)

@@ -67,7 +67,7 @@ def _err(fn, *a):
 @pytest.mark.parametrize("field,val", [("n", 0), ("n", 9000), ("N", 0), ("n_psf", 0),
                                        ("scene_pixscale", 0.0), ("scene_pixscale", float("nan")),
                                        ("scene_pixscale", float("inf")), ("interp", 7),
-                                       ("oob", -1), ("storage", 3), ("rotate", 2), ("reserved", 1)])
+                                       ("oob", -1), ("storage", 3), ("rotate", 2), ("flux", 2)])
 def test_bad_desc_rejected(field, val):
     d = psflib.make_desc(8, 3, 8, 0.5)
     setattr(d, field, val)

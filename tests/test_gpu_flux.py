@@ -1,0 +1,112 @@
+"""Flux-preserving columns (GPU, through the C ABI) against the FP64 oracle.
+
+Each column is scaled by s_j = t_j / tau_j (t_j the flux of the radially
+interpolated PSF, tau_j the column's sum), so beyond the plain build's error
+the scaling adds one float32 rounding per entry:
+  * bilinear entries (non-negative): relative 2e-6, exact zeros;
+  * cubic entries: |dA_ij| <= 2e-6 * |s_j| b_j (b_j the coefficient bound);
+  * column sums equal t_j to 1e-6 (relative);
+  * images: per pixel 1e-5 relative (bilinear), 1e-5 (|A||Z|)_i (cubic);
+  * 16-bit: exponents obey the rule for |s_j| b_j to 1e-6, entries within
+    u |A| + 2e-6 |s_j| b_j + half the FP16 subnormal spacing.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U16 = {"bf16": 2.0**-8, "fp16": 2.0**-11}
+
+CASES = [
+    # n, N, S, K, kind, rotate  (32^2 takes the LDS build, 150^2 the gather build)
+    (32, 32, 0.5, 16, "c1", "bilinear"),
+    (150, 5, 0.4, 4, "nonuniform", "bilinear"),
+    (32, 32, 0.5, 16, "c1", "cubic"),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+_cache = {}
+
+
+def _oracle(case):
+    if case not in _cache:
+        n, N, S, K, kind, rotate = case
+        if kind == "c1":
+            d = synth.config_inputs(1)
+            cube, radii = d["cube"], d["radii"]
+        else:
+            rng = np.random.default_rng(n * 7 + N)
+            radii = np.concatenate([[0.0], np.cumsum(rng.uniform(0.05, 0.9, K - 1))])
+            cube = (rng.random((K, n, n)) ** 3).astype(np.float32)
+        A0 = O.build_library(cube, radii, N, S, rotate=rotate)
+        A1 = O.build_library(cube, radii, N, S, rotate=rotate, flux="preserve")
+        tau0 = A0.sum(axis=0)
+        t = A1.sum(axis=0)
+        s = np.where(tau0 != 0, t / np.where(tau0 != 0, tau0, 1.0), 1.0)
+        b = O.column_max_bound(cube, radii, N, S, rotate=rotate)
+        _cache[case] = (cube, radii, A1, t, s, b)
+    return _cache[case]
+
+
+def _lib(torch, case, **kw):
+    from paper_2106_09122_amd import psflib
+    n, N, S, K, kind, rotate = case
+    cube, radii = _oracle(case)[:2]
+    return psflib.Library(torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float32)).cuda(),
+                          radii, N, S, rotate=rotate, flux="preserve", **kw)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_flux_fp32(torch, case):
+    n, N, S, K, kind, rotate = case
+    cube, radii, A, t, s, b = _oracle(case)
+    lib = _lib(torch, case)
+    got = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
+    if rotate == "bilinear":
+        pos = A > 0
+        assert np.all(got[~pos] == 0)
+        assert np.max(np.abs(got[pos] - A[pos]) / A[pos]) <= 2e-6
+    else:
+        assert np.all(np.abs(got - A) <= 2e-6 * (np.abs(s) * b)[None, :] + 1e-300)
+    tau = lib.column_sums().cpu().numpy()
+    live = t != 0
+    assert np.all(tau[~live] == 0)
+    assert np.max(np.abs(tau[live] - t[live]) / np.abs(t[live])) <= 1e-6
+    rng = np.random.default_rng(5)
+    Z = rng.random(N * N).astype(np.float32)
+    img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = O.apply(A, Z)
+    den = np.abs(A) @ Z.astype(np.float64)
+    assert np.all(np.abs(img - ref) <= 1e-5 * den + 1e-300)
+    lib.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("case", CASES)
+def test_flux_16bit(torch, fmt, case):
+    n, N, S, K, kind, rotate = case
+    cube, radii, A, t, s, b = _oracle(case)
+    lib = _lib(torch, case, storage=fmt)
+    e = lib.exponents().cpu().numpy().astype(np.int64)
+    bs = np.abs(s) * b
+    live = bs > 0
+    scaled = bs[live] * np.ldexp(1.0, -e[live])
+    assert np.all((scaled >= 2.0**14 * (1 - 1e-6)) & (scaled < 2.0**15 * (1 + 1e-6)))
+    u = U16[fmt]
+    deq = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
+    tol = u * (1 + 1e-5) * np.abs(A) + 2e-6 * bs[None, :] + (2.0**-25) * np.ldexp(1.0, e)[None, :]
+    assert np.all(np.abs(deq - A) <= tol)
+    tau = lib.column_sums().cpu().numpy()
+    ok = t != 0
+    assert np.max(np.abs(tau[ok] - t[ok]) / np.abs(t[ok])) <= 1e-6
+    lib.close()
