@@ -89,18 +89,6 @@ __device__ __forceinline__ uint32_t f32_to_f16_rne(float f) {
   return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-// Cubic B-spline weight (float64, the oracle's expressions).
-__device__ __forceinline__ double bspline3(double t) {
-#pragma clang fp contract(off)
-  t = fabs(t);
-  if (t < 1.0) return 2.0 / 3.0 - t * t + t * t * t / 2.0;
-  if (t < 2.0) {
-    const double u = 2.0 - t;
-    return u * u * u / 6.0;
-  }
-  return 0.0;
-}
-
 // Cubic-spline rotation: the same source point as the bilinear form, in the
 // coordinates of the spline coefficients (padded by kSplinePad), sampled with
 // the 4 x 4 B-spline weights; each tap blends the coefficient pair of the
@@ -112,20 +100,18 @@ __device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int 
   const double sy = (-cp.st) * ux + cp.ct * uy;
   const double colf = c + sx + (double)kSplinePad;
   const double rowf = c + sy + (double)kSplinePad;
-  const int c0 = (int)floor(colf);
-  const int r0 = (int)floor(rowf);
-  double wy[4], wx[4];
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    wy[d] = bspline3(rowf - (double)(r0 + d - 1));
-    wx[d] = bspline3(colf - (double)(c0 + d - 1));
-  }
+  const double c0f = floor(colf), r0f = floor(rowf);
+  const int c0 = (int)c0f;
+  const int r0 = (int)r0f;
+  float wy[4], wx[4];
+  cubic_weights(rowf - r0f, wy);
+  cubic_weights(colf - c0f, wx);
   float v = 0.0f;
 #pragma unroll
   for (int dr = 0; dr < 4; ++dr)
 #pragma unroll
     for (int dc = 0; dc < 4; ++dc)
-      v = fmaf((float)(wy[dr] * wx[dc]), tap(cp.src, Np, r0 + dr - 1, c0 + dc - 1, cp.wk0, cp.wk1), v);
+      v = fmaf(wy[dr] * wx[dc], tap(cp.src, Np, r0 + dr - 1, c0 + dc - 1, cp.wk0, cp.wk1), v);
   return v;
 }
 

@@ -343,7 +343,7 @@ bool build_lds_supported(int n, int K) {
 
 static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
 
-size_t build_lds_scratch_bytes(int K, int64_t ncols) {
+size_t bucket_scratch_bytes(int K, int64_t ncols) {
   const int64_t nb = nbuckets(K);
   const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
   size_t b = 0;
@@ -351,6 +351,35 @@ size_t build_lds_scratch_bytes(int K, int64_t ncols) {
   b += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;  // items + nitems
   b += ((size_t)ncols * 4 + 255) & ~(size_t)255;            // order
   return b;
+}
+
+size_t build_lds_scratch_bytes(int K, int64_t ncols) { return bucket_scratch_bytes(K, ncols); }
+
+hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* scratch,
+                              BucketPlan* plan, hipStream_t s) {
+  const int nb = nbuckets(K);
+  const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
+  char* p = reinterpret_cast<char*>(scratch);
+  int32_t* cnt = reinterpret_cast<int32_t*>(p);
+  int32_t* cursor = cnt + nb;
+  int32_t* bstart = cursor + nb;
+  p += ((size_t)nb * 4 * 3 + 255) & ~(size_t)255;
+  int4* items = reinterpret_cast<int4*>(p);
+  int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
+  p += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;
+  int32_t* order = reinterpret_cast<int32_t*>(p);
+  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)nb * 4 * 2, s);  // cnt and cursor
+  if (e != hipSuccess) return e;
+  const unsigned cgrid = (unsigned)((ncols + 255) / 256);
+  bucket_count_kernel<<<cgrid, 256, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt);
+  bucket_scan_kernel<<<1, 1024, 0, s>>>(cnt, nb, bstart, items, nitems);
+  bucket_scatter_kernel<<<cgrid, 256, (size_t)nb * 8, s>>>(geo, ncols, nb, bstart, cursor, order);
+  plan->order = order;
+  plan->items = items;
+  plan->nitems = nitems;
+  plan->items_max = items_max;
+  plan->nb = nb;
+  return hipGetLastError();
 }
 
 hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int64_t M,
@@ -366,26 +395,14 @@ hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int6
 
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
                             int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s) {
-  const int nb = nbuckets(K);
-  const int64_t items_max = (ncols + kLdsCols - 1) / kLdsCols + nb;
-  char* p = reinterpret_cast<char*>(scratch);
-  int32_t* cnt = reinterpret_cast<int32_t*>(p);
-  int32_t* cursor = cnt + nb;
-  int32_t* bstart = cursor + nb;
-  p += ((size_t)nb * 4 * 3 + 255) & ~(size_t)255;
-  int4* items = reinterpret_cast<int4*>(p);
-  int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
-  p += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;
-  int32_t* order = reinterpret_cast<int32_t*>(p);
-
-  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)nb * 4 * 2, s);  // cnt and cursor
+  BucketPlan bp;
+  hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
-  const unsigned cgrid = (unsigned)((ncols + 255) / 256);
-  bucket_count_kernel<<<cgrid, 256, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt);
-  bucket_scan_kernel<<<1, 1024, 0, s>>>(cnt, nb, bstart, items, nitems);
-  bucket_scatter_kernel<<<cgrid, 256, (size_t)nb * 8, s>>>(geo, ncols, nb, bstart, cursor, order);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const int32_t* order = bp.order;
+  const int4* items = bp.items;
+  const int32_t* nitems = bp.nitems;
+  const int nb = bp.nb;
+  const int64_t items_max = bp.items_max;
 
   const int ls = lds_stride(n);
   const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);

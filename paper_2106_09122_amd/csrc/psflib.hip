@@ -243,11 +243,14 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
-  const bool lds = !cubic && psflib::build_lds_supported(desc->n, K);
+  const bool lds = cubic ? psflib::build_cubic_lds_supported(desc->n)
+                         : psflib::build_lds_supported(desc->n, K);
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux);
-  const size_t path_bytes = align256(cubic ? psflib::spline_scratch_bytes(K, desc->n)
-                                     : lds ? psflib::build_lds_scratch_bytes(K, L.ncols)
-                                           : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
+  const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
+  const size_t path_bytes =
+      spline_bytes + align256(lds ? psflib::bucket_scratch_bytes(K, L.ncols)
+                              : cubic ? 0
+                                      : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
   const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
   const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
@@ -284,7 +287,12 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
-  if (cubic) {
+  if (cubic && lds) {
+    e = psflib::launch_build_cubic_lds(psflib::spline_pairs_of(path_tmp, K, desc->n), K, h->geo,
+                                       desc->n, L.M, L.ncols, reinterpret_cast<float*>(bdst), tau,
+                                       tp + spline_bytes, s);
+    if (e != hipSuccess) return bail(e, "cubic LDS build kernels");
+  } else if (cubic) {
     e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
                                    desc->n, L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "cubic build kernel");

@@ -55,6 +55,19 @@ psflib_status device_fail_status(hipError_t e, const char* what);
 void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
                  int64_t* ncols, int64_t* ncols_pad, int* storage, int* device);
 
+// The four cubic B-spline weights of the taps at offsets -1, 0, +1, +2 from
+// floor(x), for t = x - floor(x) in [0, 1): beta3 at distances 1+t, t, 1-t,
+// 2-t (all exact in float64), evaluated in float64 and rounded to float32.
+__device__ __forceinline__ void cubic_weights(double t, float w[4]) {
+#pragma clang fp contract(off)
+  constexpr double sixth = 1.0 / 6.0;  // a product, not a float64 division (within an ulp)
+  const double s = 1.0 - t;
+  w[0] = (float)(s * s * s * sixth);
+  w[1] = (float)(2.0 / 3.0 - t * t + t * t * t * 0.5);
+  w[2] = (float)(2.0 / 3.0 - s * s + s * s * s * 0.5);
+  w[3] = (float)(t * t * t * sixth);
+}
+
 // ---- kernel launchers (each returns hipGetLastError() after its launch) ----
 hipError_t launch_cube_max(const float* cube, int K, int64_t M, float* pmax, hipStream_t s);
 hipError_t launch_pair_cube(const float* cube, int K, int64_t M, float* pairs, hipStream_t s);
@@ -72,10 +85,31 @@ const float* spline_pairs_of(const void* scratch, int K, int n);
 hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                               int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
                               hipStream_t s);
+// Cubic build with the coefficient pair staged in LDS by row bands (float32
+// columns); false if the PSF is too large for bands of useful height.
+bool build_cubic_lds_supported(int n);
+size_t build_cubic_lds_scratch_bytes(int K, int64_t ncols);
+hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo, int n, int64_t M,
+                                  int64_t ncols, float* A32, double* tau, void* scratch,
+                                  hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K);
 size_t build_lds_scratch_bytes(int K, int64_t ncols);
+// Columns grouped by radial bracket on the device: order[] lists the columns
+// bucket by bucket (bucket k = bracket k, the last bucket = zero columns);
+// items[t] = (bucket, first position in order, length <= kLdsCols, 0) for
+// t < *nitems <= items_max.
+struct BucketPlan {
+  const int32_t* order;
+  const int4* items;
+  const int32_t* nitems;
+  int64_t items_max;
+  int nb;
+};
+size_t bucket_scratch_bytes(int K, int64_t ncols);
+hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* scratch,
+                              BucketPlan* plan, hipStream_t s);
 // float32 columns (A32[j*M + i]) and their float64 sums
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
                             int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s);
