@@ -150,15 +150,62 @@ __global__ __launch_bounds__(kGrpThreads, 2) void grouped_f32_kernel(
 
 // 16-bit: one thread per row (256 rows per workgroup), one 16-byte load per
 // 8-column group; the chunk's scene values times 2^e_j are staged in LDS.
+// Library loads run one batch of 8 groups ahead of the multiply (two
+// register sets), and the first batch of an item is issued before its scene
+// values are staged, so the loads stay in flight across both.
+template <bool BF16>
+__device__ __forceinline__ void grouped_h16_batch(const u32x4 (&pk)[8], int64_t g, int64_t ng,
+                                                  int nscenes, const float (*zs)[kGrpMaxChunkGroups * 8],
+                                                  float (&acc)[kGrpScenes]) {
+  float inner[kGrpScenes];
+#pragma unroll
+  for (int r = 0; r < kGrpScenes; ++r) inner[r] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (g + t >= ng) break;
+    const uint32_t wd[4] = {pk[t].x, pk[t].y, pk[t].z, pk[t].w};
+    float f[8];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      if (BF16) {
+        f[2 * h] = __uint_as_float(wd[h] << 16);
+        f[2 * h + 1] = __uint_as_float(wd[h] & 0xFFFF0000u);
+      } else {
+        f[2 * h] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] & 0xFFFFu));
+        f[2 * h + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] >> 16));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kGrpScenes; ++r) {
+      if (r >= nscenes) break;
+      const float* z = &zs[r][(g + t) * 8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) inner[r] = fmaf(f[u], z[u], inner[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kGrpScenes; ++r) acc[r] += inner[r];
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(kGrpThreads) void grouped_h16_kernel(
     const GItem* __restrict__ items, int64_t nitems, const float* const* __restrict__ scenes,
     float* __restrict__ part) {
   __shared__ float zs[kGrpScenes][kGrpMaxChunkGroups * 8];
+  const u32x4 z4 = {0u, 0u, 0u, 0u};
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem w = items[it];
     const u32x4* Mp = reinterpret_cast<const u32x4*>(w.A);
     const int64_t ng = w.j1 - w.j0;
+    const int64_t i = w.row0 + threadIdx.x;
+    const bool row_ok = i < w.M;
+    auto load = [&](int64_t g, u32x4 (&pk)[8]) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        pk[t] = (row_ok && g + t < ng) ? __builtin_nontemporal_load(Mp + (w.j0 + g + t) * w.M + i) : z4;
+    };
+    u32x4 pa[8], pb[8];
+    load(0, pa);
     __syncthreads();  // the previous item is done with zs
     for (int64_t t = threadIdx.x; t < ng * 8 * kGrpScenes; t += kGrpThreads) {
       const int r = (int)(t / (ng * 8));
@@ -169,45 +216,16 @@ __global__ __launch_bounds__(kGrpThreads) void grouped_h16_kernel(
       zs[r][q] = v;
     }
     __syncthreads();
-    const int64_t i = w.row0 + threadIdx.x;
     float acc[kGrpScenes];
 #pragma unroll
     for (int r = 0; r < kGrpScenes; ++r) acc[r] = 0.0f;
-    if (i < w.M) {
-      for (int64_t g = 0; g < ng; g += 8) {
-        u32x4 pk[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          pk[t] = (g + t < ng) ? __builtin_nontemporal_load(Mp + (w.j0 + g + t) * w.M + i)
-                               : (u32x4){0u, 0u, 0u, 0u};
-        float inner[kGrpScenes];
-#pragma unroll
-        for (int r = 0; r < kGrpScenes; ++r) inner[r] = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (g + t >= ng) break;
-          const uint32_t wd[4] = {pk[t].x, pk[t].y, pk[t].z, pk[t].w};
-          float f[8];
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            if (BF16) {
-              f[2 * h] = __uint_as_float(wd[h] << 16);
-              f[2 * h + 1] = __uint_as_float(wd[h] & 0xFFFF0000u);
-            } else {
-              f[2 * h] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] & 0xFFFFu));
-              f[2 * h + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] >> 16));
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < kGrpScenes; ++r) {
-            if (r >= w.nscenes) break;
-            const float* z = &zs[r][(g + t) * 8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) inner[r] = fmaf(f[u], z[u], inner[r]);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < kGrpScenes; ++r) acc[r] += inner[r];
+    if (row_ok) {
+      for (int64_t g = 0; g < ng; g += 16) {
+        load(g + 8, pb);
+        grouped_h16_batch<BF16>(pa, g, ng, w.nscenes, zs, acc);
+        if (g + 8 >= ng) break;
+        load(g + 16, pa);
+        grouped_h16_batch<BF16>(pb, g + 8, ng, w.nscenes, zs, acc);
       }
     }
 #pragma unroll
