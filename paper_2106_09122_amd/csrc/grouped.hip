@@ -27,7 +27,8 @@
 
 namespace psflib {
 
-constexpr int kGrpScenes = 8;   // scenes multiplied per pass over a tile
+constexpr int kGrpScenes = 8;     // FP32: scenes multiplied per pass over a tile
+constexpr int kGrpScenes16 = 16;  // 16-bit: scenes per pass (the library is read once per pass)
 constexpr int kGrpThreads = 256;
 
 struct GItem {
@@ -37,7 +38,23 @@ struct GItem {
   int64_t row0;           // first row of the block
   int64_t j0, j1;         // columns (FP32) or 8-column groups (16-bit) of the chunk
   int32_t scene0, nscenes;  // scenes (index into the plan's scene table)
-  int64_t part;           // float offset of this item's partials: [kGrpScenes][rows]
+  int64_t part;           // float offset of this item's partials: [scenes per pass][rows]
+  int64_t bpk;            // 16-bit: packed scene operand of the scene group, group 0
+};
+
+// A scene slot of the plan: its values and its library's column exponents.
+struct GScene {
+  const float* z;
+  const int32_t* exps;
+  int64_t ncols;
+};
+
+// A 16-bit scene group: slots slot0 .. slot0+nscenes-1 of one library, packed
+// into the matrix-core operand at bpk (ngroups x 32 columns x 16 bytes).
+struct GPack {
+  int64_t bpk, ncols, ngroups;
+  const int32_t* exps;
+  int32_t slot0, nscenes;
 };
 
 struct GReduce {
@@ -148,88 +165,175 @@ __global__ __launch_bounds__(kGrpThreads, 2) void grouped_f32_kernel(
   }
 }
 
-// 16-bit: one thread per row (256 rows per workgroup), one 16-byte load per
-// 8-column group; the chunk's scene values times 2^e_j are staged in LDS.
-// Library loads run one batch of 8 groups ahead of the multiply (two
-// register sets), and the first batch of an item is issued before its scene
-// values are staged, so the loads stay in flight across both.
-template <bool BF16>
-__device__ __forceinline__ void grouped_h16_batch(const u32x4 (&pk)[8], int64_t g, int64_t ng,
-                                                  int nscenes, const float (*zs)[kGrpMaxChunkGroups * 8],
-                                                  float (&acc)[kGrpScenes]) {
-  float inner[kGrpScenes];
-#pragma unroll
-  for (int r = 0; r < kGrpScenes; ++r) inner[r] = 0.0f;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    if (g + t >= ng) break;
-    const uint32_t wd[4] = {pk[t].x, pk[t].y, pk[t].z, pk[t].w};
-    float f[8];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      if (BF16) {
-        f[2 * h] = __uint_as_float(wd[h] << 16);
-        f[2 * h + 1] = __uint_as_float(wd[h] & 0xFFFF0000u);
-      } else {
-        f[2 * h] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] & 0xFFFFu));
-        f[2 * h + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[h] >> 16));
-      }
+// 16-bit, on the matrix cores (v_mfma_f32_32x32x16_{bf16,f16}).  A pass
+// multiplies a library tile by up to 16 scenes, so a library with up to 16
+// scenes is streamed from HBM once.  The 16-bit product needs 16-bit scene
+// values; to keep the error that of the stored library alone, each scaled
+// scene value v = Z_j 2^(e_j + f_s) is split into hi = RN16(v) and
+// lo = RN16(v - hi) (v = hi + lo to about u^2), and the 32 columns of the
+// B operand are the 16 scenes' hi parts followed by their lo parts; the two
+// halves are added after the products.  f_s is the per-scene power of two
+// that puts the scene's largest scaled value in [2^14, 2^15) (so FP16 neither
+// overflows nor loses the faint end to underflow).
+//
+// The split scene values are packed once per run into the B operand of every
+// (scene group, 8-column group): 32 columns x 16 bytes, 512 bytes per group,
+// all of it small enough to stay in L2/MALL.  Workgroup = 4 waves = 256 image
+// rows, wave = 64 rows (two 32-row tiles); library fragments (8 columns of one
+// row = 16 bytes = the MFMA A fragment) stream from HBM straight into
+// registers and scene fragments from the packed operand, a block of 4 K steps
+// ahead, with no LDS and no barriers.
+
+// f_s of every scene slot (one workgroup per slot).
+__global__ __launch_bounds__(256) void grouped_scene_exp_kernel(const GScene* __restrict__ slots,
+                                                                int32_t* __restrict__ fexp) {
+  __shared__ double red[256];
+  const GScene sc = slots[blockIdx.x];
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < sc.ncols; j += 256)
+    m = fmax(m, ldexp((double)fabsf(sc.z[j]), sc.exps[j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int f = 0;
+    if (red[0] > 0.0) {
+      int E;
+      (void)frexp(red[0], &E);
+      f = 15 - E;
     }
+    fexp[blockIdx.x] = f;
+  }
+}
+
+template <bool BF16>
+__device__ __forceinline__ uint16_t g16_round(float x) {
+  if constexpr (BF16) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // finite: round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+  } else {
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
+  }
+}
+
+template <bool BF16>
+__device__ __forceinline__ float g16_value(uint16_t h) {
+  if constexpr (BF16)
+    return __uint_as_float((uint32_t)h << 16);
+  else
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// Packed operand: thread = (scene group, 8-column group g); writes the 32
+// columns (hi parts of scenes 0..15, then lo parts) of group g, 16 bytes each.
+template <bool BF16>
+__global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restrict__ packs,
+                                                           const float* const* __restrict__ scenes,
+                                                           const int32_t* __restrict__ fexp,
+                                                           u32x4* __restrict__ bpk) {
+  const GPack pk = packs[blockIdx.x];
+  for (int64_t g = threadIdx.x; g < pk.ngroups; g += 256) {
+    u32x4* dst = bpk + pk.bpk + g * 32;
+    for (int r = 0; r < kGrpScenes16; ++r) {
+      uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
+      if (r < pk.nscenes) {
+        const float* z = scenes[pk.slot0 + r];
+        const int f = fexp[pk.slot0 + r];
 #pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) {
-      if (r >= nscenes) break;
-      const float* z = &zs[r][(g + t) * 8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) inner[r] = fmaf(f[u], z[u], inner[r]);
+        for (int u = 0; u < 8; ++u) {
+          const int64_t j = g * 8 + u;
+          float v = 0.0f;
+          if (j < pk.ncols) v = ldexpf(z[j], pk.exps[j] + f);
+          const uint16_t h = g16_round<BF16>(v);
+          const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
+          hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
+          lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
+        }
+      }
+      dst[r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
+      dst[16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
     }
   }
-#pragma unroll
-  for (int r = 0; r < kGrpScenes; ++r) acc[r] += inner[r];
+}
+
+template <bool BF16>
+__device__ __forceinline__ f32x16 g16_mfma(const u32x4 a, const u32x4 b, const f32x16 c) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+  if constexpr (BF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
 template <bool BF16>
 __global__ __launch_bounds__(kGrpThreads) void grouped_h16_kernel(
-    const GItem* __restrict__ items, int64_t nitems, const float* const* __restrict__ scenes,
-    float* __restrict__ part) {
-  __shared__ float zs[kGrpScenes][kGrpMaxChunkGroups * 8];
+    const GItem* __restrict__ items, int64_t nitems, const u32x4* __restrict__ bpk,
+    const int32_t* __restrict__ fexp, float* __restrict__ part) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5;  // which group of a 16-wide K step this lane feeds
   const u32x4 z4 = {0u, 0u, 0u, 0u};
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem w = items[it];
     const u32x4* Mp = reinterpret_cast<const u32x4*>(w.A);
-    const int64_t ng = w.j1 - w.j0;
-    const int64_t i = w.row0 + threadIdx.x;
-    const bool row_ok = i < w.M;
-    auto load = [&](int64_t g, u32x4 (&pk)[8]) {
+    const int ng = (int)(w.j1 - w.j0);  // even (chunks and libraries are whole 8-group blocks)
+    // this lane's library rows; rows past M read row M-1 (never stored)
+    int64_t r0 = w.row0 + 64 * wave + (lane & 31), r1 = r0 + 32;
+    if (r0 > w.M - 1) r0 = w.M - 1;
+    if (r1 > w.M - 1) r1 = w.M - 1;
+    const u32x4* A0 = Mp + w.j0 * w.M + r0;
+    const u32x4* A1 = Mp + w.j0 * w.M + r1;
+    // scene operand of this item's chunk: group g at Bg[g * 32 + column]
+    const u32x4* Bg = bpk + w.bpk + w.j0 * 32 + (lane & 31);
+    auto load4 = [&](int s0, u32x4 (&a)[4][3]) {  // K steps s0 .. s0+3 (groups 2s + half)
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        pk[t] = (row_ok && g + t < ng) ? __builtin_nontemporal_load(Mp + (w.j0 + g + t) * w.M + i) : z4;
+      for (int q = 0; q < 4; ++q) {
+        const int g = 2 * (s0 + q) + half;
+        const bool ok = g < ng;
+        a[q][0] = ok ? __builtin_nontemporal_load(A0 + (int64_t)g * w.M) : z4;
+        a[q][1] = ok ? __builtin_nontemporal_load(A1 + (int64_t)g * w.M) : z4;
+        a[q][2] = ok ? Bg[g * 32] : z4;
+      }
     };
-    u32x4 pa[8], pb[8];
-    load(0, pa);
-    __syncthreads();  // the previous item is done with zs
-    for (int64_t t = threadIdx.x; t < ng * 8 * kGrpScenes; t += kGrpThreads) {
-      const int r = (int)(t / (ng * 8));
-      const int64_t q = t - (int64_t)r * ng * 8;
-      const int64_t j = w.j0 * 8 + q;
-      float v = 0.0f;
-      if (r < w.nscenes && j < w.ncols) v = ldexpf(scenes[w.scene0 + r][j], w.exps[j]);
-      zs[r][q] = v;
-    }
-    __syncthreads();
-    float acc[kGrpScenes];
+    u32x4 pa[4][3], pb[4][3];
+    load4(0, pa);
+    const f32x16 zero16 = {};
+    f32x16 acc[2] = {zero16, zero16};
+    const int nsteps = ng / 2;
+    auto mult4 = [&](int s0, const u32x4 (&a)[4][3]) {
 #pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) acc[r] = 0.0f;
-    if (row_ok) {
-      for (int64_t g = 0; g < ng; g += 16) {
-        load(g + 8, pb);
-        grouped_h16_batch<BF16>(pa, g, ng, w.nscenes, zs, acc);
-        if (g + 8 >= ng) break;
-        load(g + 16, pa);
-        grouped_h16_batch<BF16>(pb, g + 8, ng, w.nscenes, zs, acc);
+      for (int q = 0; q < 4; ++q) {
+        if (2 * (s0 + q) >= ng) break;  // uniform
+        acc[0] = g16_mfma<BF16>(a[q][0], a[q][2], acc[0]);
+        acc[1] = g16_mfma<BF16>(a[q][1], a[q][2], acc[1]);
+      }
+    };
+    for (int s0 = 0; s0 < nsteps; s0 += 8) {
+      load4(s0 + 4, pb);
+      mult4(s0, pa);
+      if (s0 + 4 >= nsteps) break;
+      load4(s0 + 8, pa);
+      mult4(s0 + 4, pb);
+    }
+    // column n = lane % 32 holds scene n's hi part (n < 16) or scene n-16's lo part
+    const int n = lane & 31;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float v = acc[t][q] + __shfl_xor(acc[t][q], 16, 64);
+        if (n < w.nscenes) {
+          const int rl = 64 * wave + 32 * t + 8 * (q >> 2) + 4 * half + (q & 3);
+          part[w.part + (int64_t)n * kGrpThreads + rl] = ldexpf(v, -fexp[w.scene0 + n]);
+        }
       }
     }
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) part[w.part + r * kGrpThreads + threadIdx.x] = acc[r];
   }
 }
 
@@ -265,7 +369,7 @@ struct psflib_grouped {
   int device;
   hipGraph_t graph;
   hipGraphExec_t exec;
-  void* dev;        // items | reductions | scene table | image table | partials
+  void* dev;        // items | reductions | scene/image tables | slots | packed operands | partials
   int64_t chunk;    // chosen chunk length (columns, or 8-column groups for 16-bit)
   float ms_tuned;   // time of the chosen shape during autotuning (0 if not tuned)
 };
@@ -283,11 +387,15 @@ struct Plan {
   std::vector<psflib::GReduce> reds;
   std::vector<const float*> scenes;
   std::vector<float*> images;
+  std::vector<psflib::GScene> slots;  // per scene slot: values, exponents (16-bit scaling)
+  std::vector<psflib::GPack> packs;   // 16-bit: per scene group, its packed operand
   int64_t part_floats = 0;
+  int64_t bpk_vecs = 0;               // 16-byte entries of the packed operands
 };
 
 // Items for a given chunk length.  Scenes are grouped by library (kept in the
-// caller's order inside a library) and cut into groups of kGrpScenes.
+// caller's order inside a library) and cut into groups of kGrpScenes (FP32)
+// or kGrpScenes16 (16-bit).
 Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib_of_scene,
                const float* const* scenes, float* const* images, int B, int64_t chunk) {
   Plan p;
@@ -301,12 +409,20 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
     const int64_t units = f32 ? li.ncols : li.ncols_pad / 8;
     const int64_t nchunks = (units + chunk - 1) / chunk;
     const int64_t nrb = (li.M + rows_per - 1) / rows_per;
-    for (size_t g0 = 0; g0 < sc.size(); g0 += psflib::kGrpScenes) {
-      const int ns = (int)std::min<size_t>(psflib::kGrpScenes, sc.size() - g0);
+    const size_t spg = f32 ? psflib::kGrpScenes : psflib::kGrpScenes16;
+    for (size_t g0 = 0; g0 < sc.size(); g0 += spg) {
+      const int ns = (int)std::min<size_t>(spg, sc.size() - g0);
       const int32_t scene0 = (int32_t)p.scenes.size();
       for (int r = 0; r < ns; ++r) {
         p.scenes.push_back(scenes[sc[g0 + r]]);
         p.images.push_back(images[sc[g0 + r]]);
+        p.slots.push_back(psflib::GScene{scenes[sc[g0 + r]], li.exps, li.ncols});
+      }
+      int64_t bpk = 0;
+      if (!f32) {
+        bpk = p.bpk_vecs;
+        p.packs.push_back(psflib::GPack{bpk, li.ncols, units, li.exps, scene0, ns});
+        p.bpk_vecs += units * 32;
       }
       for (int64_t rb = 0; rb < nrb; ++rb) {
         psflib::GReduce rd;
@@ -314,7 +430,7 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
         rd.row0 = rb * rows_per;
         rd.rows = rows_per;
         rd.part0 = p.part_floats;
-        rd.stride = (int64_t)psflib::kGrpScenes * rows_per;
+        rd.stride = (int64_t)spg * rows_per;
         rd.nchunks = (int32_t)nchunks;
         rd.scene0 = scene0;
         rd.nscenes = ns;
@@ -332,6 +448,7 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
           it.scene0 = scene0;
           it.nscenes = ns;
           it.part = p.part_floats;
+          it.bpk = bpk;
           p.part_floats += rd.stride;
           p.items.push_back(it);
         }
@@ -359,7 +476,11 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   const size_t o_reds = align256(o_items + p.items.size() * sizeof(GItem));
   const size_t o_sc = align256(o_reds + p.reds.size() * sizeof(GReduce));
   const size_t o_im = align256(o_sc + p.scenes.size() * sizeof(void*));
-  const size_t o_part = align256(o_im + p.images.size() * sizeof(void*));
+  const size_t o_slots = align256(o_im + p.images.size() * sizeof(void*));
+  const size_t o_fexp = align256(o_slots + p.slots.size() * sizeof(GScene));
+  const size_t o_packs = align256(o_fexp + p.slots.size() * sizeof(int32_t));
+  const size_t o_bpk = align256(o_packs + p.packs.size() * sizeof(GPack));
+  const size_t o_part = align256(o_bpk + (size_t)p.bpk_vecs * 16);
   const size_t total = align256(o_part + (size_t)p.part_floats * 4);
   if (g->exec) { (void)hipGraphExecDestroy(g->exec); g->exec = nullptr; }
   if (g->graph) { (void)hipGraphDestroy(g->graph); g->graph = nullptr; }
@@ -379,11 +500,21 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
     if (e != hipSuccess) return e;
     e = hipMemcpy(d + o_im, p.images.data(), p.images.size() * sizeof(void*), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
+    e = hipMemcpy(d + o_slots, p.slots.data(), p.slots.size() * sizeof(GScene), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    if (!p.packs.empty()) {
+      e = hipMemcpy(d + o_packs, p.packs.data(), p.packs.size() * sizeof(GPack), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return e;
+    }
   }
   const GItem* items = reinterpret_cast<const GItem*>(d + o_items);
   const GReduce* reds = reinterpret_cast<const GReduce*>(d + o_reds);
   const float* const* sc = reinterpret_cast<const float* const*>(d + o_sc);
   float* const* im = reinterpret_cast<float* const*>(d + o_im);
+  const GScene* slots = reinterpret_cast<const GScene*>(d + o_slots);
+  int32_t* fexp = reinterpret_cast<int32_t*>(d + o_fexp);
+  const GPack* packs = reinterpret_cast<const GPack*>(d + o_packs);
+  u32x4* bpk = reinterpret_cast<u32x4*>(d + o_bpk);
   float* part = reinterpret_cast<float*>(d + o_part);
   const int64_t nitems = (int64_t)p.items.size();
   int cus = 256;
@@ -399,10 +530,17 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
     if (nitems > 0) {
       if (g->storage == PSFLIB_FP32)
         grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems, sc, part);
-      else if (g->storage == PSFLIB_BF16_POW2)
-        grouped_h16_kernel<true><<<grid, kGrpThreads, 0, cap>>>(items, nitems, sc, part);
-      else
-        grouped_h16_kernel<false><<<grid, kGrpThreads, 0, cap>>>(items, nitems, sc, part);
+      else {
+        grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 256, 0, cap>>>(slots, fexp);
+        const unsigned np = (unsigned)p.packs.size();
+        if (g->storage == PSFLIB_BF16_POW2) {
+          grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
+          grouped_h16_kernel<true><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
+        } else {
+          grouped_pack_kernel<false><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
+          grouped_h16_kernel<false><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
+        }
+      }
       grouped_reduce_kernel<<<(unsigned)p.reds.size(), 256, 0, cap>>>(reds, part, im);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
@@ -467,13 +605,13 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
   // Candidate chunk lengths: columns (FP32) or 8-column groups (16-bit).
   const bool f32 = storage == PSFLIB_FP32;
   std::vector<int64_t> cands = f32 ? std::vector<int64_t>{256, 512, 1024}
-                                   : std::vector<int64_t>{32, 64, 128};
+                                   : std::vector<int64_t>{128, 256, 512, 1024};
   std::string sig = std::to_string(storage) + ":";
   for (int b = 0; b < B; ++b) {
     const LibInfo& li = libs[h_lib_of_scene[b]];
     sig += std::to_string(li.M) + "x" + std::to_string(li.ncols) + ",";
   }
-  int64_t chosen = f32 ? 512 : 64;
+  int64_t chosen = f32 ? 512 : 256;
   bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
