@@ -230,13 +230,15 @@ __device__ __forceinline__ float g16_value(uint16_t h) {
 
 // Packed operand: thread = (scene group, 8-column group g); writes the 32
 // columns (hi parts of scenes 0..15, then lo parts) of group g, 16 bytes each.
+// Grid: one row of workgroups per scene group, groups strided across the row.
 template <bool BF16>
 __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restrict__ packs,
                                                            const float* const* __restrict__ scenes,
                                                            const int32_t* __restrict__ fexp,
                                                            u32x4* __restrict__ bpk) {
   const GPack pk = packs[blockIdx.x];
-  for (int64_t g = threadIdx.x; g < pk.ngroups; g += 256) {
+  for (int64_t g = (int64_t)blockIdx.y * 256 + threadIdx.x; g < pk.ngroups;
+       g += (int64_t)gridDim.y * 256) {
     u32x4* dst = bpk + pk.bpk + g * 32;
     for (int r = 0; r < kGrpScenes16; ++r) {
       uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
@@ -532,7 +534,7 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
         grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems, sc, part);
       else {
         grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 256, 0, cap>>>(slots, fexp);
-        const unsigned np = (unsigned)p.packs.size();
+        const dim3 np((unsigned)p.packs.size(), 16);  // 16 blocks of 256 groups per scene group
         if (g->storage == PSFLIB_BF16_POW2) {
           grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
           grouped_h16_kernel<true><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
