@@ -16,10 +16,11 @@
 // fill the GPU, K is split across workgroups and a second kernel adds the
 // slices in a fixed order.
 //
-// FP32: a workgroup of 4 waves computes a 128 (image rows) x 64 (scenes) tile
-// from K tiles of 16 double-buffered through LDS; accumulation is blocked in
-// three levels (one K tile, 32 K tiles, the rest) so float32 rounding chains
-// stay short.
+// FP32: each wave computes 64 image rows x 64 scenes (32 for batches of at
+// most 32) on its own, streaming library rows from HBM straight into
+// registers and pre-arranged scene fragments from L2, four groups of 8
+// columns ahead; accumulation is blocked in two levels so float32 rounding
+// chains stay short.
 //
 // 16-bit: a workgroup of 4 waves computes a 256 x 128 tile; each wave owns 64
 // image rows and all 128 scenes (2 x 4 accumulators of 32 x 32).  K advances
@@ -37,10 +38,7 @@
 namespace psflib {
 
 constexpr int kGemmThreads = 256;
-constexpr int kGM = 128;  // FP32: image rows per workgroup tile
-constexpr int kGN = 64;   // FP32: scenes per workgroup tile
-constexpr int kGK32 = 16; // FP32: K per tile
-constexpr int kMidTiles = 32;
+constexpr int kGM = 256;  // FP32: image rows per workgroup (64 per wave)
 constexpr int kHM = 256;  // 16-bit: image rows per workgroup tile (64 per wave)
 constexpr int kHN = 128;  // 16-bit: scenes per workgroup tile
 constexpr int kHG = 4;    // 16-bit: 8-column groups per K stage (32 columns)
@@ -85,105 +83,171 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t T) {
 }
 
 // ------------------------------------------------------------- FP32 -------
-__global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(const float* __restrict__ A,
-                                                                const float* __restrict__ Z,
-                                                                float* __restrict__ out,
-                                                                int64_t M, int64_t K, int64_t B,
-                                                                int64_t mblocks, int64_t nblocks,
-                                                                int64_t splits,
-                                                                int64_t ktiles_per_split) {
-  __shared__ float As[2][kGK32][kGM];
-  __shared__ float Bs[2][kGK32][kGN + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+// Scenes are first copied into a fragment-major form Zp: for each 8-column
+// group g and block of 32 scenes sb, 64 lanes x 4 floats (1 KiB), lane
+// l = 32h + n holding Z[32 sb + n][8g + 4h .. 8g + 4h + 3] (zeros past the
+// batch and past K).  One 16-byte load per lane is then the scene operand
+// of four MFMA steps.
+constexpr int kF32Ring = 4;    // 8-column groups in flight per wave
+constexpr int kF32Block = 16;  // groups per inner accumulation block (a multiple of kF32Ring)
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void pack_f32_scenes_kernel(const float* __restrict__ Z,
+                                                              int64_t K, int64_t B, int64_t ngroups,
+                                                              int64_t SB, f32x4* __restrict__ Zp) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= ngroups * SB * 64) return;
+  const int l = (int)(t & 63);
+  const int64_t sb = (t >> 6) % SB, g = (t >> 6) / SB;
+  const int64_t n = 32 * sb + (l & 31), k = 8 * g + 4 * (l >> 5);
+  f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (n < B) {
+    const float* src = Z + n * K + k;
+    if (VEC && k + 4 <= K) {
+      v = *reinterpret_cast<const f32x4*>(src);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (k + c < K) v[c] = src[c];
+    }
+  }
+  Zp[t] = v;
+}
+
+// A workgroup is 4 independent waves, each computing 64 image rows x 32*NB
+// scenes with v_mfma_f32_32x32x2f32.  Nothing is shared between waves, so
+// there is no LDS and no barrier: each wave streams its library rows straight
+// from HBM into registers and its scene fragments from L2, kF32Ring groups
+// of 8 columns ahead of use.
+//
+// Operand mapping for group g and MFMA step s (0..3): lane (i = l % 32,
+// h = l / 32) supplies column k = 8g + 4h + s for the two k-slots of the
+// MFMA, with A rows m0 + 2i (MFMA t = 0) and m0 + 2i + 1 (t = 1) read as one
+// 8-byte load, and the scene value of the same column from its Zp fragment.
+// Output row i of MFMA t is image row m0 + 2i + t.
+//
+// All loads are buffer loads whose descriptor covers only live data: columns
+// past K and groups past the slice read as zero, so the loop runs whole
+// accumulation blocks with no bounds tests.  Rows past the image read the
+// next column (finite values, never stored) or zero.
+//
+// Accumulation is blocked in two levels (kF32Block groups, then the slice)
+// so float32 rounding chains stay short; split-K slices are added by
+// reduce_splits_kernel in a fixed order.
+template <int NB, bool VEC>
+__global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
+    const float* __restrict__ A, const f32x4* __restrict__ Zp, float* __restrict__ out, int64_t M,
+    int64_t K, int64_t B, int64_t SB, int64_t mblocks, int64_t nblocks, int64_t splits,
+    int64_t gper) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t tile = xcd_tile(blockIdx.x, mblocks * nblocks * splits);
   const int64_t nb = tile % nblocks, mb = (tile / nblocks) % mblocks, sp = tile / (nblocks * mblocks);
-  const int64_t m0 = mb * kGM;
-  const int64_t n0 = nb * kGN;
-  const int64_t ktiles = (K + kGK32 - 1) / kGK32;
-  const int64_t kt0 = sp * ktiles_per_split;
-  int64_t kt1 = kt0 + ktiles_per_split;
-  if (kt1 > ktiles) kt1 = ktiles;
-  float* dst = out + sp * B * M;
-  const bool vecA = (M % 4) == 0, vecB = (K % 4) == 0;
+  const int64_t m0 = mb * kGM + 64 * wave;
+  if (m0 >= M) return;  // no barriers: a wave past the image leaves at once
+  // group indices fit 32 bits (K < 2^31); 32-bit scalar compares are native
+  const int ngroups = (int)((K + 7) / 8);
+  const int g0 = (int)(sp * gper);
+  const int g1 = (g0 + (int)gper < ngroups) ? g0 + (int)gper : ngroups;
+  const uint32_t colbytes = (uint32_t)(M * 4);
+  const int i = lane & 31, h = lane >> 5;
+  uint32_t voff[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) voff[s] = (uint32_t)(((4 * h + s) * M + m0 + 2 * i) * 4);
+  const uint32_t zoff = (uint32_t)((nb * NB * 64 + lane) * 16);
 
-  f32x4 ra[2], rbv;
-  auto load_tile = [&](int64_t kt) {
-    const int64_t k0 = kt * kGK32;
+  f32x2 ra[kF32Ring][4];
+  f32x4 rb[kF32Ring][NB];
+  auto issue = [&](int g, int slot) {
+    const bool live = g < g1;
+    const int gc = live ? g : g1 - 1;
+    // a whole group spans 8 columns (8 M floats < 2^31 bytes); the last may be partial
+    const int left = (int)(K - 8 * (int64_t)gc);
+    const int abytes = !live ? 0 : left >= 8 ? 0x7FFFFFFF : (int)((uint32_t)left * colbytes);
+    const __amdgpu_buffer_rsrc_t ra_d = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A + 8 * (int64_t)gc * M), (short)0, abytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb_d = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Zp + (int64_t)gc * SB * 64), (short)0, live ? (int)(SB * 1024) : 0, 0x00020000);
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = tid + kGemmThreads * r;
-      const int kk = idx >> 5, m4 = (idx & 31) * 4;
-      const int64_t k = k0 + kk, m = m0 + m4;
-      if (k < K && vecA && m + 4 <= M) {
-        ra[r] = *reinterpret_cast<const f32x4*>(A + k * M + m);  // cached: re-read per scene block
+    for (int s = 0; s < 4; ++s) {
+      if (VEC) {
+        ra[slot][s] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra_d, voff[s], 0, 0));
       } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) ra[r][e] = (k < K && m + e < M) ? A[k * M + m + e] : 0.0f;
+        ra[slot][s][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s], 0, 0));
+        ra[slot][s][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s] + 4, 0, 0));
       }
     }
-    {
-      const int nn = tid >> 2, k4 = (tid & 3) * 4;
-      const int64_t n = n0 + nn, k = k0 + k4;
-      if (n < B && vecB && k + 4 <= K) {
-        rbv = *reinterpret_cast<const f32x4*>(Z + n * K + k);
-      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rbv[e] = (n < B && k + e < K) ? Z[n * K + k + e] : 0.0f;
-      }
-    }
-  };
-  auto store_tile = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int idx = tid + kGemmThreads * r;
-      const int kk = idx >> 5, m4 = (idx & 31) * 4;
-      *reinterpret_cast<f32x4*>(&As[buf][kk][m4]) = ra[r];
-    }
-    const int nn = tid >> 2, k4 = (tid & 3) * 4;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) Bs[buf][k4 + e][nn] = rbv[e];
+    for (int q = 0; q < NB; ++q)
+      rb[slot][q] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb_d, zoff + 1024 * q, 0, 0));
   };
 
   const f32x16 zero16 = {};
-  f32x16 acc_out[2] = {zero16, zero16}, acc_mid[2] = {zero16, zero16};
-  if (kt0 < kt1) {
-    load_tile(kt0);
-    store_tile(0);
-  }
-  __syncthreads();
-  int mid_count = 0;
-  for (int64_t kt = kt0; kt < kt1; ++kt) {
-    const int cur = (int)((kt - kt0) & 1);
-    if (kt + 1 < kt1) load_tile(kt + 1);
-    f32x16 acc_t[2] = {zero16, zero16};
-#pragma unroll
-    for (int kk = 0; kk < kGK32 / 2; ++kk) {
-      const int krow = 2 * kk + (lane >> 5);
-      const float b = Bs[cur][krow][32 * wn + (lane & 31)];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const float a = As[cur][krow][64 * wm + 32 * t + (lane & 31)];
-        acc_t[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc_t[t], 0, 0, 0);
-      }
-    }
-    acc_mid[0] += acc_t[0];
-    acc_mid[1] += acc_t[1];
-    if (++mid_count == kMidTiles) {
-      acc_out[0] += acc_mid[0];
-      acc_out[1] += acc_mid[1];
-      acc_mid[0] = zero16;
-      acc_mid[1] = zero16;
-      mid_count = 0;
-    }
-    if (kt + 1 < kt1) store_tile(cur ^ 1);
-    __syncthreads();
-  }
-  acc_out[0] += acc_mid[0];
-  acc_out[1] += acc_mid[1];
+  f32x16 acc[2][NB], tot[2][NB];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
-    store_acc(acc_out[t], dst, M, B, m0 + 64 * wm + 32 * t, n0 + 32 * wn, lane, nullptr, false);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) tot[t][q] = zero16;
+
+  const int nblk = g1 > g0 ? (g1 - g0 + kF32Block - 1) / kF32Block : 0;
+  if (nblk > 0) {
+#pragma unroll
+    for (int r = 0; r < kF32Ring; ++r) issue(g0 + r, r);
+  }
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int gb = g0 + blk * kF32Block;
+#pragma unroll
+    for (int j = 0; j < kF32Block; ++j) {
+      const int slot = j % kF32Ring;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+            acc[t][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[slot][s][t], rb[slot][q][s],
+                                                            (j == 0 && s == 0) ? zero16 : acc[t][q],
+                                                            0, 0, 0);
+      issue(gb + j + kF32Ring, slot);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) tot[t][q] += acc[t][q];
+  }
+
+  // lane holds scene column l % 32 and MFMA rows 8(r/4) + 4h + r%4, i.e. image
+  // rows m0 + 16(r/4) + 8h + 2(r%4) + t: 8 consecutive rows per r/4
+  float* dst = out + sp * B * M;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int64_t n = (nb * NB + q) * 32 + i;
+    if (n >= B) continue;
+    float* row = dst + n * M;
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int64_t m = m0 + 16 * r4 + 8 * h;
+      f32x4 lo, hi;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        lo[2 * e] = tot[0][q][4 * r4 + e];
+        lo[2 * e + 1] = tot[1][q][4 * r4 + e];
+        hi[2 * e] = tot[0][q][4 * r4 + 2 + e];
+        hi[2 * e + 1] = tot[1][q][4 * r4 + 2 + e];
+      }
+      if ((M % 4) == 0 && m + 8 <= M) {
+        *reinterpret_cast<f32x4*>(row + m) = lo;
+        *reinterpret_cast<f32x4*>(row + m + 4) = hi;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (m + e < M) row[m + e] = lo[e];
+          if (m + 4 + e < M) row[m + 4 + e] = hi[e];
+        }
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------- 16-bit -----
@@ -443,24 +507,34 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const float* __restr
 
 // ------------------------------------------------------------ launch ------
 struct GemmPlan {
-  int64_t mblocks, nblocks, kunits, splits, per;  // kunits: K tiles (FP32) or K stages (16-bit)
+  int64_t mblocks, nblocks, kunits, splits, per;  // kunits: 8-column groups (FP32) or K stages (16-bit)
 };
+
+// FP32 scene blocks of 32 per workgroup tile: 1 for batches of at most 32
+static int f32_nb(int64_t bc) { return bc <= 32 ? 1 : 2; }
+
+// scene blocks of 32 in the FP32 fragment-major scene copy (whole tiles)
+static int64_t f32_scene_blocks(int64_t bc) {
+  const int nb = f32_nb(bc);
+  return (bc + 32 * nb - 1) / (32 * nb) * nb;
+}
 
 static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int64_t bc) {
   GemmPlan p;
   const bool f32 = storage == PSFLIB_FP32;
-  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? kGN : kHN;
+  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? 32 * f32_nb(bc) : kHN;
   p.mblocks = (M + tm - 1) / tm;
   p.nblocks = (bc + tn - 1) / tn;
-  p.kunits = f32 ? (ncols + kGK32 - 1) / kGK32 : (ncols_pad / 8) / kHG;
+  p.kunits = f32 ? (ncols + 7) / 8 : (ncols_pad / 8) / kHG;
   // about two workgroups per CU, split K if the tile grid is smaller
-  const int64_t want = f32 ? 1024 : 512;
+  const int64_t want = 512;
   const int64_t tiles = p.mblocks * p.nblocks;
   int64_t s = (want + tiles - 1) / tiles;
   if (s > 16) s = 16;
   if (s > p.kunits) s = p.kunits;
   if (s < 1) s = 1;
   p.per = (p.kunits + s - 1) / s;
+  if (f32) p.per = (p.per + kF32Block - 1) / kF32Block * kF32Block;  // whole accumulation blocks
   p.splits = (p.kunits + p.per - 1) / p.per;  // no empty slice
   if (p.splits < 1) p.splits = 1;
   return p;
@@ -487,6 +561,8 @@ size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncol
   if (storage != PSFLIB_FP32) {
     bytes += ((size_t)padded_batch(bc) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;  // Zg
     bytes += ((size_t)bc * 4 + 255) & ~(size_t)255;                                    // fexp
+  } else {
+    bytes += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bc) * 1024;          // Zp
   }
   size_t part = split_partial_bytes(storage, M, ncols, ncols_pad, bc);
   const int64_t rem = B % bc;
@@ -506,11 +582,15 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
   int32_t* fexp = nullptr;
   const int64_t bcmax = chunk_of(B);
   size_t off = 0;
+  f32x4* Zp = nullptr;
   if (storage != PSFLIB_FP32) {
     Zg = reinterpret_cast<u32x4*>(sp);
     off += ((size_t)padded_batch(bcmax) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
     fexp = reinterpret_cast<int32_t*>(sp + off);
     off += ((size_t)bcmax * 4 + 255) & ~(size_t)255;
+  } else {
+    Zp = reinterpret_cast<f32x4*>(sp);
+    off += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bcmax) * 1024;
   }
   float* part = reinterpret_cast<float*>(sp + off);
   for (int64_t b0 = 0; b0 < B; b0 += bcmax) {
@@ -525,9 +605,29 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
     const unsigned grid = (unsigned)(p.mblocks * p.nblocks * p.splits);
     float* dst = p.splits > 1 ? part : outc;
     if (storage == PSFLIB_FP32) {
-      gemm_f32_kernel<<<grid, kGemmThreads, 0, s>>>(reinterpret_cast<const float*>(lib), Zc, dst,
-                                                    M, ncols, bc, p.mblocks, p.nblocks, p.splits,
-                                                    p.per);
+      const int64_t ngroups = (ncols + 7) / 8, SB = f32_scene_blocks(bc);
+      const bool zvec = (ncols % 4) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
+      const unsigned pgrid = (unsigned)((ngroups * SB * 64 + 255) / 256);
+      if (zvec)
+        pack_f32_scenes_kernel<true><<<pgrid, 256, 0, s>>>(Zc, ncols, bc, ngroups, SB, Zp);
+      else
+        pack_f32_scenes_kernel<false><<<pgrid, 256, 0, s>>>(Zc, ncols, bc, ngroups, SB, Zp);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const float* Af = reinterpret_cast<const float*>(lib);
+      const bool avec = (M % 2) == 0;
+      if (f32_nb(bc) == 1 && avec)
+        gemm_f32_kernel<1, true><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
+                                                                p.mblocks, p.nblocks, p.splits, p.per);
+      else if (f32_nb(bc) == 1)
+        gemm_f32_kernel<1, false><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
+                                                                 p.mblocks, p.nblocks, p.splits, p.per);
+      else if (avec)
+        gemm_f32_kernel<2, true><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
+                                                                p.mblocks, p.nblocks, p.splits, p.per);
+      else
+        gemm_f32_kernel<2, false><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
+                                                                 p.mblocks, p.nblocks, p.splits, p.per);
       e = hipGetLastError();
     } else {
       const bool bf = storage == PSFLIB_BF16_POW2;

@@ -120,3 +120,36 @@ def test_c2_16bit_sampled(torch, c2, sample, fmt):
         err = np.max(np.abs(outb - refb), axis=1) / np.max(np.abs(refb), axis=1)
         assert np.max(err) <= 2 * u, (B, np.max(err))
     lib.close()
+
+
+@pytest.fixture(scope="module")
+def dense(c2):
+    """Dense scenes over every column of the full library, with expected
+    images from the whole oracle library (built in column chunks, float64),
+    so every term of every accumulation chain is exercised."""
+    N = c2["N"]
+    K = N * N
+    Zb = np.random.default_rng(31).random((256, K)).astype(np.float32)
+    ref = np.zeros((256, c2["n"] ** 2))
+    for c0 in range(0, K, 2048):
+        cols = np.arange(c0, min(K, c0 + 2048))
+        A = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols)
+        ref += Zb[:, cols].astype(np.float64) @ A.T
+    return Zb, ref
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+def test_c2_batched_dense(torch, c2, dense, storage):
+    Zb, ref = dense
+    lib = _build(torch, c2, storage)
+    for B in (20, 64, 256):
+        out = lib.apply_batched(torch.from_numpy(Zb[:B]).cuda()).cpu().numpy().astype(np.float64)
+        r = ref[:B]
+        if storage == "fp32":
+            pos = r > 0
+            assert np.all(out[~pos] == 0)
+            assert np.max(np.abs(out[pos] - r[pos]) / r[pos]) <= FP32_REL, B
+        else:
+            err = np.max(np.abs(out - r), axis=1) / np.max(np.abs(r), axis=1)
+            assert np.max(err) <= 2 * U16[storage], (B, np.max(err))
+    lib.close()
