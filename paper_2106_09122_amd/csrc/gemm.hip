@@ -134,7 +134,10 @@ __global__ __launch_bounds__(256) void pack_f32_scenes_kernel(const float* __res
 // Accumulation is blocked in two levels (kF32Block groups, then the slice)
 // so float32 rounding chains stay short; split-K slices are added by
 // reduce_splits_kernel in a fixed order.
-template <int NB, bool VEC>
+//
+// NT: library loads carry the non-temporal hint, for grids with one scene
+// tile, where no other workgroup reads the same library rows.
+template <int NB, bool VEC, bool NT>
 __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
     const float* __restrict__ A, const f32x4* __restrict__ Zp, float* __restrict__ out, int64_t M,
     int64_t K, int64_t B, int64_t SB, int64_t mblocks, int64_t nblocks, int64_t splits,
@@ -157,6 +160,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
   for (int s = 0; s < 4; ++s) voff[s] = (uint32_t)(((4 * h + s) * M + m0 + 2 * i) * 4);
   const uint32_t zoff = (uint32_t)((nb * NB * 64 + lane) * 16);
 
+  constexpr int kAux = NT ? 2 : 0;  // cache-policy bits of the library loads
   f32x2 ra[kF32Ring][4];
   f32x4 rb[kF32Ring][NB];
   auto issue = [&](int g, int slot) {
@@ -172,10 +176,10 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       if (VEC) {
-        ra[slot][s] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra_d, voff[s], 0, 0));
+        ra[slot][s] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra_d, voff[s], 0, kAux));
       } else {
-        ra[slot][s][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s], 0, 0));
-        ra[slot][s][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s] + 4, 0, 0));
+        ra[slot][s][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s], 0, kAux));
+        ra[slot][s][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra_d, voff[s] + 4, 0, kAux));
       }
     }
 #pragma unroll
@@ -540,6 +544,31 @@ static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_p
   return p;
 }
 
+template <int NB, bool VEC, bool NT>
+static hipError_t launch_gemm_f32_t(unsigned grid, const float* A, const f32x4* Zp, float* dst,
+                                    int64_t M, int64_t K, int64_t B, int64_t SB, const GemmPlan& p,
+                                    hipStream_t s) {
+  gemm_f32_kernel<NB, VEC, NT><<<grid, kGemmThreads, 0, s>>>(A, Zp, dst, M, K, B, SB, p.mblocks,
+                                                             p.nblocks, p.splits, p.per);
+  return hipGetLastError();
+}
+
+// variant bits: 4 = two scene blocks per wave, 2 = even M (8-byte row pairs), 1 = non-temporal
+static hipError_t launch_gemm_f32(int variant, unsigned grid, const float* A, const f32x4* Zp,
+                                  float* dst, int64_t M, int64_t K, int64_t B, int64_t SB,
+                                  const GemmPlan& p, hipStream_t s) {
+  switch (variant) {
+    case 0: return launch_gemm_f32_t<1, false, false>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 1: return launch_gemm_f32_t<1, false, true>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 2: return launch_gemm_f32_t<1, true, false>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 3: return launch_gemm_f32_t<1, true, true>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 4: return launch_gemm_f32_t<2, false, false>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 5: return launch_gemm_f32_t<2, false, true>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    case 6: return launch_gemm_f32_t<2, true, false>(grid, A, Zp, dst, M, K, B, SB, p, s);
+    default: return launch_gemm_f32_t<2, true, true>(grid, A, Zp, dst, M, K, B, SB, p, s);
+  }
+}
+
 static int64_t chunk_of(int B) { return B < kMaxBatchChunk ? B : kMaxBatchChunk; }
 
 // scenes per group row of the packed 16-bit scene copy (whole scene tiles)
@@ -614,21 +643,9 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
         pack_f32_scenes_kernel<false><<<pgrid, 256, 0, s>>>(Zc, ncols, bc, ngroups, SB, Zp);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      const float* Af = reinterpret_cast<const float*>(lib);
-      const bool avec = (M % 2) == 0;
-      if (f32_nb(bc) == 1 && avec)
-        gemm_f32_kernel<1, true><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
-                                                                p.mblocks, p.nblocks, p.splits, p.per);
-      else if (f32_nb(bc) == 1)
-        gemm_f32_kernel<1, false><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
-                                                                 p.mblocks, p.nblocks, p.splits, p.per);
-      else if (avec)
-        gemm_f32_kernel<2, true><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
-                                                                p.mblocks, p.nblocks, p.splits, p.per);
-      else
-        gemm_f32_kernel<2, false><<<grid, kGemmThreads, 0, s>>>(Af, Zp, dst, M, ncols, bc, SB,
-                                                                 p.mblocks, p.nblocks, p.splits, p.per);
-      e = hipGetLastError();
+      const int variant = (f32_nb(bc) == 2 ? 4 : 0) + ((M % 2) == 0 ? 2 : 0) + (p.nblocks == 1 ? 1 : 0);
+      e = launch_gemm_f32(variant, grid, reinterpret_cast<const float*>(lib), Zp, dst, M, ncols, bc,
+                          SB, p, s);
     } else {
       const bool bf = storage == PSFLIB_BF16_POW2;
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
