@@ -530,8 +530,10 @@ static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_p
   p.mblocks = (M + tm - 1) / tm;
   p.nblocks = (bc + tn - 1) / tn;
   p.kunits = f32 ? (ncols + 7) / 8 : (ncols_pad / 8) / kHG;
-  // about two workgroups per CU, split K if the tile grid is smaller
-  const int64_t want = 512;
+  // split K if the tile grid is smaller than the GPU: FP32 aims at two
+  // workgroups per CU; the 16-bit kernel at one (an extra K slice costs a
+  // partial-image round trip that a second workgroup per CU does not repay)
+  const int64_t want = f32 ? 512 : 256;
   const int64_t tiles = p.mblocks * p.nblocks;
   int64_t s = (want + tiles - 1) / tiles;
   if (s > 16) s = 16;
