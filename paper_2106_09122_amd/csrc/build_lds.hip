@@ -265,6 +265,160 @@ __global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict
   if (lane == 0) tau[j] = tsum;
 }
 
+// PSFs whose bordered pair exceeds the LDS are staged in bands of H rows of
+// the bordered array that overlap by one row: band b holds bordered rows
+// [b (H-1), b (H-1) + H).  The two tap rows of an output pixel, R = r0 + 1
+// and R + 1, both lie in band b when b (H-1) <= R <= b (H-1) + H - 2 (the
+// last band takes every R up to n), so each pixel is produced in exactly one
+// band; pixels whose taps miss the array in the row direction are written as
+// zeros in band 0.  Per band, every lane first forms the pixel's row
+// coordinate (the oracle's float64 operations) to test membership and does
+// the rest of the element's work only for pixels of that band.  Stores go to
+// the same columns as in the unbanded kernel, each element written once.
+template <int E, bool FULL>
+__global__ __launch_bounds__(1024) void build_band_kernel(const float* __restrict__ cube, int K,
+                                                          const ColGeom* __restrict__ geo,
+                                                          const int32_t* __restrict__ order,
+                                                          const int4* __restrict__ items,
+                                                          const int32_t* __restrict__ nitems,
+                                                          int nb, int n, int ls, int H, int nbands,
+                                                          int64_t M, float* __restrict__ A,
+                                                          double* __restrict__ tau) {
+  extern __shared__ float2 P2[];  // H rows of the bordered pair array, row stride ls
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, start = it.y, len = it.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int np = n + 2;
+  if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
+    if (wave >= len) return;
+    const int64_t j = order[start + wave];
+    float* col = A + j * M;
+    for (int a = 0; a < n; ++a)
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        const int b = lane + 64 * v;
+        if (FULL || b < n) __builtin_nontemporal_store(0.0f, col + a * n + b);
+      }
+    if (lane == 0) tau[j] = 0.0;
+    return;
+  }
+  const float* Pk = cube + (int64_t)bkt * M;
+  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+  const bool live = wave < len;
+  int64_t j = 0;
+  ColGeom g;
+  g.ct = 1.0; g.st = 0.0; g.w = 0.0;
+  if (live) {
+    j = order[start + wave];
+    g = geo[j];
+  }
+  float* col = A + j * M;
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  double ctux[E], mstux[E];
+#pragma unroll
+  for (int v = 0; v < E; ++v) {
+#pragma clang fp contract(off)
+    const double ux = (double)(lane + 64 * v) - c;
+    ctux[v] = g.ct * ux;
+    mstux[v] = (-g.st) * ux;
+  }
+  const bool vec = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(cube) & 15) == 0;
+  double tsum = 0.0;
+  for (int bi = 0; bi < nbands; ++bi) {
+    const int s0 = bi * (H - 1);
+    const int rows = (np - s0 < H) ? np - s0 : H;
+    const int lo = s0, hi = (bi == nbands - 1) ? n : s0 + H - 2;
+    __syncthreads();  // the previous band's reads are done
+    // bordered rows s0 .. s0+rows-1: zero border rows and columns, PSF rows inside
+    for (int r = tid; r < rows; r += 1024) {
+      P2[r * ls] = make_float2(0.0f, 0.0f);
+      P2[r * ls + np - 1] = make_float2(0.0f, 0.0f);
+    }
+    if (vec) {
+      const int nq = n >> 2;
+      for (int q = tid; q < rows * nq; q += 1024) {
+        const int r = q / nq, cc = 4 * (q - r * nq);
+        const int pr = s0 + r - 1;  // PSF row
+        f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f};
+        if ((unsigned)pr < (unsigned)n) {
+          x = *reinterpret_cast<const f32x4*>(Pk + pr * n + cc);
+          if (Pk1) y = *reinterpret_cast<const f32x4*>(Pk1 + pr * n + cc);
+        }
+        float2* dst = P2 + r * ls + cc + 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = make_float2(x[e], y[e]);
+      }
+    } else {
+      for (int q = tid; q < rows * n; q += 1024) {
+        const int r = q / n, cc = q - r * n;
+        const int pr = s0 + r - 1;
+        float2 v = make_float2(0.0f, 0.0f);
+        if ((unsigned)pr < (unsigned)n) v = make_float2(Pk[pr * n + cc], Pk1 ? Pk1[pr * n + cc] : 0.0f);
+        P2[r * ls + cc + 1] = v;
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int a = 0; a < n; ++a) {
+      double stuy, ctuy;
+      {
+#pragma clang fp contract(off)
+        const double uy = (double)a - c;
+        stuy = g.st * uy;
+        ctuy = g.ct * uy;
+      }
+      float rowsum = 0.0f;
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        const int b = lane + 64 * v;
+        if (!(FULL || b < n)) continue;
+        int R;
+        double rowf;
+        {
+#pragma clang fp contract(off)
+          const double sy = mstux[v] + ctuy;
+          rowf = c + sy;
+          R = (int)floor(rowf) + 1;  // |rowf| < 3n: exact
+        }
+        const bool rok = (unsigned)R <= (unsigned)n;
+        if (rok ? (R < lo || R > hi) : bi != 0) continue;
+        double colf;
+        {
+#pragma clang fp contract(off)
+          const double sx = ctux[v] + stuy;
+          colf = c + sx;
+        }
+        const double c0f = floor(colf), r0f = (double)(R - 1);
+        const double fx = colf - c0f, fy = rowf - r0f;
+        const float tfx = (float)fx, tgx = (float)(1.0 - fx);
+        const float tfy = (float)fy, tgy = (float)(1.0 - fy);
+        const int C = (int)c0f + 1;
+        const bool ok = rok && (unsigned)C <= (unsigned)n;
+        const int idx = ok ? (R - s0) * ls + C : 0;
+        const float2 p00 = P2[idx], p01 = P2[idx + 1];
+        const float2 p10 = P2[idx + ls], p11 = P2[idx + ls + 1];
+        const float q00 = fmaf(wk1, p00.y, wk0 * p00.x);
+        const float q01 = fmaf(wk1, p01.y, wk0 * p01.x);
+        const float q10 = fmaf(wk1, p10.y, wk0 * p10.x);
+        const float q11 = fmaf(wk1, p11.y, wk0 * p11.x);
+        float val = (tgy * tgx) * q00;
+        val = fmaf(tgy * tfx, q01, val);
+        val = fmaf(tfy * tgx, q10, val);
+        val = fmaf(tfy * tfx, q11, val);
+        val = ok ? val : 0.0f;
+        __builtin_nontemporal_store(val, col + a * n + b);
+        rowsum += val;
+      }
+      tsum += (double)rowsum;
+    }
+  }
+  if (!live) return;
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) tau[j] = tsum;
+}
+
 // 16-bit packing: M16[g][i][u] = RN16(A32[8g+u][i] * 2^-e), zeros past ncols.
 // Two rows per thread: 8 x 8-byte loads (one per column; 512 B per wave and
 // column) and 32 contiguous bytes stored.
@@ -335,10 +489,24 @@ static int lds_stride(int n) {
   return (size_t)np * ls * sizeof(float2) <= (size_t)kLdsBuildMaxBytes ? ls : np;
 }
 
+static bool pair_fits_lds(int n) {
+  return (size_t)(n + 2) * (n + 2) * sizeof(float2) <= (size_t)kLdsBuildMaxBytes;
+}
+
+// banded staging: row stride n+2 rounded up to 5 mod 8 (as lds_stride), and
+// the rows of that stride that fit the LDS
+static int band_stride(int n) {
+  const int np = n + 2;
+  return np + ((5 - np % 8) + 8) % 8;
+}
+static int band_rows(int n) { return (int)((size_t)kLdsBuildMaxBytes / ((size_t)band_stride(n) * sizeof(float2))); }
+
 bool build_lds_supported(int n, int K) {
-  // the bordered pair must fit the LDS, and the bucket histograms (8 B per
-  // bucket) the sort kernels' LDS
-  return (size_t)(n + 2) * (n + 2) * sizeof(float2) <= (size_t)kLdsBuildMaxBytes && K <= 8192;
+  // the bordered pair fits the LDS whole, or in bands of at least 16 rows with
+  // at most 4 image columns per lane; the bucket histograms (8 B per bucket)
+  // must fit the sort kernels' LDS
+  if (K > 8192) return false;
+  return pair_fits_lds(n) || (n <= 256 && band_rows(n) >= 16);
 }
 
 static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
@@ -404,9 +572,27 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
   const int nb = bp.nb;
   const int64_t items_max = bp.items_max;
 
+  const unsigned grid = (unsigned)items_max;
+  const bool full = (n % 64) == 0;
+  if (!pair_fits_lds(n)) {
+    const int ls = band_stride(n), H = band_rows(n), np = n + 2;
+    const int nbands = (np - 1 + (H - 1) - 1) / (H - 1);
+    const size_t lds = (size_t)H * ls * sizeof(float2);
+    auto launch = [&](auto kern) -> hipError_t {
+      const void* fn = reinterpret_cast<const void*>(kern);
+      hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (err != hipSuccess) return err;
+      kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, ls, H, nbands, M, A32,
+                                   tau);
+      return hipGetLastError();
+    };
+    switch (lds_e(n)) {  // n > 141 here
+      case 3: return full ? launch(build_band_kernel<3, true>) : launch(build_band_kernel<3, false>);
+      default: return full ? launch(build_band_kernel<4, true>) : launch(build_band_kernel<4, false>);
+    }
+  }
   const int ls = lds_stride(n);
   const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
-  const unsigned grid = (unsigned)items_max;
   const void* fn;
   auto launch = [&](auto kern) -> hipError_t {
     fn = reinterpret_cast<const void*>(kern);
@@ -415,7 +601,6 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
     kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, ls, M, A32, tau);
     return hipSuccess;
   };
-  const bool full = (n % 64) == 0;
   switch (lds_e(n)) {
     case 1: e = full ? launch(build_lds_kernel<1, true>) : launch(build_lds_kernel<1, false>); break;
     case 2: e = full ? launch(build_lds_kernel<2, true>) : launch(build_lds_kernel<2, false>); break;

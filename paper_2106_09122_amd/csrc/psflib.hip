@@ -235,10 +235,11 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   char* lib = reinterpret_cast<char*>(d_lib);
   double* tau = reinterpret_cast<double*>(lib + L.off_tau);
   int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
-  // Cubic-spline rotation: spline coefficients of the cube, then a gather
-  // build over coefficient pairs.  Bilinear: small PSFs (the bordered pair
-  // fits the LDS) take the bucketed LDS build; larger ones gather from a
-  // pair-interleaved copy of the cube.  The LDS build writes float32 columns,
+  // Cubic-spline rotation: spline coefficients of the cube, then a build over
+  // coefficient pairs staged in LDS (in row bands when large), or a gather
+  // past 256 x 256.  Bilinear: the bucketed LDS build, the pair staged whole
+  // when it fits the LDS and in row bands up to 256 x 256; larger PSFs gather
+  // from a pair-interleaved copy of the cube.  The LDS build writes float32 columns,
   // and so does every build when the flux-preserving rescale follows; the
   // 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;

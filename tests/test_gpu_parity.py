@@ -158,8 +158,13 @@ SHAPES = [
     (16, 13, 0.6, 1, "linear", "linear", "zero"),
     (64, 17, 0.25, 12, "nonuniform", "linear", "zero"),
     (36, 36, 0.3, 8, "linear", "nearest", "clamp"),
-    # PSFs too large for the LDS-staged build take the gather path
+    # bordered PSF pairs larger than the LDS: staged in row bands (2, 3 and 4
+    # bands; 199 also takes the scalar staging loads and partial lanes)
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
+    (199, 4, 0.5, 3, "nonuniform", "linear", "zero"),
+    (256, 3, 0.9, 3, "linear", "linear", "clamp"),
+    # PSFs larger than 256 x 256 take the gather path
+    (260, 3, 0.4, 3, "nonuniform", "linear", "clamp"),
 ]
 
 
@@ -196,7 +201,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[-1:] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + [SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
