@@ -2,11 +2,13 @@
 // and scene sizes, different wavelengths), in one persistent launch captured
 // in a HIP graph.  Sec. 5 of the paper points at simulating many complex
 // scenes at once; with a few scenes per library the product streams every
-// library once from HBM and is bandwidth bound, so it is a multi-right-hand-
-// side matvec rather than a matrix-core GEMM.
+// library once from HBM and is bandwidth bound: a multi-right-hand-side
+// matvec.  It still runs on the matrix cores, because they multiply a library
+// tile by 16 scenes at the rate HBM delivers it where the vector ALUs manage
+// about 8, and a library whose scenes fit one pass is read once.
 //
-// Work items are (library, scene group of <= kGrpScenes, row block, column
-// chunk) tiles, listed on the host when the plan is made.  A persistent grid
+// Work items are (library, scene group of <= 16, row block, column chunk)
+// tiles, listed on the host when the plan is made.  A persistent grid
 // walks the list; each workgroup streams its tile of the library once and
 // multiplies it with every scene of the group, writing partial images; a
 // second kernel adds the partials of each (scene, row block) in chunk order
@@ -27,9 +29,8 @@
 
 namespace psflib {
 
-constexpr int kGrpScenes = 8;     // FP32: scenes multiplied per pass over a tile
-constexpr int kGrpScenes16 = 16;  // 16-bit: scenes per pass (the library is read once per pass)
-constexpr int kGrpThreads = 256;
+constexpr int kGrpScenes = 16;  // scenes multiplied per pass (the library is read once per pass)
+constexpr int kGrpThreads = 256;  // 4 waves of 64 image rows
 
 struct GItem {
   const void* A;          // library matrix (FP32 column-major or 16-bit 8-column groups)
@@ -39,7 +40,7 @@ struct GItem {
   int64_t j0, j1;         // columns (FP32) or 8-column groups (16-bit) of the chunk
   int32_t scene0, nscenes;  // scenes (index into the plan's scene table)
   int64_t part;           // float offset of this item's partials: [scenes per pass][rows]
-  int64_t bpk;            // 16-bit: packed scene operand of the scene group, group 0
+  int64_t bpk;            // packed scene operand of the scene group (16-byte units)
 };
 
 // A scene slot of the plan: its values and its library's column exponents.
@@ -49,8 +50,9 @@ struct GScene {
   int64_t ncols;
 };
 
-// A 16-bit scene group: slots slot0 .. slot0+nscenes-1 of one library, packed
-// into the matrix-core operand at bpk (ngroups x 32 columns x 16 bytes).
+// A scene group: slots slot0 .. slot0+nscenes-1 of one library, packed into
+// the matrix-core operand at bpk: 16-bit, ngroups 8-column groups x 32 columns
+// x 16 bytes; FP32, ngroups 16-column blocks x 64 lanes x 16 bytes.
 struct GPack {
   int64_t bpk, ncols, ngroups;
   const int32_t* exps;
@@ -65,103 +67,123 @@ struct GReduce {
 };
 
 // ------------------------------------------------------------- kernels ----
-// FP32: each thread owns 4 consecutive rows (1024 rows per workgroup) and one
-// accumulator per scene; the chunk's scene values are staged in LDS (zeros for
-// the unused scene slots, so every slot is computed without branches) and read
-// as broadcasts; 8 columns of 16-byte non-temporal loads are in flight.
-template <bool FULL>
-__device__ __forceinline__ void grouped_f32_block8(const float* __restrict__ A, int64_t M,
-                                                   int64_t i0, int64_t j, const float* zrow,
-                                                   int zstride, f32x4* inner) {
-  f32x4 v[8];
+// FP32, on the matrix cores (v_mfma_f32_16x16x4f32: 16 rows x 16 scenes x 4
+// columns per instruction).  The scene group is packed once per run into
+// blocks of 16 columns: block b holds 64 lanes x 4 floats, lane l = 16q + n
+// holding Z_n[16b + 4s + q] for s = 0..3 (scene slot n, zeros past the
+// group's scenes and past ncols), the B operand of the four MFMA steps s of
+// the block.  A wave owns 64 image rows: lane (n = l % 16, q = l / 16) loads
+// rows m0 + 4n .. m0 + 4n + 3 of column 16b + 4s + q as one 16-byte load,
+// whose component t is the A operand of MFMA t; output row i of MFMA t is
+// image row m0 + 4i + t.  Loads go through buffer descriptors that end at the
+// live data (columns past ncols and blocks past the item read as zero), kGrpRing
+// blocks ahead of use, with no LDS and no barriers.  Accumulation is blocked
+// (64 columns, then the chunk).
+constexpr int kGrpRing = 2;
+
+template <bool VEC>
+__device__ __forceinline__ void grouped_f32_item(const GItem& w, const f32x4* __restrict__ zpk,
+                                                 int lane, int wave, float* __restrict__ part) {
+  const int64_t m0 = w.row0 + 64 * wave;
+  if (m0 >= w.M) return;  // no barriers: a wave past the image leaves at once
+  const int n = lane & 15, q = lane >> 4;
+  const int M4 = (int)(w.M * 4);
+  uint32_t voff[4];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const float* col = A + (j + u) * M + i0;
-    if constexpr (FULL) {
-      v[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
-    } else {
+  for (int s4 = 0; s4 < 4; ++s4) voff[s4] = (uint32_t)((4 * s4 + q) * M4 + (m0 + 4 * n) * 4);
+  const float* A = reinterpret_cast<const float*>(w.A);
+  const int b0 = (int)(w.j0 / 16), b1 = (int)((w.j1 + 15) / 16);
+  const int ncols = (int)w.ncols;
+  f32x4 ra[kGrpRing][4], rb[kGrpRing];
+  auto issue = [&](int b, int slot) {
+    const bool live = b < b1;
+    const int bc = live ? b : b1 - 1;
+    const int left = ncols - 16 * bc;  // columns of the library from this block on
+    const int abytes = !live ? 0 : left >= 16 ? 0x7FFFFFFF : left * M4;
+    const __amdgpu_buffer_rsrc_t ad = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A + (int64_t)16 * bc * w.M), (short)0, abytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t bd = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(zpk + w.bpk + (int64_t)bc * 64), (short)0, live ? 1024 : 0, 0x00020000);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[u][e] = (i0 + e < M) ? col[e] : 0.0f;
+    for (int s4 = 0; s4 < 4; ++s4) {
+      if (VEC) {
+        ra[slot][s4] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ad, voff[s4], 0, 2));
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          ra[slot][s4][t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ad, voff[s4] + 4 * t, 0, 2));
+      }
     }
-  }
+    rb[slot] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(bd, (uint32_t)lane * 16, 0, 0));
+  };
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[4], tot[4];
 #pragma unroll
-  for (int r = 0; r < kGrpScenes; ++r) {
-    const f32x4 za = *reinterpret_cast<const f32x4*>(zrow + r * zstride);
-    const f32x4 zb = *reinterpret_cast<const f32x4*>(zrow + r * zstride + 4);
-    inner[r] += v[0] * za.x;
-    inner[r] += v[1] * za.y;
-    inner[r] += v[2] * za.z;
-    inner[r] += v[3] * za.w;
-    inner[r] += v[4] * zb.x;
-    inner[r] += v[5] * zb.y;
-    inner[r] += v[6] * zb.z;
-    inner[r] += v[7] * zb.w;
+  for (int t = 0; t < 4; ++t) tot[t] = zero4;
+  const int nblk = (b1 - b0 + 3) / 4;  // groups of 4 blocks = 64 columns
+#pragma unroll
+  for (int r = 0; r < kGrpRing; ++r) issue(b0 + r, r);
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int bb = b0 + 4 * kb;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int slot = u % kGrpRing;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[slot][s4][t], rb[slot][s4],
+                                                        (u == 0 && s4 == 0) ? zero4 : acc[t], 0, 0, 0);
+      issue(bb + u + kGrpRing, slot);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) tot[t] += acc[t];
+  }
+  // lane holds scene n and MFMA rows 4q + r, i.e. image rows m0 + 16q + 4r + t
+  if (n < w.nscenes) {
+    float* dst = part + w.part + (int64_t)n * kGrpThreads + 64 * wave + 16 * q;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const f32x4 v = {tot[0][r], tot[1][r], tot[2][r], tot[3][r]};
+      *reinterpret_cast<f32x4*>(dst + 4 * r) = v;
+    }
   }
 }
 
-template <bool FULL>
-__device__ __forceinline__ void grouped_f32_rows(const float* __restrict__ A, int64_t M,
-                                                 int64_t i0, int64_t j0, int nc,
-                                                 const float* zs, f32x4* acc) {
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  int q = 0;
-  for (; q + 16 <= nc; q += 16) {  // blocked sums: 16 columns per inner sum
-    f32x4 inner[kGrpScenes];
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) inner[r] = zero;
-    grouped_f32_block8<FULL>(A, M, i0, j0 + q, zs + q, kGrpMaxChunkCols, inner);
-    grouped_f32_block8<FULL>(A, M, i0, j0 + q + 8, zs + q + 8, kGrpMaxChunkCols, inner);
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) acc[r] += inner[r];
-  }
-  f32x4 inner[kGrpScenes];
-#pragma unroll
-  for (int r = 0; r < kGrpScenes; ++r) inner[r] = zero;
-  for (; q < nc; ++q) {
-    const float* col = A + (j0 + q) * M + i0;
-    f32x4 v;
-    if constexpr (FULL) {
-      v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(col));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = (i0 + e < M) ? col[e] : 0.0f;
-    }
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) inner[r] += v * zs[r * kGrpMaxChunkCols + q];
-  }
-#pragma unroll
-  for (int r = 0; r < kGrpScenes; ++r) acc[r] += inner[r];
-}
-
-__global__ __launch_bounds__(kGrpThreads, 2) void grouped_f32_kernel(
-    const GItem* __restrict__ items, int64_t nitems, const float* const* __restrict__ scenes,
+__global__ __launch_bounds__(kGrpThreads) void grouped_f32_kernel(
+    const GItem* __restrict__ items, int64_t nitems, const f32x4* __restrict__ zpk,
     float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) float zs[kGrpScenes * kGrpMaxChunkCols];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem w = items[it];
-    const float* A = reinterpret_cast<const float*>(w.A);
-    const int nc = (int)(w.j1 - w.j0);
-    __syncthreads();  // the previous item is done with zs
-    for (int t = threadIdx.x; t < kGrpScenes * nc; t += kGrpThreads) {
-      const int r = t / nc, q = t - r * nc;
-      zs[r * kGrpMaxChunkCols + q] = (r < w.nscenes) ? scenes[w.scene0 + r][w.j0 + q] : 0.0f;
+    if ((w.M & 3) == 0)
+      grouped_f32_item<true>(w, zpk, lane, wave, part);
+    else
+      grouped_f32_item<false>(w, zpk, lane, wave, part);
+  }
+}
+
+// FP32 packed scene operand: thread = (scene group, 16-column block b, lane l).
+__global__ __launch_bounds__(256) void grouped_pack_f32_kernel(const GPack* __restrict__ packs,
+                                                               const float* const* __restrict__ scenes,
+                                                               f32x4* __restrict__ zpk) {
+  const GPack pk = packs[blockIdx.x];
+  for (int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x; t < pk.ngroups * 64;
+       t += (int64_t)gridDim.y * 256) {
+    const int l = (int)(t & 63);
+    const int64_t b = t >> 6;
+    const int n = l & 15, q = l >> 4;
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (n < pk.nscenes) {
+      const float* z = scenes[pk.slot0 + n];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int64_t j = 16 * b + 4 * s4 + q;
+        if (j < pk.ncols) v[s4] = z[j];
+      }
     }
-    __syncthreads();
-    const int64_t i0 = w.row0 + 4 * (int64_t)threadIdx.x;
-    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-    f32x4 acc[kGrpScenes];
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r) acc[r] = zero;
-    // uniform across the workgroup: every row of the block is inside the image
-    const bool block_full = (w.M % 4 == 0) && w.row0 + 4 * kGrpThreads <= w.M;
-    if (block_full)
-      grouped_f32_rows<true>(A, w.M, i0, w.j0, nc, zs, acc);
-    else if (i0 < w.M)
-      grouped_f32_rows<false>(A, w.M, i0, w.j0, nc, zs, acc);
-    const int64_t rows = 4 * kGrpThreads;
-#pragma unroll
-    for (int r = 0; r < kGrpScenes; ++r)
-      *reinterpret_cast<f32x4*>(part + w.part + r * rows + 4 * threadIdx.x) = acc[r];
+    zpk[pk.bpk + t] = v;
   }
 }
 
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restri
   for (int64_t g = (int64_t)blockIdx.y * 256 + threadIdx.x; g < pk.ngroups;
        g += (int64_t)gridDim.y * 256) {
     u32x4* dst = bpk + pk.bpk + g * 32;
-    for (int r = 0; r < kGrpScenes16; ++r) {
+    for (int r = 0; r < kGrpScenes; ++r) {
       uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
       if (r < pk.nscenes) {
         const float* z = scenes[pk.slot0 + r];
@@ -396,22 +418,22 @@ struct Plan {
 };
 
 // Items for a given chunk length.  Scenes are grouped by library (kept in the
-// caller's order inside a library) and cut into groups of kGrpScenes (FP32)
-// or kGrpScenes16 (16-bit).
+// caller's order inside a library) and cut into groups of kGrpScenes.
 Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib_of_scene,
                const float* const* scenes, float* const* images, int B, int64_t chunk) {
   Plan p;
   const bool f32 = storage == PSFLIB_FP32;
-  const int64_t rows_per = f32 ? 4 * psflib::kGrpThreads : psflib::kGrpThreads;
+  const int64_t rows_per = psflib::kGrpThreads;
   for (size_t L = 0; L < libs.size(); ++L) {
     std::vector<int> sc;
     for (int b = 0; b < B; ++b)
       if (lib_of_scene[b] == (int)L) sc.push_back(b);
     const LibInfo& li = libs[L];
-    const int64_t units = f32 ? li.ncols : li.ncols_pad / 8;
+    const int64_t units = f32 ? li.ncols : li.ncols_pad / 8;  // chunks count columns or 8-column groups
+    const int64_t pk_units = f32 ? (li.ncols + 15) / 16 : units;  // packed operand blocks
     const int64_t nchunks = (units + chunk - 1) / chunk;
     const int64_t nrb = (li.M + rows_per - 1) / rows_per;
-    const size_t spg = f32 ? psflib::kGrpScenes : psflib::kGrpScenes16;
+    const size_t spg = psflib::kGrpScenes;
     for (size_t g0 = 0; g0 < sc.size(); g0 += spg) {
       const int ns = (int)std::min<size_t>(spg, sc.size() - g0);
       const int32_t scene0 = (int32_t)p.scenes.size();
@@ -420,12 +442,9 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
         p.images.push_back(images[sc[g0 + r]]);
         p.slots.push_back(psflib::GScene{scenes[sc[g0 + r]], li.exps, li.ncols});
       }
-      int64_t bpk = 0;
-      if (!f32) {
-        bpk = p.bpk_vecs;
-        p.packs.push_back(psflib::GPack{bpk, li.ncols, units, li.exps, scene0, ns});
-        p.bpk_vecs += units * 32;
-      }
+      const int64_t bpk = p.bpk_vecs;
+      p.packs.push_back(psflib::GPack{bpk, li.ncols, pk_units, li.exps, scene0, ns});
+      p.bpk_vecs += pk_units * (f32 ? 64 : 32);
       for (int64_t rb = 0; rb < nrb; ++rb) {
         psflib::GReduce rd;
         rd.M = li.M;
@@ -530,9 +549,12 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     if (nitems > 0) {
-      if (g->storage == PSFLIB_FP32)
-        grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems, sc, part);
-      else {
+      if (g->storage == PSFLIB_FP32) {
+        const dim3 np((unsigned)p.packs.size(), 16);
+        grouped_pack_f32_kernel<<<np, 256, 0, cap>>>(packs, sc, reinterpret_cast<f32x4*>(bpk));
+        grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems,
+                                                          reinterpret_cast<const f32x4*>(bpk), part);
+      } else {
         grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 256, 0, cap>>>(slots, fexp);
         const dim3 np((unsigned)p.packs.size(), 16);  // 16 blocks of 256 groups per scene group
         if (g->storage == PSFLIB_BF16_POW2) {
@@ -606,7 +628,7 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
 
   // Candidate chunk lengths: columns (FP32) or 8-column groups (16-bit).
   const bool f32 = storage == PSFLIB_FP32;
-  std::vector<int64_t> cands = f32 ? std::vector<int64_t>{256, 512, 1024}
+  std::vector<int64_t> cands = f32 ? std::vector<int64_t>{256, 512, 1024, 2048}
                                    : std::vector<int64_t>{128, 256, 512, 1024};
   std::string sig = std::to_string(storage) + ":";
   for (int b = 0; b < B; ++b) {

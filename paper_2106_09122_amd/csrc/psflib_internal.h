@@ -33,7 +33,6 @@ constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 floa
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
 constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
 constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
-constexpr int kGrpMaxChunkCols = 1024;   // grouped FP32 apply: columns per chunk, at most
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter

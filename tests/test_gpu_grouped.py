@@ -69,3 +69,35 @@ def test_grouped_empty_and_unused_libraries(torch, work):
         got = g2.run()[0].cpu().numpy().astype(np.float64)
         pos = ref > 0
         assert np.max(np.abs(got[pos] - ref[pos]) / ref[pos]) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def crowded():
+    """Two libraries with odd pixel counts (15^2, 17^2: the unaligned load path)
+    and about 20 scenes each, so each library takes a full and a partial scene
+    group."""
+    libs, scene_lib, scenes = synth.mixed_workload(B=40, sizes=(15, 17), wavelengths=(1.0,))
+    As = [O.build_library(L["cube"], L["radii"], L["N"], L["S"]) for L in libs]
+    refs = [As[L] @ z.astype(np.float64) for L, z in zip(scene_lib, scenes)]
+    return libs, scene_lib, scenes, refs
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+def test_grouped_crowded_odd_sizes(torch, crowded, storage):
+    from paper_2106_09122_amd import psflib
+    libs, scene_lib, scenes, refs = crowded
+    assert max(np.bincount(scene_lib)) > 16
+    L = [psflib.Library(torch.from_numpy(l["cube"]).cuda(), l["radii"], l["N"], l["S"], storage=storage)
+         for l in libs]
+    Zs = [torch.from_numpy(z).cuda() for z in scenes]
+    g = psflib.Grouped(L, scene_lib, Zs, autotune=True)
+    out = [im.cpu().numpy().astype(np.float64) for im in g.run()]
+    for b, (got, ref) in enumerate(zip(out, refs)):
+        if storage == "fp32":
+            pos = ref > 0
+            assert np.all(got[~pos] == 0)
+            assert np.max(np.abs(got[pos] - ref[pos]) / ref[pos]) <= 1e-5, b
+        else:
+            big = ref > 1e-6 * ref.max()
+            assert np.max(np.abs(got - ref)[big] / ref[big]) <= U16[storage] + 1e-5, b
+    g.close()
