@@ -45,7 +45,9 @@ def kernel_bodies(text):
 def test_stage_issue_pattern(asm):
     for name, lines in kernel_bodies(asm):
         assert not any("scratch_" in l for l in lines), name
-        bars = [i for i, l in enumerate(lines) if "s_waitcnt vmcnt(12)" in l]
+        # a stage barrier: the ring wait (vmcnt(12)) then s_barrier
+        bars = [i for i, l in enumerate(lines)
+                if "s_barrier" in l and i > 0 and "s_waitcnt vmcnt(12)" in lines[i - 1]]
         assert len(bars) >= 8, name
         for a, b in zip(bars, bars[1:]):
             seg = lines[a:b]
