@@ -243,8 +243,9 @@ psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
                                  const double* d_theta, float* d_scene, void* stream);
 
 /* d_dtheta[k] = sum_j d_dscene[j] * dZ_j/dtheta_k (float64 [5]), accumulated in
- * float64 in a fixed order (one workgroup; intended for scenes up to ~1e6
- * pixels). */
+ * float64 in a fixed order (per-workgroup trees, then their sums in block
+ * order), so repeated calls give identical results.  Uses N*N/256 * 40 bytes
+ * of stream-ordered scratch from the library's device memory pool. */
 psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double rmax,
                                       const double* d_theta, const float* d_dscene,
                                       double* d_dtheta, void* stream);

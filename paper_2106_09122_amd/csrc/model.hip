@@ -53,42 +53,70 @@ __global__ __launch_bounds__(256) void render_disk_kernel(int N, double S, doubl
   Z[j] = (float)disk_terms(j, N, S, rmax, th).Z;
 }
 
-// One workgroup: dtheta_k = sum_j dZ_j dZ_j/dtheta_k, float64, fixed order
-// (each thread a strided set of pixels, then a tree).
-__global__ __launch_bounds__(1024) void render_disk_grad_kernel(int N, double S, double rmax,
-                                                                const double* __restrict__ theta,
-                                                                const float* __restrict__ dZ,
-                                                                double* __restrict__ dtheta) {
-  __shared__ double red[5][1024];
+// dtheta_k = sum_j dZ_j dZ_j/dtheta_k in float64, in a fixed order: one
+// pixel per thread, a tree per workgroup into partial[k][block], then one
+// workgroup adds the block sums (each thread a strided run, then a tree).
+constexpr int kGradThreads = 256;
+
+__device__ __forceinline__ void tree256(double (*red)[kGradThreads], int tid) {
+  for (int s = kGradThreads / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if (tid < s) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) red[k][tid] += red[k][tid + s];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kGradThreads) void render_disk_grad_kernel(
+    int N, double S, double rmax, const double* __restrict__ theta, const float* __restrict__ dZ,
+    int64_t nblocks, double* __restrict__ partial) {
+  __shared__ double red[5][kGradThreads];
+  const int tid = threadIdx.x;
   double th[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) th[k] = theta[k];
-  const double ci = cos(th[0]), si = sin(th[0]);
-  const double r0 = th[1], w = th[2], g = th[3], F = th[4];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int64_t npix = (int64_t)N * N;
-  for (int64_t j = threadIdx.x; j < npix; j += 1024) {
+  const int64_t j = (int64_t)blockIdx.x * kGradThreads + tid;
+  if (j < (int64_t)N * N) {
     const DiskTerms d = disk_terms(j, N, S, rmax, th);
-    if (!d.live) continue;
-    const double gz = (double)dZ[j] * d.Z;
-    const double dr = d.rho - r0;
-    acc[0] += (double)dZ[j] * d.dZdrho * (d.y * d.y * si / (ci * ci * ci * d.rho));
-    acc[1] += gz * (-g / r0 + dr / (w * w));
-    acc[2] += gz * dr * dr / (w * w * w);
-    acc[3] += gz * log(d.rho / r0);
-    acc[4] += gz / F;
-  }
-#pragma unroll
-  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    if (d.live) {
+      const double ci = cos(th[0]), si = sin(th[0]);
+      const double r0 = th[1], w = th[2], g = th[3], F = th[4];
+      const double gz = (double)dZ[j] * d.Z;
+      const double dr = d.rho - r0;
+      acc[0] = (double)dZ[j] * d.dZdrho * (d.y * d.y * si / (ci * ci * ci * d.rho));
+      acc[1] = gz * (-g / r0 + dr / (w * w));
+      acc[2] = gz * dr * dr / (w * w * w);
+      acc[3] = gz * log(d.rho / r0);
+      acc[4] = gz / F;
     }
-    __syncthreads();
   }
-  if (threadIdx.x < 5) dtheta[threadIdx.x] = red[threadIdx.x][0];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) red[k][tid] = acc[k];
+  tree256(red, tid);
+  if (tid < 5) partial[(int64_t)tid * nblocks + blockIdx.x] = red[tid][0];
+}
+
+__global__ __launch_bounds__(kGradThreads) void grad_sum_kernel(const double* __restrict__ partial,
+                                                                int64_t nblocks,
+                                                                double* __restrict__ dtheta) {
+  __shared__ double red[5][kGradThreads];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double a = 0.0;
+    for (int64_t b = tid; b < nblocks; b += kGradThreads) a += partial[k * nblocks + b];
+    red[k][tid] = a;
+  }
+  tree256(red, tid);
+  if (tid < 5) dtheta[tid] = red[tid][0];
+}
+
+size_t render_disk_grad_scratch_bytes(int N) {
+  const int64_t nblocks = ((int64_t)N * N + kGradThreads - 1) / kGradThreads;
+  return (size_t)nblocks * 5 * sizeof(double);
 }
 
 hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,
@@ -99,8 +127,14 @@ hipError_t launch_render_disk(int N, double S, double rmax, const double* theta,
 }
 
 hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
-                                   const float* dZ, double* dtheta, hipStream_t s) {
-  render_disk_grad_kernel<<<1, 1024, 0, s>>>(N, S, rmax, theta, dZ, dtheta);
+                                   const float* dZ, double* dtheta, void* scratch, hipStream_t s) {
+  const int64_t nblocks = ((int64_t)N * N + kGradThreads - 1) / kGradThreads;
+  double* partial = reinterpret_cast<double*>(scratch);
+  render_disk_grad_kernel<<<(unsigned)nblocks, kGradThreads, 0, s>>>(N, S, rmax, theta, dZ,
+                                                                     nblocks, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  grad_sum_kernel<<<1, kGradThreads, 0, s>>>(partial, nblocks, dtheta);
   return hipGetLastError();
 }
 

@@ -454,9 +454,18 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_dscene);
   if (st != PSFLIB_OK) return st;
   if (!d_dtheta) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be non-NULL");
-  hipError_t e = psflib::launch_render_disk_grad(N, scene_pixscale, rmax, d_theta, d_dscene,
-                                                 d_dtheta, reinterpret_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return device_fail(e, "render_disk_grad kernel");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  void* scratch = nullptr;
+  e = scratch_alloc(&scratch, psflib::render_disk_grad_scratch_bytes(N), dev, s);
+  if (e != hipSuccess) return device_fail(e, "scratch allocation (disk gradient)");
+  e = psflib::launch_render_disk_grad(N, scene_pixscale, rmax, d_theta, d_dscene, d_dtheta,
+                                      scratch, s);
+  hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return device_fail(e, "render_disk_grad kernels");
   return PSFLIB_OK;
 }
 

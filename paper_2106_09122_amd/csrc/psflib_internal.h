@@ -138,8 +138,9 @@ hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
                               float* out, hipStream_t s);
 hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,
                               hipStream_t s);
+size_t render_disk_grad_scratch_bytes(int N);
 hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
-                                   const float* dZ, double* dtheta, hipStream_t s);
+                                   const float* dZ, double* dtheta, void* scratch, hipStream_t s);
 hipError_t launch_export_geometry(const ColGeom* geo, int64_t ncols, double* geom, int32_t* k,
                                   hipStream_t s);
 
