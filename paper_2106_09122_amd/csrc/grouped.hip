@@ -206,17 +206,31 @@ __global__ __launch_bounds__(256) void grouped_pack_f32_kernel(const GPack* __re
 // registers and scene fragments from the packed operand, a block of 4 K steps
 // ahead, with no LDS and no barriers.
 
-// f_s of every scene slot (one workgroup per slot).
-__global__ __launch_bounds__(256) void grouped_scene_exp_kernel(const GScene* __restrict__ slots,
-                                                                int32_t* __restrict__ fexp) {
-  __shared__ double red[256];
+// f_s of every scene slot (one 1024-thread workgroup per slot; 16-byte loads
+// of the scene and the exponents when both are aligned).
+__global__ __launch_bounds__(1024) void grouped_scene_exp_kernel(const GScene* __restrict__ slots,
+                                                                 int32_t* __restrict__ fexp) {
+  __shared__ double red[1024];
   const GScene sc = slots[blockIdx.x];
   double m = 0.0;
-  for (int64_t j = threadIdx.x; j < sc.ncols; j += 256)
-    m = fmax(m, ldexp((double)fabsf(sc.z[j]), sc.exps[j]));
+  const bool vec = (sc.ncols % 4) == 0 && (reinterpret_cast<uintptr_t>(sc.z) % 16) == 0 &&
+                   (reinterpret_cast<uintptr_t>(sc.exps) % 16) == 0;
+  if (vec) {
+    for (int64_t j = 4 * (int64_t)threadIdx.x; j < sc.ncols; j += 4 * 1024) {
+      const f32x4 z = *reinterpret_cast<const f32x4*>(sc.z + j);
+      const int4 e = *reinterpret_cast<const int4*>(sc.exps + j);
+      m = fmax(m, ldexp((double)fabsf(z[0]), e.x));
+      m = fmax(m, ldexp((double)fabsf(z[1]), e.y));
+      m = fmax(m, ldexp((double)fabsf(z[2]), e.z));
+      m = fmax(m, ldexp((double)fabsf(z[3]), e.w));
+    }
+  } else {
+    for (int64_t j = threadIdx.x; j < sc.ncols; j += 1024)
+      m = fmax(m, ldexp((double)fabsf(sc.z[j]), sc.exps[j]));
+  }
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
@@ -250,37 +264,38 @@ __device__ __forceinline__ float g16_value(uint16_t h) {
     return (float)__builtin_bit_cast(_Float16, h);
 }
 
-// Packed operand: thread = (scene group, 8-column group g); writes the 32
-// columns (hi parts of scenes 0..15, then lo parts) of group g, 16 bytes each.
-// Grid: one row of workgroups per scene group, groups strided across the row.
+// Packed operand: thread = (scene group, 8-column group g, scene slot r);
+// writes column r (hi parts) and 16 + r (lo parts) of group g, 16 bytes each
+// (zeros for slots past the group's scenes).  Grid: one row of workgroups per
+// scene group, (group, slot) pairs strided across the row.
 template <bool BF16>
 __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restrict__ packs,
                                                            const float* const* __restrict__ scenes,
                                                            const int32_t* __restrict__ fexp,
                                                            u32x4* __restrict__ bpk) {
   const GPack pk = packs[blockIdx.x];
-  for (int64_t g = (int64_t)blockIdx.y * 256 + threadIdx.x; g < pk.ngroups;
-       g += (int64_t)gridDim.y * 256) {
+  for (int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x; t < pk.ngroups * kGrpScenes;
+       t += (int64_t)gridDim.y * 256) {
+    const int64_t g = t / kGrpScenes;
+    const int r = (int)(t - g * kGrpScenes);
     u32x4* dst = bpk + pk.bpk + g * 32;
-    for (int r = 0; r < kGrpScenes; ++r) {
-      uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
-      if (r < pk.nscenes) {
-        const float* z = scenes[pk.slot0 + r];
-        const int f = fexp[pk.slot0 + r];
+    uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
+    if (r < pk.nscenes) {
+      const float* z = scenes[pk.slot0 + r];
+      const int f = fexp[pk.slot0 + r];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int64_t j = g * 8 + u;
-          float v = 0.0f;
-          if (j < pk.ncols) v = ldexpf(z[j], pk.exps[j] + f);
-          const uint16_t h = g16_round<BF16>(v);
-          const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
-          hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
-          lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = g * 8 + u;
+        float v = 0.0f;
+        if (j < pk.ncols) v = ldexpf(z[j], pk.exps[j] + f);
+        const uint16_t h = g16_round<BF16>(v);
+        const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
+        hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
+        lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
       }
-      dst[r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
-      dst[16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
     }
+    dst[r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
+    dst[16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
   }
 }
 
@@ -550,13 +565,13 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   if (e == hipSuccess) {
     if (nitems > 0) {
       if (g->storage == PSFLIB_FP32) {
-        const dim3 np((unsigned)p.packs.size(), 16);
+        const dim3 np((unsigned)p.packs.size(), 64);
         grouped_pack_f32_kernel<<<np, 256, 0, cap>>>(packs, sc, reinterpret_cast<f32x4*>(bpk));
         grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems,
                                                           reinterpret_cast<const f32x4*>(bpk), part);
       } else {
-        grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 256, 0, cap>>>(slots, fexp);
-        const dim3 np((unsigned)p.packs.size(), 16);  // 16 blocks of 256 groups per scene group
+        grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 1024, 0, cap>>>(slots, fexp);
+        const dim3 np((unsigned)p.packs.size(), 64);  // 64 workgroups per scene group
         if (g->storage == PSFLIB_BF16_POW2) {
           grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
           grouped_h16_kernel<true><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
