@@ -129,8 +129,8 @@ def dense(c2):
     so every term of every accumulation chain is exercised."""
     N = c2["N"]
     K = N * N
-    Zb = np.random.default_rng(31).random((256, K)).astype(np.float32)
-    ref = np.zeros((256, c2["n"] ** 2))
+    Zb = np.random.default_rng(31).random((512, K)).astype(np.float32)
+    ref = np.zeros((512, c2["n"] ** 2))
     for c0 in range(0, K, 2048):
         cols = np.arange(c0, min(K, c0 + 2048))
         A = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols)
@@ -142,7 +142,7 @@ def dense(c2):
 def test_c2_batched_dense(torch, c2, dense, storage):
     Zb, ref = dense
     lib = _build(torch, c2, storage)
-    for B in (20, 64, 256):
+    for B in (20, 64, 256, 512):  # every K-split shape, down to no split (the longest chains)
         out = lib.apply_batched(torch.from_numpy(Zb[:B]).cuda()).cpu().numpy().astype(np.float64)
         r = ref[:B]
         if storage == "fp32":
