@@ -89,10 +89,18 @@ __device__ __forceinline__ uint32_t f32_to_f16_rne(float f) {
   return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
+// Coefficient pair at (r, c) of the padded array, zero outside it.
+__device__ __forceinline__ float2 tap_pair(const float2* __restrict__ P, int Np, int r, int c) {
+  if ((unsigned)r < (unsigned)Np && (unsigned)c < (unsigned)Np) return P[r * Np + c];
+  return make_float2(0.0f, 0.0f);
+}
+
 // Cubic-spline rotation: the same source point as the bilinear form, in the
 // coordinates of the spline coefficients (padded by kSplinePad), sampled with
-// the 4 x 4 B-spline weights; each tap blends the coefficient pair of the
-// column's bracket, and taps outside the padded array are zero.
+// the 4 x 4 B-spline weights, taps outside the padded array zero.  The taps
+// are summed separably — each row's weighted sum of the k and k+1
+// coefficients, those rows weighted, then the radial blend — in the order the
+// LDS-staged cubic build uses, so both forms give identical values.
 __device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int Np, double c,
                                                     double ux, double uy) {
 #pragma clang fp contract(off)
@@ -106,13 +114,23 @@ __device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int 
   float wy[4], wx[4];
   cubic_weights(rowf - r0f, wy);
   cubic_weights(colf - c0f, wx);
-  float v = 0.0f;
+  float X = 0.0f, Y = 0.0f;
 #pragma unroll
-  for (int dr = 0; dr < 4; ++dr)
-#pragma unroll
-    for (int dc = 0; dc < 4; ++dc)
-      v = fmaf(wy[dr] * wx[dc], tap(cp.src, Np, r0 + dr - 1, c0 + dc - 1, cp.wk0, cp.wk1), v);
-  return v;
+  for (int dr = 0; dr < 4; ++dr) {
+    const int r = r0 + dr - 1;
+    const float2 p0 = tap_pair(cp.src, Np, r, c0 - 1), p1 = tap_pair(cp.src, Np, r, c0);
+    const float2 p2 = tap_pair(cp.src, Np, r, c0 + 1), p3 = tap_pair(cp.src, Np, r, c0 + 2);
+    float x = wx[0] * p0.x, y = wx[0] * p0.y;
+    x = fmaf(wx[1], p1.x, x);
+    y = fmaf(wx[1], p1.y, y);
+    x = fmaf(wx[2], p2.x, x);
+    y = fmaf(wx[2], p2.y, y);
+    x = fmaf(wx[3], p3.x, x);
+    y = fmaf(wx[3], p3.y, y);
+    X = fmaf(wy[dr], x, X);
+    Y = fmaf(wy[dr], y, Y);
+  }
+  return fmaf(cp.wk1, Y, cp.wk0 * X);
 }
 
 template <int STORE, bool CUBIC>

@@ -127,31 +127,51 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Rows per LDS band of the padded coefficient pair (Np pairs per row).
+// The padded coefficient pair is staged in LDS with 4 more zero rows and
+// columns on every side (the extended array, Ne = Np + 8 per side, row
+// stride ls >= Ne).  A pixel's tap origin is clamped to padded indices
+// [-3, Np+1]: where that moves it, all 4 x 4 taps lay outside the padded
+// array and the clamped taps all read the zero margin, so the value is still
+// exactly zero; every tap is then a plain LDS read at a fixed offset from one
+// base address, with no bounds tests or weight masking.
+constexpr int kCubicMargin = 4;
+
+__host__ __device__ inline int cubic_ext(int Np) { return Np + 2 * kCubicMargin; }
+
+// row stride of the extended array: Ne rounded up to 5 mod 8 (spreads the
+// taps of a near-vertical line over the banks, as in the bilinear build)
+__host__ __device__ inline int cubic_stride(int Np) {
+  const int ne = cubic_ext(Np);
+  return ne + ((5 - ne % 8) + 8) % 8;
+}
+
+// Rows per LDS band of the extended array.
 __host__ __device__ inline int cubic_band_rows(int Np) {
-  const int h = (int)((size_t)kLdsBuildMaxBytes / ((size_t)Np * sizeof(float2)));
-  return h < Np ? h : Np;
+  const int h = (int)((size_t)kLdsBuildMaxBytes / ((size_t)cubic_stride(Np) * sizeof(float2)));
+  const int ne = cubic_ext(Np);
+  return h < ne ? h : ne;
 }
 
 // Cubic-spline build with the bracket's coefficient pair (C_k, C_{k+1}) staged
-// in LDS.  The padded pair has Np x Np entries; when that exceeds the LDS it
-// is staged in bands of H rows that overlap by 3, band b holding rows
-// [b (H-3), b (H-3) + H).  The 4 tap rows of an output pixel, r0-1 .. r0+2,
-// all lie in band floor(max(r0-1, 0) / (H-3)) (the last band for rows near
-// the bottom), so each pixel is produced in exactly one band.  A work item is
-// up to kLdsCols columns of one bracket (columns grouped on the device), one
-// wave per column, lane l owning image columns l, l+64, ...; coordinates and
-// B-spline weights in float64 (weights rounded once to float32), the weight
-// products, blended taps and the 16-term sum in float32 in the same order as
-// the gather form, so both forms give identical values.
+// in LDS.  When the extended array exceeds the LDS it is staged in bands of H
+// rows that overlap by 3, band b holding extended rows [b (H-3), b (H-3) + H);
+// the 4 tap rows of a pixel, from its (clamped) origin row R - 1 on, all lie
+// in band min((R - 1) / (H-3), last), so each pixel is produced in exactly
+// one band.  A work item is up to kLdsCols columns of one bracket (columns
+// grouped on the device), one wave per column, lane l owning image columns
+// l, l+64, ...  Coordinates and B-spline weights in float64 (weights rounded
+// once to float32); the 16 taps are summed separably in float32 — each row's
+// weighted sum of the k and k+1 coefficients, those rows weighted, then the
+// radial blend — in the same order as the gather form, so both give identical
+// values.
 template <int E, bool FULL>
 __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
-    const float2* __restrict__ pairs, int Np, int H, int nbands, const ColGeom* __restrict__ geo,
-    const int32_t* __restrict__ order, const int4* __restrict__ items,
-    const int32_t* __restrict__ nitems, int nb, int n, int64_t M, float* __restrict__ A,
-    double* __restrict__ tau) {
+    const float2* __restrict__ pairs, int Np, int ls, int H, int nbands,
+    const ColGeom* __restrict__ geo, const int32_t* __restrict__ order,
+    const int4* __restrict__ items, const int32_t* __restrict__ nitems, int nb, int n, int64_t M,
+    float* __restrict__ A, double* __restrict__ tau) {
 #pragma clang fp contract(off)
-  extern __shared__ float2 band[];  // H rows of Np pairs
+  extern __shared__ float2 band[];  // H rows of the extended array, stride ls
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
   const int bkt = it.x, start = it.y, len = it.z;
@@ -170,6 +190,7 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
     return;
   }
   const float2* src = pairs + (int64_t)bkt * Np * Np;
+  const int Ne = cubic_ext(Np);
   const bool live = wave < len;
   int64_t j = 0;
   ColGeom g;
@@ -184,7 +205,6 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
   double ctux[E], mstux[E];
 #pragma unroll
   for (int v = 0; v < E; ++v) {
-#pragma clang fp contract(off)
     const double ux = (double)(lane + 64 * v) - c;
     ctux[v] = g.ct * ux;
     mstux[v] = (-g.st) * ux;
@@ -193,16 +213,21 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
   double tsum = 0.0;
   for (int bi = 0; bi < nbands; ++bi) {
     const int s0 = bi * (H - 3);
-    const int rows = (Np - s0 < H) ? Np - s0 : H;
+    const int rows = (Ne - s0 < H) ? Ne - s0 : H;
+    const int hi = (bi == nbands - 1) ? Ne : s0 + H - 4;  // last origin row of this band
     __syncthreads();  // the previous band's reads are done
-    const float2* bsrc = src + (int64_t)s0 * Np;
-    for (int q = tid; q < rows * Np; q += 1024) band[q] = bsrc[q];
+    for (int q = tid; q < rows * Ne; q += 1024) {
+      const int r = q / Ne, cc = q - r * Ne;
+      const int pr = s0 + r - kCubicMargin, pc = cc - kCubicMargin;
+      float2 v = make_float2(0.0f, 0.0f);
+      if ((unsigned)pr < (unsigned)Np && (unsigned)pc < (unsigned)Np) v = src[(int64_t)pr * Np + pc];
+      band[r * ls + cc] = v;
+    }
     __syncthreads();
     if (!live) continue;
     for (int a = 0; a < n; ++a) {
       double stuy, ctuy;
       {
-#pragma clang fp contract(off)
         const double uy = (double)a - c;
         stuy = g.st * uy;
         ctuy = g.ct * uy;
@@ -212,42 +237,36 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
       for (int v = 0; v < E; ++v) {
         const int b = lane + 64 * v;
         if (!(FULL || b < n)) continue;
-        const double sy = mstux[v] + ctuy;
-        const double rowf = c + sy + pad;
+        const double rowf = c + (mstux[v] + ctuy) + pad;
         const double r0f = floor(rowf);
-        const int r0 = (int)r0f;
-        int rl = r0 - 1 > 0 ? r0 - 1 : 0;
-        int mine = rl / (H - 3);
-        if (mine > nbands - 1) mine = nbands - 1;
-        if (mine != bi) continue;
-        const double sx = ctux[v] + stuy;
-        const double colf = c + sx + pad;
+        int r0 = (int)r0f;  // |rowf| < 3n + pad: exact
+        r0 = r0 < -3 ? -3 : (r0 > Np + 1 ? Np + 1 : r0);
+        const int R = r0 + kCubicMargin - 1;  // extended row of the first tap
+        if (R < s0 || R > hi) continue;
+        const double colf = c + (ctux[v] + stuy) + pad;
         const double c0f = floor(colf);
-        const int c0 = (int)c0f;
+        int c0 = (int)c0f;
+        c0 = c0 < -3 ? -3 : (c0 > Np + 1 ? Np + 1 : c0);
         float wy[4], wx[4];
         cubic_weights(rowf - r0f, wy);
         cubic_weights(colf - c0f, wx);
-        // taps outside the padded array are zero: their weight is zeroed and
-        // their LDS address clamped into the band (no branches)
-        int rofs[4], cidx[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          const int r = r0 + d - 1, cc = c0 + d - 1;
-          if ((unsigned)r >= (unsigned)Np) wy[d] = 0.0f;
-          if ((unsigned)cc >= (unsigned)Np) wx[d] = 0.0f;
-          const int rb = r - s0;
-          rofs[d] = (rb < 0 ? 0 : (rb > rows - 1 ? rows - 1 : rb)) * Np;
-          cidx[d] = cc < 0 ? 0 : (cc > Np - 1 ? Np - 1 : cc);
-        }
-        float val = 0.0f;
+        const float2* t0 = band + (R - s0) * ls + (c0 + kCubicMargin - 1);
+        float X = 0.0f, Y = 0.0f;
 #pragma unroll
         for (int dr = 0; dr < 4; ++dr) {
-#pragma unroll
-          for (int dc = 0; dc < 4; ++dc) {
-            const float2 p = band[rofs[dr] + cidx[dc]];
-            val = fmaf(wy[dr] * wx[dc], fmaf(wk1, p.y, wk0 * p.x), val);
-          }
+          const float2* tr = t0 + dr * ls;
+          const float2 p0 = tr[0], p1 = tr[1], p2 = tr[2], p3 = tr[3];
+          float x = wx[0] * p0.x, y = wx[0] * p0.y;
+          x = fmaf(wx[1], p1.x, x);
+          y = fmaf(wx[1], p1.y, y);
+          x = fmaf(wx[2], p2.x, x);
+          y = fmaf(wx[2], p2.y, y);
+          x = fmaf(wx[3], p3.x, x);
+          y = fmaf(wx[3], p3.y, y);
+          X = fmaf(wy[dr], x, X);
+          Y = fmaf(wy[dr], y, Y);
         }
+        const float val = fmaf(wk1, Y, wk0 * X);
         __builtin_nontemporal_store(val, col + a * n + b);
         rowsum += val;
       }
@@ -311,16 +330,16 @@ hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo,
   BucketPlan bp;
   hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
-  const int Np = n + 2 * kSplinePad;
+  const int Np = n + 2 * kSplinePad, Ne = cubic_ext(Np), ls = cubic_stride(Np);
   const int H = cubic_band_rows(Np);
-  const int nbands = (H >= Np) ? 1 : (Np - 3 + (H - 3) - 1) / (H - 3);
-  const size_t lds = (size_t)H * Np * sizeof(float2);
+  const int nbands = (H >= Ne) ? 1 : (Ne - 3 + (H - 3) - 1) / (H - 3);
+  const size_t lds = (size_t)H * ls * sizeof(float2);
   const float2* P = reinterpret_cast<const float2*>(pairs);
   auto launch = [&](auto kern) -> hipError_t {
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
-    kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(P, Np, H, nbands, geo, bp.order, bp.items,
+    kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(P, Np, ls, H, nbands, geo, bp.order, bp.items,
                                                    bp.nitems, bp.nb, n, M, A32, tau);
     return hipGetLastError();
   };
