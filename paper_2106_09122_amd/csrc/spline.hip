@@ -91,6 +91,67 @@ __global__ __launch_bounds__(256) void spline_rows_kernel(int K, int Np, double*
   spline_line(T + t * Np, 1, Np);
 }
 
+// The same two passes with the lines staged in LDS: a workgroup loads a tile
+// of W lines (coalesced, all 4 waves), one lane per line runs the recursion
+// on LDS, and the tile is written back by all 4 waves.  The recursions are sequential
+// along a line, so this trades global-memory latency per step for LDS latency.
+// Column pass: tile = Np rows x W columns of one padded PSF, [row][column].
+__global__ __launch_bounds__(256) void spline_cols_lds_kernel(const float* __restrict__ cube, int n,
+                                                             int Np, int W,
+                                                             double* __restrict__ T) {
+  extern __shared__ double tile[];  // Np x W
+  const int nblk = (Np + W - 1) / W;
+  const int64_t k = blockIdx.x / nblk;
+  const int q0 = (int)(blockIdx.x % nblk) * W;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < Np * W; e += 256) {
+    const int i = e / W, dq = e - i * W;
+    const int a = i - kSplinePad, b = q0 + dq - kSplinePad;
+    const bool in = (unsigned)a < (unsigned)n && (unsigned)b < (unsigned)n;
+    tile[e] = in ? (double)cube[(k * n + a) * (int64_t)n + b] : 0.0;
+  }
+  __syncthreads();
+  if (tid < W && q0 + tid < Np) spline_line(tile + tid, W, Np);
+  __syncthreads();
+  double* dst = T + k * (int64_t)Np * Np;
+  for (int e = tid; e < Np * W; e += 256) {
+    const int i = e / W, dq = e - i * W;
+    if (q0 + dq < Np) dst[(int64_t)i * Np + q0 + dq] = tile[e];
+  }
+}
+
+// Row pass: tile = W rows of Np, row stride Np + 1 (an odd number of doubles
+// spreads the lanes' rows over the LDS banks).
+__global__ __launch_bounds__(256) void spline_rows_lds_kernel(int Np, int W,
+                                                             double* __restrict__ T) {
+  extern __shared__ double tile[];  // W x (Np + 1)
+  const int nblk = (Np + W - 1) / W;
+  const int64_t k = blockIdx.x / nblk;
+  const int i0 = (int)(blockIdx.x % nblk) * W;
+  const int rows = (Np - i0 < W) ? Np - i0 : W;
+  const int st = Np + 1;
+  const int tid = threadIdx.x;
+  double* src = T + (k * (int64_t)Np + i0) * Np;
+  for (int e = tid; e < rows * Np; e += 256) {
+    const int r = e / Np, c = e - r * Np;
+    tile[r * st + c] = src[e];
+  }
+  __syncthreads();
+  if (tid < rows) spline_line(tile + tid * st, 1, Np);
+  __syncthreads();
+  for (int e = tid; e < rows * Np; e += 256) {
+    const int r = e / Np, c = e - r * Np;
+    src[e] = tile[r * st + c];
+  }
+}
+
+// Lines per LDS tile (64, 32 or 16 lines of Np doubles), 0 if none fits.
+int spline_tile_lines(int Np) {
+  for (int W = 64; W >= 16; W >>= 1)
+    if ((size_t)W * (size_t)(Np + 1) * sizeof(double) <= (size_t)kLdsBuildMaxBytes) return W;
+  return 0;
+}
+
 // pairs[k][p] = (C_k[p], C_{k+1}[p]) in float32 (C_1 reads as 0 when K == 1).
 __global__ __launch_bounds__(256) void spline_pair_kernel(const double* __restrict__ T, int K,
                                                           int64_t P, float2* __restrict__ pairs) {
@@ -298,11 +359,28 @@ hipError_t launch_spline_pairs(const float* cube, int K, int n, void* scratch, f
   const int64_t P = (int64_t)Np * Np;
   double* T = reinterpret_cast<double*>(scratch);
   float2* pairs = reinterpret_cast<float2*>(const_cast<float*>(spline_pairs_of(scratch, K, n)));
-  const unsigned lines = (unsigned)(((int64_t)K * Np + 255) / 256);
-  spline_cols_kernel<<<lines, 256, 0, s>>>(cube, K, n, Np, T);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  spline_rows_kernel<<<lines, 256, 0, s>>>(K, Np, T);
+  const int W = spline_tile_lines(Np);
+  hipError_t e;
+  if (W > 0) {
+    const size_t lds = (size_t)W * (size_t)(Np + 1) * sizeof(double);
+    const unsigned tiles = (unsigned)((int64_t)K * ((Np + W - 1) / W));
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(spline_cols_lds_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(spline_rows_lds_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    spline_cols_lds_kernel<<<tiles, 256, lds, s>>>(cube, n, Np, W, T);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    spline_rows_lds_kernel<<<tiles, 256, lds, s>>>(Np, W, T);
+  } else {
+    const unsigned lines = (unsigned)(((int64_t)K * Np + 255) / 256);
+    spline_cols_kernel<<<lines, 256, 0, s>>>(cube, K, n, Np, T);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    spline_rows_kernel<<<lines, 256, 0, s>>>(K, Np, T);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = ((K > 1) ? (int64_t)(K - 1) : 1) * P;
