@@ -196,10 +196,12 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
  * Many scenes, each simulated with its own library (libraries of different
  * sizes or wavelengths), as one graph launch (Sec. 5: simulating many
  * complex scenes at once).  A plan lists work tiles over every (library,
- * group of up to 8 of its scenes, row block, column chunk); a persistent
- * kernel streams each library once from HBM and multiplies it with all the
- * scenes assigned to it; a second kernel adds the chunk partials in a fixed
- * order (bitwise reproducible).  Both launches are captured in a HIP graph.
+ * group of up to 16 of its scenes, row block, column chunk); a persistent
+ * kernel streams each library once per scene group from HBM and multiplies
+ * it with the group's scenes on the matrix cores; a second kernel adds the
+ * chunk partials in a fixed order (bitwise reproducible).  The scene groups
+ * are packed into the matrix-core operand at the start of every run.  All
+ * launches are captured in a HIP graph.
  *   h_libs          host array of nlibs built handles; all share one storage
  *                   form and device, and must outlive the plan.
  *   h_lib_of_scene  host int32 [B]: the library of each scene.
