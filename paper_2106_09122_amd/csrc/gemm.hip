@@ -22,9 +22,10 @@
 // columns ahead; accumulation is blocked in two levels so float32 rounding
 // chains stay short.
 //
-// 16-bit: a workgroup of 4 waves computes a 256 x 128 tile; each wave owns 64
-// image rows and all 128 scenes (2 x 4 accumulators of 32 x 32).  K advances
-// in stages of 32 columns through a 4-slot ring, three stages ahead of use:
+// 16-bit: a workgroup of 4 waves computes a 256 x TN tile (TN = 128 or 256
+// scenes); each wave owns 64 image rows and all TN scenes (2 x TN/32
+// accumulators of 32 x 32).  K advances in stages of 32 columns through a
+// 4-slot ring, three stages ahead of use:
 // library fragments (each used by one wave only) go from HBM straight into
 // registers, and the scene tile (shared by the 4 waves) is copied from a
 // group-major packed copy of the scenes into LDS by the buffer unit, with no
@@ -40,7 +41,6 @@ namespace psflib {
 constexpr int kGemmThreads = 256;
 constexpr int kGM = 256;  // FP32: image rows per workgroup (64 per wave)
 constexpr int kHM = 256;  // 16-bit: image rows per workgroup tile (64 per wave)
-constexpr int kHN = 128;  // 16-bit: scenes per workgroup tile
 constexpr int kHG = 4;    // 16-bit: 8-column groups per K stage (32 columns)
 constexpr int kMaxBatchChunk = 1024;  // scenes per internal pass (bounds the scratch)
 
@@ -372,43 +372,46 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 a, const u32x4 b, const f32
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-// The 16-bit GEMM.  Workgroup = 4 waves, tile 256 image rows x 128 scenes,
-// K stages of 32 columns (4 groups); each wave owns 64 rows and all 128 scenes
-// (2 x 4 accumulators of 32 x 32).  Operands of a stage travel on two paths
-// into a 4-slot ring, three stages ahead of use:
+// The 16-bit GEMM.  Workgroup = 4 waves, tile 256 image rows x TN scenes,
+// K stages of 32 columns (4 groups); each wave owns 64 rows and all TN scenes
+// (2 x TN/32 accumulators of 32 x 32: 128 registers at TN = 128, two
+// workgroups per CU; 256 at TN = 256, one).  Operands of a stage travel on
+// two paths into a 4-slot ring, three stages ahead of use:
 //   library fragments (each used by one wave only) go from memory straight to
 //   registers, 4 x 16 bytes per lane per stage;
 //   the scene tile (shared by the 4 waves) is copied from memory into LDS by
-//   the buffer unit (buffer_load ... lds), 2 KiB per wave per stage, with no
-//   register staging.
-// Each lane issues exactly 6 vector-memory operations per stage, and those
-// complete in issue order, so "at most 12 outstanding" means this wave's
-// copies for the stage about to be used have landed; the barrier after that
-// wait makes every wave's copies visible, and the lgkmcnt(0) before it ends
-// this wave's LDS reads of the slot the next copy overwrites.  Each ring slot
-// is its own LDS array, so the compiler can tell that the scene-fragment
-// reads of one slot do not alias the copies in flight into the others: it
-// waits only for the copy into the slot being read (the same "12 outstanding"
-// bound), and schedules the reads between the products with partial
-// lgkmcnt waits (at B = 512, one workgroup per CU, ~306 -> 272-290 us against
+//   the buffer unit (buffer_load ... lds), TN x 16 bytes per wave per stage
+//   (C = TN/64 copies per lane), with no register staging.
+// Each lane issues exactly 4 + C vector-memory operations per stage, and
+// those complete in issue order, so "at most 2 (4 + C) outstanding" means
+// this wave's copies for the stage about to be used have landed; the barrier
+// after that wait makes every wave's copies visible, and the lgkmcnt(0)
+// before it ends this wave's LDS reads of the slot the next copy overwrites.
+// Each ring slot is its own LDS array, so the compiler can tell that the
+// scene-fragment reads of one slot do not alias the copies in flight into
+// the others: it waits only for the copy into the slot being read (the same
+// bound), and schedules the reads between the products with partial lgkmcnt
+// waits (at B = 512, one workgroup per CU, ~306 -> 272-290 us against
 // whole-block reads that waited for all four fragments before any product).
 constexpr int kHRing = 4;    // ring slots
 constexpr int kHUnroll = 16; // stages per main-loop iteration (a multiple of kHRing)
 
-template <bool BF16>
-__global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
+template <bool BF16, int TN>
+__global__ __launch_bounds__(kGemmThreads, TN == 128 ? 2 : 1) void gemm_h16_kernel(
     const u32x4* Mp, const u32x4* Zg, const int32_t* __restrict__ fexp,
     float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t Bp, int64_t mblocks,
     int64_t nblocks, int64_t splits, int64_t stages_per_split) {
-  __shared__ u32x4 Bs0[kHG][kHN], Bs1[kHG][kHN], Bs2[kHG][kHN], Bs3[kHG][kHN];  // ring slots
-  auto slot_of = [&](int slot) -> u32x4 (*)[kHN] {
+  constexpr int NU = TN / 32;     // 32-scene accumulator columns per wave
+  constexpr int NC = TN / 64;     // LDS copies per lane per stage
+  __shared__ u32x4 Bs0[kHG][TN], Bs1[kHG][TN], Bs2[kHG][TN], Bs3[kHG][TN];  // ring slots
+  auto slot_of = [&](int slot) -> u32x4 (*)[TN] {
     return slot == 0 ? Bs0 : slot == 1 ? Bs1 : slot == 2 ? Bs2 : Bs3;
   };
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t tile = xcd_tile(blockIdx.x, mblocks * nblocks * splits);
   const int64_t nb = tile % nblocks, mb = (tile / nblocks) % mblocks, sp = tile / (nblocks * mblocks);
-  const int64_t m0 = mb * kHM, n0 = nb * kHN;
+  const int64_t m0 = mb * kHM, n0 = nb * TN;
   const int64_t nstages = ngroups / kHG;  // ngroups is a multiple of 8
   const int64_t st0 = sp * stages_per_split;
   const int64_t ns = (nstages - st0 < stages_per_split ? nstages - st0 : stages_per_split);
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
   const uint32_t offa0 = (uint32_t)((half * M + row0) * 16);
   const uint32_t offa1 = (uint32_t)((half * M + row1) * 16);
   const char* Ab = reinterpret_cast<const char*>(Mp);
-  // this wave copies group `wave` of each stage: scenes n0 .. n0+127
+  // this wave copies group `wave` of each stage: scenes n0 .. n0+TN-1
   const char* Zb = reinterpret_cast<const char*>(Zg + (int64_t)wave * Bp + n0);
   const int offb = lane * 16;
 
@@ -439,25 +442,25 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
     const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(Zb + st * kHG * Bp * 16), (short)0, 0x7FFFFFFF, 0x00020000);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < NC; ++h)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rb, (void __attribute__((address_space(3)))*)(&slot_of(slot)[wave][64 * h]), 16,
           offb + 1024 * h, 0, 0, 0);
   };
 
   const f32x16 zero16 = {};
-  f32x16 acc[2][4];
+  f32x16 acc[2][NU];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[t][u] = zero16;
+    for (int u = 0; u < NU; ++u) acc[t][u] = zero16;
 
-  u32x4 bf[2][4];
+  u32x4 bf[2][NU];
   auto readb = [&](int slot) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bf[ks][u] = slot_of(slot)[2 * ks + half][32 * u + (lane & 31)];
+      for (int u = 0; u < NU; ++u) bf[ks][u] = slot_of(slot)[2 * ks + half][32 * u + (lane & 31)];
   };
   auto compute = [&](int slot) {
 #pragma unroll
@@ -465,12 +468,16 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = mfma16<BF16>(a[slot][ks][t], bf[ks][u], acc[t][u]);
+        for (int u = 0; u < NU; ++u) acc[t][u] = mfma16<BF16>(a[slot][ks][t], bf[ks][u], acc[t][u]);
   };
   // stage ls: issue stage ls + 3 (clamped to the last one: the extra copies
   // land in a slot nobody reads again) and multiply stage ls
   auto step = [&](int64_t ls, int j) {
-    asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    // 4 + NC operations per stage, two stages issued after this one
+    if constexpr (NC == 2)
+      asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(16) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     readb(j % kHRing);
     const int64_t nx = ls + kHRing - 1;
     issue(nx < ns ? nx : ns - 1, (j + kHRing - 1) % kHRing);
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_h16_kernel(
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < NU; ++u)
       store_acc(acc[t][u], dst, M, B, m0 + 64 * wave + 32 * t, n0 + 32 * u, lane, fexp, !split);
 }
 
@@ -517,6 +524,13 @@ struct GemmPlan {
   int64_t mblocks, nblocks, kunits, splits, per;  // kunits: 8-column groups (FP32) or K stages (16-bit)
 };
 
+// 16-bit scene-tile width: 256 scenes (one workgroup per CU, 2 x 8
+// accumulators per wave) for 128 < B <= 256, where it is ~5% faster than two
+// 128-wide tiles; else 128 (two workgroups per CU).  At B <= 128 half of a
+// 256-wide tile would be padding; at B = 512 a 256-wide grid has to split K
+// and add the partials; at B = 1024 the two widths measured within noise.
+static int64_t h16_tile(int64_t bc) { return (bc > 128 && bc <= 256) ? 256 : 128; }
+
 // FP32 scene blocks of 32 per workgroup tile: 1 for batches of at most 32
 static int f32_nb(int64_t bc) { return bc <= 32 ? 1 : 2; }
 
@@ -529,7 +543,7 @@ static int64_t f32_scene_blocks(int64_t bc) {
 static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int64_t bc) {
   GemmPlan p;
   const bool f32 = storage == PSFLIB_FP32;
-  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? 32 * f32_nb(bc) : kHN;
+  const int64_t tm = f32 ? kGM : kHM, tn = f32 ? 32 * f32_nb(bc) : h16_tile(bc);
   p.mblocks = (M + tm - 1) / tm;
   p.nblocks = (bc + tn - 1) / tn;
   p.kunits = f32 ? (ncols + 7) / 8 : (ncols_pad / 8) / kHG;
@@ -577,7 +591,7 @@ static hipError_t launch_gemm_f32(int variant, unsigned grid, const float* A, co
 static int64_t chunk_of(int B) { return B < kMaxBatchChunk ? B : kMaxBatchChunk; }
 
 // scenes per group row of the packed 16-bit scene copy (whole scene tiles)
-static int64_t padded_batch(int64_t bc) { return (bc + kHN - 1) / kHN * kHN; }
+static int64_t padded_batch(int64_t bc) { return (bc + h16_tile(bc) - 1) / h16_tile(bc) * h16_tile(bc); }
 
 static size_t split_partial_bytes(int storage, int64_t M, int64_t ncols, int64_t ncols_pad,
                                   int64_t bc) {
@@ -673,12 +687,21 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
-      if (bf)
-        gemm_h16_kernel<true><<<grid, kGemmThreads, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, bc, Bp,
-                                                            p.mblocks, p.nblocks, p.splits, p.per);
-      else
-        gemm_h16_kernel<false><<<grid, kGemmThreads, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, bc, Bp,
-                                                             p.mblocks, p.nblocks, p.splits, p.per);
+      if (h16_tile(bc) == 256) {
+        if (bf)
+          gemm_h16_kernel<true, 256><<<grid, kGemmThreads, 0, s>>>(
+              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
+        else
+          gemm_h16_kernel<false, 256><<<grid, kGemmThreads, 0, s>>>(
+              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
+      } else {
+        if (bf)
+          gemm_h16_kernel<true, 128><<<grid, kGemmThreads, 0, s>>>(
+              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
+        else
+          gemm_h16_kernel<false, 128><<<grid, kGemmThreads, 0, s>>>(
+              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
+      }
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
