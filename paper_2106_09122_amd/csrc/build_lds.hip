@@ -270,11 +270,15 @@ __global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict
 // [b (H-1), b (H-1) + H).  The two tap rows of an output pixel, R = r0 + 1
 // and R + 1, both lie in band b when b (H-1) <= R <= b (H-1) + H - 2 (the
 // last band takes every R up to n), so each pixel is produced in exactly one
-// band; pixels whose taps miss the array in the row direction are written as
-// zeros in band 0.  Per band, every lane first forms the pixel's row
-// coordinate (the oracle's float64 operations) to test membership and does
-// the rest of the element's work only for pixels of that band.  Stores go to
-// the same columns as in the unbanded kernel, each element written once.
+// band; pixels whose taps miss the array in the row direction are zeros,
+// written in the first band (R < 0) or the last (R > n).  Per band and block
+// of 64 image columns, a conservative range of image rows that can reach the
+// band is derived from the column's angle (the extreme source rows of the
+// block's end pixels, with a margin); over those rows every lane forms its
+// pixel's row coordinate (the oracle's float64 operations) to test membership
+// exactly, and does the rest of the element's work only for pixels of the
+// band.  Stores go to the same columns as in the unbanded kernel, each
+// element written once.
 template <int E, bool FULL>
 __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restrict__ cube, int K,
                                                           const ColGeom* __restrict__ geo,
@@ -361,7 +365,41 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
     }
     __syncthreads();
     if (!live) continue;
-    for (int a = 0; a < n; ++a) {
+    // Rows a whose pixels in lane block v can have R in [lo, hi] (the first
+    // band open below, the last open above): the source row is
+    // c - st (b - c) + ct (a - c) up to rounding, so over the block's ends
+    // b0, b1 it spans [c + m1 + ct (a - c), c + m2 + ct (a - c)], which must meet
+    // [lo - 1, hi + 1] (a margin of a row on each side, and 1e-6).
+    int alo[E], ahi[E], afirst = n, alast = -1;
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      const double b0 = (double)(64 * v) - c;
+      const double b1 = (double)((64 * v + 63 < n - 1) ? 64 * v + 63 : n - 1) - c;
+      const double t0 = -g.st * b0, t1 = -g.st * b1;
+      const double m1 = fmin(t0, t1), m2 = fmax(t0, t1);
+      const double LO = (bi == 0) ? -1e30 : (double)lo - 1.0 - 1e-6;
+      const double HI = (bi == nbands - 1) ? 1e30 : (double)hi + 1.0 + 1e-6;
+      const double U1 = LO - c - m2, U2 = HI - c - m1;  // need U1 <= ct (a - c) <= U2
+      double amin, amax;
+      if (g.ct > 1e-9) {
+        amin = c + U1 / g.ct;
+        amax = c + U2 / g.ct;
+      } else if (g.ct < -1e-9) {
+        amin = c + U2 / g.ct;
+        amax = c + U1 / g.ct;
+      } else {  // |ct| tiny: ct (a - c) is ~0 for every row
+        const bool any = U1 <= 1e-6 && U2 >= -1e-6;
+        amin = any ? -1e30 : 1e30;
+        amax = any ? 1e30 : -1e30;
+      }
+      amin = fmax(floor(amin) - 1.0, 0.0);
+      amax = fmin(ceil(amax) + 1.0, (double)(n - 1));
+      alo[v] = __builtin_amdgcn_readfirstlane((int)fmin(amin, (double)n));
+      ahi[v] = __builtin_amdgcn_readfirstlane((int)fmax(amax, -1.0));
+      afirst = alo[v] < afirst ? alo[v] : afirst;
+      alast = ahi[v] > alast ? ahi[v] : alast;
+    }
+    for (int a = afirst; a <= alast; ++a) {
       double stuy, ctuy;
       {
 #pragma clang fp contract(off)
@@ -372,6 +410,7 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
       float rowsum = 0.0f;
 #pragma unroll
       for (int v = 0; v < E; ++v) {
+        if (a < alo[v] || a > ahi[v]) continue;  // uniform
         const int b = lane + 64 * v;
         if (!(FULL || b < n)) continue;
         int R;
@@ -383,7 +422,8 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
           R = (int)floor(rowf) + 1;  // |rowf| < 3n: exact
         }
         const bool rok = (unsigned)R <= (unsigned)n;
-        if (rok ? (R < lo || R > hi) : bi != 0) continue;
+        const int Rc = R < 0 ? 0 : (R > n ? n : R);  // rows off the array: first or last band
+        if (Rc < lo || Rc > hi) continue;
         double colf;
         {
 #pragma clang fp contract(off)

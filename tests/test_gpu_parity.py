@@ -161,6 +161,7 @@ SHAPES = [
     # bordered PSF pairs larger than the LDS: staged in row bands (2, 3 and 4
     # bands; 199 also takes the scalar staging loads and partial lanes)
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
+    (150, 33, 0.3, 6, "linear", "linear", "zero"),   # 1089 position angles
     (199, 4, 0.5, 3, "nonuniform", "linear", "zero"),
     (256, 3, 0.9, 3, "linear", "linear", "clamp"),
     # PSFs larger than 256 x 256 take the gather path
@@ -230,3 +231,31 @@ def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
     for b in range(5):
         assert np.max(np.abs(outb[b] - refb[b])) <= 2 * u * np.max(np.abs(refb[b])) + 1e-30
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+def test_batched_multi_pass(torch, psflib, storage):
+    """More scenes than one internal pass holds (1024): the batch runs as a
+    full pass and a short one (each with its own tile shape and K split);
+    every image must match the oracle, and so must the tail run alone."""
+    n, N, S, K = 20, 18, 0.4, 5
+    cube, radii, rng = _shape_inputs(n, N, S, K, "nonuniform", 4242)
+    A = O.build_library(cube, radii, N, S)
+    lib = _lib(torch, psflib, cube, radii, N, S, storage=storage)
+    B = 1100
+    Zb = rng.random((B, N * N)).astype(np.float32)
+    out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    ref = O.apply_batched(A, Zb)
+    if storage == "fp32":
+        assert _rel_err_pos(out, ref) <= FP32_REL
+    else:
+        u = U16[storage]
+        err = np.max(np.abs(out - ref), axis=1) / np.max(np.abs(ref), axis=1)
+        assert np.max(err) <= 2 * u
+    tail = lib.apply_batched(torch.from_numpy(Zb[1024:]).cuda()).cpu().numpy()
+    if storage == "fp32":
+        assert _rel_err_pos(tail, ref[1024:]) <= FP32_REL
+    else:
+        err = np.max(np.abs(tail - ref[1024:]), axis=1) / np.max(np.abs(ref[1024:]), axis=1)
+        assert np.max(err) <= 2 * U16[storage]
+    lib.close()
