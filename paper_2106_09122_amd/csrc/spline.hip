@@ -219,13 +219,18 @@ __host__ __device__ inline int cubic_band_rows(int Np) {
 // the 4 tap rows of a pixel, from its (clamped) origin row R - 1 on, all lie
 // in band min((R - 1) / (H-3), last), so each pixel is produced in exactly
 // one band.  A work item is up to kLdsCols columns of one bracket (columns
-// grouped on the device), one wave per column, lane l owning image columns
-// l, l+64, ...  Coordinates and B-spline weights in float64 (weights rounded
-// once to float32); the 16 taps are summed separably in float32 — each row's
-// weighted sum of the k and k+1 coefficients, those rows weighted, then the
-// radial blend — in the same order as the gather form, so both give identical
-// values.
-template <int E, bool FULL>
+// grouped on the device), one wave per column.  A wave walks its column in
+// tiles of 8 x 8 image pixels (lane l: row 8 a' + l / 8, column 8 b' + l % 8),
+// so the 64 stencils of one LDS read cover a compact rotated patch of the
+// array rather than a 64-pixel line: with the row stride at 5 mod 8 pairs
+// their 16-byte reads spread over the banks at any angle.  A store
+// instruction writes 8 runs of 32 bytes; plain stores let L2 merge the runs
+// of neighbouring tiles into whole lines (non-temporal ones were ~11% slower
+// end to end).  Coordinates and
+// B-spline weights in float64 (weights rounded once to float32); the 16 taps
+// are summed separably in float32 — each row's weighted sum of the k and k+1
+// coefficients, those rows weighted, then the radial blend — in the same
+// order as the gather form, so both give identical values.
 __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
     const float2* __restrict__ pairs, int Np, int ls, int H, int nbands,
     const ColGeom* __restrict__ geo, const int32_t* __restrict__ order,
@@ -237,16 +242,14 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
   const int4 it = items[blockIdx.x];
   const int bkt = it.x, start = it.y, len = it.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane >> 3, lj = lane & 7;  // row and column of the lane in its tile
+  const int nt = (n + 7) / 8;               // tiles per side
   if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
     if (wave >= len) return;
     const int64_t j = order[start + wave];
     float* col = A + j * M;
     for (int a = 0; a < n; ++a)
-#pragma unroll
-      for (int v = 0; v < E; ++v) {
-        const int b = lane + 64 * v;
-        if (FULL || b < n) __builtin_nontemporal_store(0.0f, col + a * n + b);
-      }
+      for (int b = lane; b < n; b += 64) __builtin_nontemporal_store(0.0f, col + a * n + b);
     if (lane == 0) tau[j] = 0.0;
     return;
   }
@@ -263,13 +266,6 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
   float* col = A + j * M;
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
-  double ctux[E], mstux[E];
-#pragma unroll
-  for (int v = 0; v < E; ++v) {
-    const double ux = (double)(lane + 64 * v) - c;
-    ctux[v] = g.ct * ux;
-    mstux[v] = (-g.st) * ux;
-  }
   const double pad = (double)kSplinePad;
   double tsum = 0.0;
   for (int bi = 0; bi < nbands; ++bi) {
@@ -286,25 +282,25 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
     }
     __syncthreads();
     if (!live) continue;
-    for (int a = 0; a < n; ++a) {
+    for (int ta = 0; ta < nt; ++ta) {
+      const int a = 8 * ta + li;
       double stuy, ctuy;
       {
         const double uy = (double)a - c;
         stuy = g.st * uy;
         ctuy = g.ct * uy;
       }
-      float rowsum = 0.0f;
-#pragma unroll
-      for (int v = 0; v < E; ++v) {
-        const int b = lane + 64 * v;
-        if (!(FULL || b < n)) continue;
-        const double rowf = c + (mstux[v] + ctuy) + pad;
+      for (int tb = 0; tb < nt; ++tb) {
+        const int b = 8 * tb + lj;
+        if (a >= n || b >= n) continue;
+        const double ux = (double)b - c;
+        const double rowf = c + ((-g.st) * ux + ctuy) + pad;
         const double r0f = floor(rowf);
         int r0 = (int)r0f;  // |rowf| < 3n + pad: exact
         r0 = r0 < -3 ? -3 : (r0 > Np + 1 ? Np + 1 : r0);
         const int R = r0 + kCubicMargin - 1;  // extended row of the first tap
         if (R < s0 || R > hi) continue;
-        const double colf = c + (ctux[v] + stuy) + pad;
+        const double colf = c + (g.ct * ux + stuy) + pad;
         const double c0f = floor(colf);
         int c0 = (int)c0f;
         c0 = c0 < -3 ? -3 : (c0 > Np + 1 ? Np + 1 : c0);
@@ -328,10 +324,9 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
           Y = fmaf(wy[dr], y, Y);
         }
         const float val = fmaf(wk1, Y, wk0 * X);
-        __builtin_nontemporal_store(val, col + a * n + b);
-        rowsum += val;
+        col[a * n + b] = val;
+        tsum += (double)val;
       }
-      tsum += (double)rowsum;
     }
   }
   if (!live) return;
@@ -421,13 +416,7 @@ hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo,
                                                    bp.nitems, bp.nb, n, M, A32, tau);
     return hipGetLastError();
   };
-  const bool full = (n % 64) == 0;
-  switch ((n + 63) / 64) {
-    case 1: return full ? launch(build_cubic_lds_kernel<1, true>) : launch(build_cubic_lds_kernel<1, false>);
-    case 2: return full ? launch(build_cubic_lds_kernel<2, true>) : launch(build_cubic_lds_kernel<2, false>);
-    case 3: return full ? launch(build_cubic_lds_kernel<3, true>) : launch(build_cubic_lds_kernel<3, false>);
-    default: return full ? launch(build_cubic_lds_kernel<4, true>) : launch(build_cubic_lds_kernel<4, false>);
-  }
+  return launch(build_cubic_lds_kernel);
 }
 
 }  // namespace psflib
