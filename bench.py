@@ -9,8 +9,8 @@ simulated scene.  The same run also times every other part of the hot path
 (library build in each storage form, the 16-bit scaled products, the
 adjoint, the batched matrix-core products) and prints them under "rows".
 
-Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one
-GPU.
+Prints ONE JSON line.  ``--gpus`` above 1 is refused: the operator has no
+multi-GPU path, so the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -175,8 +175,8 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the operator is "
-              "not sharded in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the operator "
+              "has no multi-GPU path (sharding is described, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
