@@ -274,6 +274,25 @@ def main():
         t_fit = _timed(torch, lambda: fit.loss_and_grad(lib, th0, ct, vt, Kc, 8.0), 50, 5)
         rows["fit_step_fp32"] = {"ms": t_fit, "steps_per_s": 1e3 / t_fit,
                                  "note": "render + A Z + chi2 + A^T g + render gradient"}
+        # the paper's own shape (its IPAC set): 128^2 PSFs at 0.2 lambda/D with 86
+        # non-uniform offsets to 11 lambda/D, a 256^2 scene at 3.529 mas: a
+        # 16384 x 65536 library (4 GiB FP32); the paper's CPU times for this
+        # shape (FP64, 8 cores) are quoted beside it as context
+        dp = synth.config_inputs(6)
+        cp = torch.from_numpy(dp["cube"]).to(dev)
+        zp = torch.from_numpy(dp["scene"]).to(dev)
+        lp = psflib.Library(cp, dp["radii"], dp["N"], dp["S"], storage="fp32")
+        t_bp = _time_build(torch, psflib, lp.desc, cp, dp["radii"], lp.buf, lp.nbytes)
+        ip = torch.empty(dp["n"] ** 2, dtype=torch.float32, device=dev)
+        t_ap = _timed(torch, lambda: lp.apply(zp, out=ip), 100, 10)
+        pbytes = dp["n"] ** 2 * dp["N"] ** 2 * 4
+        rows["paper_shape_fp32"] = {
+            "shape": "n=128 (s=0.2 lambda/D), N=256 (S=3.529 mas), 86 non-uniform offsets, A 16384 x 65536",
+            "build_ms": t_bp, "apply_ms": t_ap, "apply_GB_per_s": pbytes / (t_ap * 1e-3) / 1e9,
+            "paper_cpu_fp64_build_s": 506.680, "paper_cpu_fp64_apply_s": 0.1642,
+            "paper_source": "Table 2 (IPAC, linear, time to create) and Table 4 (IPAC, linear)"}
+        lp.close()
+        del lp, cp, zp, ip
         # mixed sizes and wavelengths: 256 scenes over 33 libraries, one graph launch
         libs_m, scene_lib, scenes_m = synth.mixed_workload()
         Zm = [torch.from_numpy(z).to(dev) for z in scenes_m]

@@ -203,6 +203,11 @@ CONFIGS = {
     4: dict(n=128, N=128, s=0.125, S=0.125, K=64, planets=0),
     # large library 256x256 (65536 x 65536)
     5: dict(n=256, N=256, s=0.0625, S=0.0625, K=128, planets=0),
+    # the paper's own shape (its IPAC set, Sec. 4): 128x128 PSFs at 0.2 lambda/D
+    # with the IPAC offset pattern to 11 lambda/D, a 256x256 scene at
+    # 3.529 mas = 0.2 * 3.529 / 10.0379 lambda/D (Eq. 1's 0.2 lambda/D =
+    # 10.0379 mas): a 16384 x 65536 library
+    6: dict(n=128, N=256, s=0.2, S=0.2 * 3.529 / 10.0379, K=None, planets=3),
 }
 
 
@@ -211,7 +216,7 @@ def config_inputs(config: int, *, with_cube: bool = True) -> dict:
 
     Returns dict(n, N, s, S, radii[K] f64, cube[K][n][n] f32, scene[N*N] f32)."""
     p = dict(CONFIGS[config])
-    radii = radii_linspace(p["K"], 8.0)
+    radii = radii_nonuniform() if p["K"] is None else radii_linspace(p["K"], 8.0)
     out = dict(n=p["n"], N=p["N"], s=p["s"], S=p["S"], radii=radii)
     if with_cube:
         out["cube"] = psf_cube(p["n"], p["s"], radii, rng=rng_for(config, STREAM_ABERR))

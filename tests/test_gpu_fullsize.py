@@ -153,3 +153,27 @@ def test_c2_batched_dense(torch, c2, dense, storage):
             err = np.max(np.abs(out - r), axis=1) / np.max(np.abs(r), axis=1)
             assert np.max(err) <= 2 * U16[storage], (B, np.max(err))
     lib.close()
+
+
+def test_paper_shape_sampled(torch):
+    """The paper's own shape (128^2 PSFs at 0.2 lambda/D with the non-uniform
+    IPAC offsets, a 256^2 scene at 3.529 mas: n != N, s != S, a 16384 x 65536
+    library) on 64 seeded columns and a scene supported on them."""
+    from paper_2106_09122_amd import psflib
+    d = synth.config_inputs(6)
+    N = d["N"]
+    rng = synth.rng_for(6, synth.STREAM_SUBSAMPLE)
+    cols = np.sort(rng.choice(N * N, 64, replace=False))
+    Aref = O.build_library(d["cube"], d["radii"], N, d["S"], columns=cols)
+    lib = psflib.Library(torch.from_numpy(d["cube"]).cuda(), d["radii"], N, d["S"])
+    got = lib.get_columns(cols).cpu().numpy().T.astype(np.float64)
+    pos = Aref > 0
+    assert np.all(got[~pos] == 0)
+    assert np.max(np.abs(got[pos] - Aref[pos]) / Aref[pos]) <= LIB_REL
+    Zs = _sparse_scenes(cols, N * N, 1, 61)[0]
+    ref = Aref @ Zs[cols].astype(np.float64)
+    img = lib.apply(torch.from_numpy(Zs).cuda()).cpu().numpy()
+    pos = ref > 0
+    assert np.all(img[~pos] == 0)
+    assert np.max(np.abs(img[pos] - ref[pos]) / ref[pos]) <= FP32_REL
+    lib.close()
