@@ -29,6 +29,11 @@
 namespace psflib {
 
 // ------------------------------------------------------------ buckets -----
+__global__ __launch_bounds__(256) void zero_ints_kernel(int32_t* __restrict__ p, int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
 // bucket of column j: its bracket k, or nb-1 for an identically zero column.
 // Counts are gathered in an LDS histogram per workgroup and added to the
 // global counts with one atomic per non-empty bucket (few buckets, many
@@ -576,7 +581,10 @@ hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* sc
   int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
   p += ((size_t)items_max * 16 + 16 + 255) & ~(size_t)255;
   int32_t* order = reinterpret_cast<int32_t*>(p);
-  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)nb * 4 * 2, s);  // cnt and cursor
+  // cnt and cursor start at zero (a fill kernel, not hipMemsetAsync, so a
+  // captured build replays correctly)
+  zero_ints_kernel<<<(unsigned)((2 * nb + 255) / 256), 256, 0, s>>>(cnt, 2 * nb);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const unsigned cgrid = (unsigned)((ncols + 255) / 256);
   bucket_count_kernel<<<cgrid, 256, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt);
