@@ -214,7 +214,8 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
  *                   fastest; the choice is cached per plan shape for the
  *                   process.  Zero: use the cached or default choice.
  * Synchronises `stream` once (libraries built on it must be complete) and
- * allocates the plan's device tables and partials (hipMalloc). */
+ * allocates the plan's device tables and partials (hipMalloc).  FP32 plans
+ * take libraries with n*n <= 2^25 (n <= 5792; PSFLIB_ERR_UNSUPPORTED beyond). */
 typedef struct psflib_grouped psflib_grouped;
 psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t nlibs,
                                     const int32_t* h_lib_of_scene, const float* const* h_scenes,

@@ -87,10 +87,12 @@ __device__ __forceinline__ void grouped_f32_item(const GItem& w, const f32x4* __
   const int64_t m0 = w.row0 + 64 * wave;
   if (m0 >= w.M) return;  // no barriers: a wave past the image leaves at once
   const int n = lane & 15, q = lane >> 4;
+  // 16 columns of M floats span < 2^31 bytes (M <= 2^25, checked when the plan is made)
   const int M4 = (int)(w.M * 4);
   uint32_t voff[4];
 #pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4) voff[s4] = (uint32_t)((4 * s4 + q) * M4 + (m0 + 4 * n) * 4);
+  for (int s4 = 0; s4 < 4; ++s4)
+    voff[s4] = (uint32_t)((int64_t)(4 * s4 + q) * w.M * 4 + (m0 + 4 * n) * 4);
   const float* A = reinterpret_cast<const float*>(w.A);
   const int b0 = (int)(w.j0 / 16), b1 = (int)((w.j1 + 15) / 16);
   const int ncols = (int)w.ncols;
@@ -613,6 +615,9 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
     if (st != storage)
       return psflib::fail_status(PSFLIB_ERR_UNSUPPORTED, "grouped: all libraries must share one storage form");
     if (d != dev) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: libraries on different devices");
+    if (st == PSFLIB_FP32 && li.M > ((int64_t)1 << 25))
+      return psflib::fail_status(PSFLIB_ERR_UNSUPPORTED,
+                                 "grouped: FP32 libraries need n*n <= 2^25 (n <= 5792)");
     libs.push_back(li);
   }
   for (int b = 0; b < B; ++b) {
