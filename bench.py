@@ -252,14 +252,17 @@ def main():
                                       "column_scale_max": float(sc.max())}
         lf.close()
         del lf
-        for B in (64, 256):
+        for B in (1, 8, 64, 256):
             Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
             out = torch.empty((B, M), device=dev, dtype=torch.float32)
             t_b = _timed(torch, lambda: lib.apply_batched(Zb, out=out), 10, 3)
             fl = 2.0 * M * ncols * B
-            rows[f"batched_fp32_B{B}"] = {
-                "ms": t_b, "scenes_per_s": B / (t_b * 1e-3), "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
-                "frac_mfma_fp32": fl / (t_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+            ent = {"ms": t_b, "scenes_per_s": B / (t_b * 1e-3), "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
+                   "frac_mfma_fp32": fl / (t_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+            if B < 40:  # below the ridge (157.3 TF / 8 TB/s): the library read binds
+                gbs = (lib_bytes + 4 * B * (M + ncols)) / (t_b * 1e-3) / 1e9
+                ent.update({"bound": "hbm", "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS})
+            rows[f"batched_fp32_B{B}"] = ent
             del Zb, out
         # differentiation: one fitting step (render disk, simulate, chi-square,
         # backward through the adjoint and the renderer) on the 128^2 library
@@ -293,6 +296,33 @@ def main():
             "paper_source": "Table 2 (IPAC, linear, time to create) and Table 4 (IPAC, linear)"}
         lp.close()
         del lp, cp, zp, ip
+        # the large library (256^2 PSFs and scene, 128 PSFs: 65536 x 65536, 2^32
+        # entries): build, matvec and a 64-scene batched product, FP32 and BF16
+        d5 = synth.config_inputs(5)
+        c5 = torch.from_numpy(d5["cube"]).to(dev)
+        z5 = torch.from_numpy(d5["scene"]).to(dev)
+        M5, K5 = d5["n"] ** 2, d5["N"] ** 2
+        Zb5 = torch.from_numpy(synth.scene_batch(d5["N"], d5["S"], 64, config=5, rmax_mask=8.0)).to(dev)
+        o5 = torch.empty((64, M5), device=dev, dtype=torch.float32)
+        i5 = torch.empty(M5, device=dev, dtype=torch.float32)
+        ent5 = {"shape": "n = N = 256, 128 PSFs: A 65536 x 65536 (2^32 entries)"}
+        for fmt in ("fp32", "bf16"):
+            l5 = psflib.Library(c5, d5["radii"], d5["N"], d5["S"], storage=fmt)
+            t_b5 = _time_build(torch, psflib, l5.desc, c5, d5["radii"], l5.buf, l5.nbytes, reps=2)
+            t_a5 = _timed(torch, lambda: l5.apply(z5, out=i5), 20, 3)
+            t_g5 = _timed(torch, lambda: l5.apply_batched(Zb5, out=o5), 3, 1)
+            abytes = M5 * K5 * (4 if fmt == "fp32" else 2)
+            fl = 2.0 * M5 * K5 * 64
+            ent5[fmt] = {"build_ms": t_b5, "apply_ms": t_a5,
+                         "apply_GB_per_s": abytes / (t_a5 * 1e-3) / 1e9,
+                         "batched_B64_ms": t_g5,
+                         "batched_B64_TFLOP_per_s": fl / (t_g5 * 1e-3) / 1e12,
+                         "batched_B64_frac_mfma": fl / (t_g5 * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[fmt],
+                         "batched_B64_GB_per_s": abytes / (t_g5 * 1e-3) / 1e9}
+            l5.close()
+            del l5
+        rows["large_256"] = ent5
+        del c5, z5, Zb5, o5, i5
         # mixed sizes and wavelengths: 256 scenes over 33 libraries, one graph launch
         libs_m, scene_lib, scenes_m = synth.mixed_workload()
         Zm = [torch.from_numpy(z).to(dev) for z in scenes_m]
