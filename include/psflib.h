@@ -167,8 +167,10 @@ psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, flo
  * FP32 storage runs float32 matrix-core products; the 16-bit forms round each
  * scene to the storage format with a per-scene power-of-two scale (so the
  * scaled scene spans [2^14, 2^15) at its largest) and run 16-bit matrix-core
- * products with float32 accumulation.  Allocates stream-ordered scratch for
- * the 16-bit forms. */
+ * products with float32 accumulation.  B = 1 runs psflib_apply instead (the
+ * matvec streams the library faster).  Allocates stream-ordered scratch from
+ * the library's device memory pool (fragment-major scene copies, K-split
+ * partials). */
 psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
                                    int32_t B, void* stream);
 

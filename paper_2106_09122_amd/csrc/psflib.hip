@@ -359,6 +359,8 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
   if (B < 0) return fail(PSFLIB_ERR_INVALID_ARG, "B must be >= 0");
   if (B == 0) return PSFLIB_OK;
   if (!d_scenes || !d_images) return fail(PSFLIB_ERR_INVALID_ARG, "d_scenes and d_images must be non-NULL");
+  // one scene: the matvec streams the library faster than a one-scene product
+  if (B == 1) return psflib_apply(h, d_scenes, d_images, stream);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t bytes = psflib::batched_scratch_bytes(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad, B);
   void* scratch = nullptr;
