@@ -6,8 +6,10 @@
 // of scaled columns.  It is split over (row block, column chunk) workgroups:
 // each thread owns 4 consecutive rows and walks the chunk's columns with 16
 // independent 16-byte non-temporal loads in flight, and writes a partial
-// image; the last workgroup of each row block adds the partials in a fixed
-// order.  Sums are blocked (16 columns per inner sum) so every rounding chain
+// image; a second kernel adds the partials of every row in chunk order.  (Doing
+// that sum in the last workgroup to finish each row block needs a device-scope
+// release per workgroup, which writes back the XCD's L2: measured slower than
+// the extra launch.)  Sums are blocked (16 columns per inner sum) so every rounding chain
 // stays short.  Results are bitwise reproducible.
 #include <math.h>
 #include <stdlib.h>

@@ -166,9 +166,11 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
   auto issue = [&](int g, int slot) {
     const bool live = g < g1;
     const int gc = live ? g : g1 - 1;
-    // a whole group spans 8 columns (8 M floats < 2^31 bytes); the last may be partial
+    // the descriptor ends with the group's last live column (8 M floats <= 2^31
+    // bytes; the record count is an unsigned 32-bit field): rows a wave reads
+    // past the image read zero there, never past the library
     const int left = (int)(K - 8 * (int64_t)gc);
-    const int abytes = !live ? 0 : left >= 8 ? 0x7FFFFFFF : (int)((uint32_t)left * colbytes);
+    const int abytes = !live ? 0 : (int)((uint32_t)(left < 8 ? left : 8) * colbytes);
     const __amdgpu_buffer_rsrc_t ra_d = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(A + 8 * (int64_t)gc * M), (short)0, abytes, 0x00020000);
     const __amdgpu_buffer_rsrc_t rb_d = __builtin_amdgcn_make_buffer_rsrc(

@@ -100,8 +100,11 @@ __device__ __forceinline__ void grouped_f32_item(const GItem& w, const f32x4* __
   auto issue = [&](int b, int slot) {
     const bool live = b < b1;
     const int bc = live ? b : b1 - 1;
+    // the descriptor ends with the block's last library column: rows a wave
+    // reads past the image read zero there, never past the library
     const int left = ncols - 16 * bc;  // columns of the library from this block on
-    const int abytes = !live ? 0 : left >= 16 ? 0x7FFFFFFF : left * M4;
+    // (the record count is an unsigned 32-bit field: 16 M4 <= 2^31 fits)
+    const int abytes = !live ? 0 : (int)((uint32_t)(left < 16 ? left : 16) * (uint32_t)M4);
     const __amdgpu_buffer_rsrc_t ad = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(A + (int64_t)16 * bc * w.M), (short)0, abytes, 0x00020000);
     const __amdgpu_buffer_rsrc_t bd = __builtin_amdgcn_make_buffer_rsrc(
