@@ -142,7 +142,9 @@ def dense(c2):
 def test_c2_batched_dense(torch, c2, dense, storage):
     Zb, ref = dense
     lib = _build(torch, c2, storage)
-    for B in (20, 64, 256, 512):  # every K-split shape, down to no split (the longest chains)
+    # a few scenes (mostly-padding tiles, the most K slices), then every K-split
+    # shape of the GEMMs down to no split (the longest chains)
+    for B in (2, 3, 5, 8, 20, 64, 256, 512):
         out = lib.apply_batched(torch.from_numpy(Zb[:B]).cuda()).cpu().numpy().astype(np.float64)
         r = ref[:B]
         if storage == "fp32":
@@ -176,4 +178,11 @@ def test_paper_shape_sampled(torch):
     pos = ref > 0
     assert np.all(img[~pos] == 0)
     assert np.max(np.abs(img[pos] - ref[pos]) / ref[pos]) <= FP32_REL
+    # a few scenes at once (more columns than image rows)
+    Zb = _sparse_scenes(cols, N * N, 6, 62)
+    refb = Zb[:, cols].astype(np.float64) @ Aref.T
+    out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    pos = refb > 0
+    assert np.all(out[~pos] == 0)
+    assert np.max(np.abs(out[pos] - refb[pos]) / refb[pos]) <= FP32_REL
     lib.close()

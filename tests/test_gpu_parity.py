@@ -193,7 +193,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
     G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
     den = np.abs(A).T @ np.abs(g.astype(np.float64))
     assert np.max(np.abs(G - O.apply_adjoint(A, g)) / np.maximum(den, 1e-300)) <= FP32_REL
-    for B in (0, 1, 3, 70):
+    for B in (0, 1, 2, 3, 8, 70):
         Zb = rng.random((B, N * N)).astype(np.float32)
         out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
         assert out.shape == (B, n * n)
