@@ -157,6 +157,61 @@ def test_c2_batched_dense(torch, c2, dense, storage):
     lib.close()
 
 
+MODES = {
+    "nearest": dict(interp="nearest"),
+    "cubic": dict(rotate="cubic"),
+    "flux": dict(flux="preserve"),
+    "cubic_flux": dict(rotate="cubic", flux="preserve"),
+}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_c2_modes_sampled(torch, c2, sample, mode):
+    """The build modes the bench times at 128^2 (nearest radial samples,
+    cubic-spline rotation in LDS row bands, flux-preserving columns) on the
+    sampled columns and a scene supported on them.  Bounds as in the small-size
+    tests of each mode: non-negative entries relative (1e-6, 2e-6 rescaled),
+    cubic ones against the column bound b_j (times |s_j| when rescaled)."""
+    from paper_2106_09122_amd import psflib
+    kw = MODES[mode]
+    cols = sample[0]
+    N = c2["N"]
+    A = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols, **kw)
+    lib = psflib.Library(torch.from_numpy(c2["cube"]).cuda(), c2["radii"], N, c2["S"], **kw)
+    got = lib.get_columns(cols).cpu().numpy().T.astype(np.float64)
+    cubic = kw.get("rotate") == "cubic"
+    flux = kw.get("flux") == "preserve"
+    Zs = _sparse_scenes(cols, N * N, 1, 71)[0]
+    z = Zs[cols].astype(np.float64)
+    img = lib.apply(torch.from_numpy(Zs).cuda()).cpu().numpy().astype(np.float64)
+    ref = A @ z
+    if not cubic:
+        pos = A > 0
+        assert np.all(got[~pos] == 0)
+        assert np.max(np.abs(got[pos] - A[pos]) / A[pos]) <= (2e-6 if flux else LIB_REL)
+        pos = ref > 0
+        assert np.all(img[~pos] == 0)
+        assert np.max(np.abs(img[pos] - ref[pos]) / ref[pos]) <= FP32_REL
+    else:
+        b = O.column_max_bound(c2["cube"], c2["radii"], N, c2["S"], rotate="cubic")[cols]
+        if flux:
+            A0 = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols, rotate="cubic")
+            tau0, t = A0.sum(axis=0), A.sum(axis=0)
+            sc = np.where(tau0 != 0, t / np.where(tau0 != 0, tau0, 1.0), 1.0)
+            eb = 2e-6 * np.abs(sc) * b
+        else:
+            eb = 1e-6 * b
+        assert np.all(np.abs(got - A) <= eb[None, :] + 1e-300)
+        assert np.all(np.abs(img - ref) <= FP32_REL * (np.abs(A) @ z) + eb @ z + 1e-300)
+    if flux:
+        tau = lib.column_sums().cpu().numpy()[cols]
+        t = A.sum(axis=0)
+        live = t != 0
+        assert np.all(tau[~live] == 0)
+        assert np.max(np.abs(tau[live] - t[live]) / np.abs(t[live])) <= 1e-6
+    lib.close()
+
+
 def test_paper_shape_sampled(torch):
     """The paper's own shape (128^2 PSFs at 0.2 lambda/D with the non-uniform
     IPAC offsets, a 256^2 scene at 3.529 mas: n != N, s != S, a 16384 x 65536
