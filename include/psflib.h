@@ -75,6 +75,11 @@ typedef enum { PSFLIB_OOB_CLAMP = 0, PSFLIB_OOB_ZERO = 1 } psflib_oob;
  *             Products accumulate in float32. */
 typedef enum { PSFLIB_FP32 = 0, PSFLIB_BF16_POW2 = 1, PSFLIB_FP16_POW2 = 2 } psflib_storage;
 
+/* Exponent e_j of an identically zero column in the 16-bit forms (its
+ * mantissas are all zero; any finite value times 2^e_j underflows to 0, so a
+ * scene value at such a column never sets the scene's scale). */
+#define PSFLIB_ZERO_COLUMN_EXPONENT (-16384)
+
 /* Interpolation of the rotation step (Sec. 2, the rotate() call).
  *  BILINEAR  four-neighbour bilinear sampling of the radially interpolated
  *            PSF Q, neighbours outside the n x n frame counting as zero.
@@ -183,7 +188,10 @@ psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* st
 psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, int32_t count,
                                  float* d_out, void* stream);
 
-/* Per-column exponents e_j (int32 [N*N]) of the 16-bit forms;
+/* Per-column exponents e_j (int32 [N*N]) of the 16-bit forms: column j is
+ * stored as mantissas M_ij = A_ij * 2^-e_j; an identically zero column has
+ * e_j = PSFLIB_ZERO_COLUMN_EXPONENT, so that a scene value at that column,
+ * scaled by 2^e_j, is exactly 0 (it multiplies only zeros).
  * PSFLIB_ERR_UNSUPPORTED for FP32 storage. */
 psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void* stream);
 

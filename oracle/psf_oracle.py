@@ -57,7 +57,7 @@ __all__ = [
     "spline_prefilter", "spline_prefilter_1d", "spline_coefficients", "bspline3", "rotate_cubic",
     "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
     "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
-    "quantize_library", "scale_exponent", "render_disk", "render_disk_grad",
+    "quantize_library", "scale_exponent", "ZERO_COLUMN_EXPONENT", "render_disk", "render_disk_grad",
 ]
 
 
@@ -340,11 +340,18 @@ def apply_batched(A: np.ndarray, Zb) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ a4 ----
+# An identically zero column has no scale of its own.  Its exponent is chosen
+# so that every finite value times 2**e underflows to exactly 0, in float32 and
+# in float64: a scene value at that column (which multiplies only zeros) then
+# cannot set the per-scene scale of the 16-bit product or overflow the format.
+ZERO_COLUMN_EXPONENT = -16384
+
+
 def scale_exponent(m: float) -> int:
     """Power-of-two exponent e with m * 2**-e in [2**14, 2**15) for m > 0,
-    and 0 for m == 0."""
+    and ZERO_COLUMN_EXPONENT for m == 0."""
     if m == 0.0:
-        return 0
+        return ZERO_COLUMN_EXPONENT
     _, E = math.frexp(m)  # m = f * 2**E, f in [0.5, 1)
     return E - 15
 
@@ -412,7 +419,8 @@ def quantize_library(A: np.ndarray, e: np.ndarray, fmt: str) -> np.ndarray:
     """Mantissa matrix M_ij = RN(A_ij * 2**-e_j) in the 16-bit format, as
     float64 (exact)."""
     A = np.asarray(A, dtype=np.float64)
-    return round_to_format(A * np.ldexp(1.0, -np.asarray(e, dtype=np.int64))[None, :], fmt)
+    # ldexp scales exactly (a zero column stays 0 at any exponent)
+    return round_to_format(np.ldexp(A, -np.asarray(e, dtype=np.int64)[None, :]), fmt)
 
 
 # ------------------------------------------------ fitting model (disk) ----

@@ -17,8 +17,8 @@ namespace psflib {
 
 namespace {
 
-__device__ inline int32_t exponent_of(double m) {  // m * 2^-e in [2^14, 2^15), 0 for m == 0
-  if (m == 0.0) return 0;
+__device__ inline int32_t exponent_of(double m) {  // m * 2^-e in [2^14, 2^15); kZeroColumnExp for m == 0
+  if (m == 0.0) return kZeroColumnExp;
   int E;
   (void)frexp(m, &E);
   return E - 15;

@@ -43,9 +43,12 @@ __global__ __launch_bounds__(256) void pair_cube_kernel(const float* __restrict_
   }
 }
 
-// Power-of-two exponent e with m * 2^-e in [2^14, 2^15) (0 for m == 0).
+// Power-of-two exponent e with m * 2^-e in [2^14, 2^15); kZeroColumnExp for
+// m == 0 (a zero column has no scale: with this exponent every scene value
+// at the column scales to exactly 0, so it can neither set a scene's
+// exponent nor overflow the 16-bit format).
 __device__ inline int32_t scale_exponent(double m) {
-  if (m == 0.0) return 0;
+  if (m == 0.0) return kZeroColumnExp;
   int E;
   (void)frexp(m, &E);  // m = f * 2^E, f in [0.5, 1)
   return E - 15;
@@ -66,9 +69,9 @@ __global__ __launch_bounds__(256) void geometry_kernel(int N, double S,
   ColGeom g;
   g.pad[0] = g.pad[1] = 0;
   if (j >= ncols) {  // padding column of the 16-bit layout: identically zero
-    g.r = 0.0; g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.k = -1; g.e = 0;
+    g.r = 0.0; g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.k = -1; g.e = want_exp ? kZeroColumnExp : 0;
     geo[j] = g;
-    if (exps) exps[j] = 0;
+    if (exps) exps[j] = g.e;
     return;
   }
   const int64_t p = j / N, q = j - p * N;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void geometry_kernel(int N, double S,
     }
   }
   g.r = r; g.ct = ct; g.st = st; g.w = zero ? 0.0 : w; g.k = zero ? -1 : k;
-  g.e = 0;
+  g.e = want_exp ? kZeroColumnExp : 0;
   if (want_exp && !zero) {
     // Bound on the column's largest value: bilinear rotation is a convex
     // combination of Q's pixels (or zero), so max_i A_ij <= max Q.

@@ -33,6 +33,7 @@ constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 floa
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
 constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
 constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
+constexpr int32_t kZeroColumnExp = PSFLIB_ZERO_COLUMN_EXPONENT;  // exponent of an identically zero column
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter

@@ -110,7 +110,7 @@ def test_cubic_16bit(torch, fmt, case):
     live = b > 0
     scaled = b[live] * np.ldexp(1.0, -e[live])
     assert np.all((scaled >= 2.0**14 * (1 - 1e-6)) & (scaled < 2.0**15 * (1 + 1e-6)))
-    assert np.all(e[~live] == 0)
+    assert np.all(e[~live] == O.ZERO_COLUMN_EXPONENT)
     u = U16[fmt]
     deq = lib.get_columns(np.arange(N * N)).cpu().numpy().T.astype(np.float64)
     tol = u * (1 + 1e-5) * np.abs(A) + ENTRY * b[None, :] + (2.0**-25) * np.ldexp(1.0, e)[None, :]

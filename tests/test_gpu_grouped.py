@@ -101,3 +101,47 @@ def test_grouped_crowded_odd_sizes(torch, crowded, storage):
             big = ref > 1e-6 * ref.max()
             assert np.max(np.abs(got - ref)[big] / ref[big]) <= U16[storage] + 1e-5, b
     g.close()
+
+
+@pytest.fixture(scope="module")
+def full():
+    """The mixed workload at its full size (sizes 64, 96, 128 x 11 wavelengths:
+    33 libraries, 256 scenes), each scene replaced by one supported on 8 seeded
+    columns of its library, so the oracle builds only the columns each image
+    needs; the plan and launch are those of the full workload."""
+    libs, scene_lib, _ = synth.mixed_workload()
+    rng = np.random.default_rng(77)
+    scenes, refs = [], []
+    for L in scene_lib:
+        lib = libs[L]
+        ncols = lib["N"] ** 2
+        cols = np.sort(rng.choice(ncols, 8, replace=False))
+        z = np.zeros(ncols, dtype=np.float32)
+        z[cols] = (rng.random(8) * 10.0 ** rng.uniform(-9, -7, 8)).astype(np.float32)
+        A = O.build_library(lib["cube"], lib["radii"], lib["N"], lib["S"], columns=cols)
+        scenes.append(z)
+        refs.append(A @ z[cols].astype(np.float64))
+    return libs, scene_lib, scenes, refs
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_grouped_full_workload_sampled(torch, full, storage):
+    from paper_2106_09122_amd import psflib
+    libs, scene_lib, scenes, refs = full
+    assert len(libs) == 33 and len(scene_lib) == 256
+    L = [psflib.Library(torch.from_numpy(l["cube"]).cuda(), l["radii"], l["N"], l["S"], storage=storage)
+         for l in libs]
+    Zs = [torch.from_numpy(z).cuda() for z in scenes]
+    g = psflib.Grouped(L, scene_lib, Zs, autotune=True)
+    out = [im.cpu().numpy().astype(np.float64) for im in g.run()]
+    for b, (got, ref) in enumerate(zip(out, refs)):
+        if storage == "fp32":
+            pos = ref > 0
+            assert np.all(got[~pos] == 0)
+            assert np.max(np.abs(got[pos] - ref[pos]) / ref[pos]) <= 1e-5, b
+        else:
+            big = ref > 1e-6 * ref.max()
+            assert np.max(np.abs(got - ref)[big] / ref[big]) <= U16[storage] + 1e-5, b
+    g.close()
+    for lib in L:
+        lib.close()

@@ -473,7 +473,14 @@ def test_scale_exponent_and_bound():
     for m in [1e-30, 3e-10, 0.5, 1.0, 2.0**-20, 0.7647, 12345.6]:
         e = O.scale_exponent(m)
         assert 2**14 <= m * 2.0**-e < 2**15
-    assert O.scale_exponent(0.0) == 0
+    # a zero column: any finite scene value scaled by its exponent is exactly 0
+    # (float32 and float64), and the column's dequantised values stay 0
+    ez = O.scale_exponent(0.0)
+    assert ez == O.ZERO_COLUMN_EXPONENT
+    big = np.array([np.finfo(np.float32).max, 1.0, 1e-30], dtype=np.float32)
+    assert np.all(np.ldexp(big, np.int32(ez)) == 0)
+    assert np.all(np.ldexp(big.astype(np.float64), ez) == 0)
+    assert np.all(O.quantize_library(np.zeros((5, 1)), np.array([ez]), "fp16") == 0)
     rng = np.random.default_rng(12)
     cube = rng.random((6, 12, 12)) ** 4
     radii = np.linspace(0, 2.5, 6)
