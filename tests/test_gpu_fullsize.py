@@ -241,3 +241,34 @@ def test_paper_shape_sampled(torch):
     assert np.all(out[~pos] == 0)
     assert np.max(np.abs(out[pos] - refb[pos]) / refb[pos]) <= FP32_REL
     lib.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_paper_shape_16bit_sampled(torch, fmt):
+    """The paper's shape (n = 128 != N = 256, non-uniform offsets, 16384 x 65536)
+    in the 16-bit forms: exponents bitwise, sampled dequantised columns, and a
+    single and a batched product of scenes supported on those columns."""
+    from paper_2106_09122_amd import psflib
+    d = synth.config_inputs(6)
+    N = d["N"]
+    rng = synth.rng_for(6, synth.STREAM_SUBSAMPLE)
+    cols = np.sort(rng.choice(N * N, 64, replace=False))
+    Aref = O.build_library(d["cube"], d["radii"], N, d["S"], columns=cols)
+    lib = psflib.Library(torch.from_numpy(d["cube"]).cuda(), d["radii"], N, d["S"], storage=fmt)
+    e_ref = O.pow2_exponents(O.column_max_bound(d["cube"], d["radii"], N, d["S"]))
+    assert np.array_equal(lib.exponents().cpu().numpy(), e_ref)
+    u = U16[fmt]
+    deq = lib.get_columns(cols).cpu().numpy().T.astype(np.float64)
+    tol = (u * (1 + 1e-5) + LIB_REL) * Aref + 2.0**-25 * np.ldexp(1.0, e_ref[cols])[None, :]
+    assert np.all(np.abs(deq - Aref) <= tol)
+    Zs = _sparse_scenes(cols, N * N, 1, 63)[0]
+    ref = Aref @ Zs[cols].astype(np.float64)
+    img = lib.apply(torch.from_numpy(Zs).cuda()).cpu().numpy()
+    big = ref > 1e-6 * ref.max()
+    assert np.max(np.abs(img - ref)[big] / ref[big]) <= u + FP32_REL
+    Zb = _sparse_scenes(cols, N * N, 6, 64)
+    refb = Zb[:, cols].astype(np.float64) @ Aref.T
+    outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
+    err = np.max(np.abs(outb - refb), axis=1) / np.max(np.abs(refb), axis=1)
+    assert np.max(err) <= 2 * u, np.max(err)
+    lib.close()

@@ -124,7 +124,7 @@ def full():
     return libs, scene_lib, scenes, refs
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
 def test_grouped_full_workload_sampled(torch, full, storage):
     from paper_2106_09122_amd import psflib
     libs, scene_lib, scenes, refs = full
