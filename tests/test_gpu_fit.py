@@ -113,3 +113,27 @@ def test_fit_reduces_chi2_and_moves_towards_truth(torch, setup):
     tt, t0 = np.array(synth.DISK_TRUE), np.array(synth.DISK_START)
     for k in (0, 1, 2):  # geometry parameters move towards the truth
         assert abs(t[k] - tt[k]) < abs(t0[k] - tt[k]), (k, t, tt, t0)
+
+
+@pytest.mark.parametrize("N,S", [(128, 0.125), (256, 0.0625), (33, 0.49)])
+def test_render_and_grad_at_larger_sizes(torch, N, S):
+    """The renderer and its gradient at the fit step's 128^2 size and beyond,
+    where the gradient's fixed-order reduction spans many workgroups, and at an
+    odd size (a partial last workgroup)."""
+    from paper_2106_09122_amd import fit, psflib
+    rng = np.random.default_rng(N)
+    for th in (synth.DISK_TRUE, synth.DISK_START):
+        t = torch.tensor(th, dtype=torch.float64, device="cuda")
+        Z = fit.render_disk(t, N, S, RMAX).cpu().numpy().astype(np.float64)
+        ref = O.render_disk(N, S, RMAX, th)
+        pos = ref > 0
+        assert np.all(Z[~pos] == 0)
+        assert np.max(np.abs(Z[pos] - ref[pos]) / ref[pos]) <= 1e-6
+        dZ = rng.standard_normal(N * N).astype(np.float32)
+        out = torch.empty(5, dtype=torch.float64, device="cuda")
+        psflib.render_disk_grad(N, S, RMAX, t.data_ptr(), torch.from_numpy(dZ).cuda().data_ptr(),
+                                out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        gref = O.render_disk_grad(N, S, RMAX, th, dZ.astype(np.float64))
+        scale = O.render_disk_grad(N, S, RMAX, th, np.abs(dZ.astype(np.float64)))
+        got = out.cpu().numpy()
+        assert np.all(np.abs(got - gref) <= 1e-9 * np.abs(scale) + 1e-300), (got, gref)

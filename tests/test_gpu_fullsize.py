@@ -123,19 +123,24 @@ def test_c2_16bit_sampled(torch, c2, sample, fmt):
 
 
 @pytest.fixture(scope="module")
-def dense(c2):
-    """Dense scenes over every column of the full library, with expected
-    images from the whole oracle library (built in column chunks, float64),
-    so every term of every accumulation chain is exercised."""
+def full_A(c2):
+    """The whole oracle library at 128^2 (float64, 2 GiB), built in column chunks."""
     N = c2["N"]
     K = N * N
-    Zb = np.random.default_rng(31).random((512, K)).astype(np.float32)
-    ref = np.zeros((512, c2["n"] ** 2))
+    A = np.empty((c2["n"] ** 2, K))
     for c0 in range(0, K, 2048):
         cols = np.arange(c0, min(K, c0 + 2048))
-        A = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols)
-        ref += Zb[:, cols].astype(np.float64) @ A.T
-    return Zb, ref
+        A[:, cols] = O.build_library(c2["cube"], c2["radii"], N, c2["S"], columns=cols)
+    return A
+
+
+@pytest.fixture(scope="module")
+def dense(c2, full_A):
+    """Dense scenes over every column of the full library, with expected
+    images from the whole oracle library, so every term of every accumulation
+    chain is exercised."""
+    Zb = np.random.default_rng(31).random((512, c2["N"] ** 2)).astype(np.float32)
+    return Zb, Zb.astype(np.float64) @ full_A.T
 
 
 @pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
@@ -271,4 +276,26 @@ def test_paper_shape_16bit_sampled(torch, fmt):
     outb = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
     err = np.max(np.abs(outb - refb), axis=1) / np.max(np.abs(refb), axis=1)
     assert np.max(err) <= 2 * u, np.max(err)
+    lib.close()
+
+
+def test_c2_fit_step_gradient(torch, c2, full_A):
+    """The fit step the bench times at 128^2 (render -> A Z -> chi-square ->
+    A^T -> renderer gradient) against the FP64 oracle chain on the whole
+    library; data from the oracle's image of the true disk plus seeded noise."""
+    from paper_2106_09122_amd import fit
+    N, S, rmax = c2["N"], c2["S"], 8.0
+    lib = _build(torch, c2, "fp32")
+    counts, K, var = synth.noisy_counts(full_A @ O.render_disk(N, S, rmax, synth.DISK_TRUE), 2e4,
+                                        synth.rng_for(4, synth.STREAM_NOISE))
+    th = torch.tensor(synth.DISK_START, dtype=torch.float64, device="cuda")
+    L, g = fit.loss_and_grad(lib, th, torch.from_numpy(counts).cuda(), torch.from_numpy(var).cuda(),
+                             K, rmax)
+    Z = O.render_disk(N, S, rmax, synth.DISK_START)
+    r = K * (full_A @ Z) - counts
+    Lref = float(np.sum(r * r / var))
+    gref = O.render_disk_grad(N, S, rmax, synth.DISK_START, full_A.T @ (2.0 * K * r / var))
+    assert abs(float(L) - Lref) <= 1e-4 * Lref
+    g = g.cpu().numpy()
+    assert np.linalg.norm(g - gref) <= 2e-3 * np.linalg.norm(gref), (g, gref)
     lib.close()
