@@ -16,6 +16,9 @@
  * --------------------------------
  *  - Pointers named d_* are HIP device memory; h_* are host memory.  The
  *    caller owns every buffer passed in, including the library buffer.
+ *    Device arrays must be 16-byte aligned (the library buffer 256-byte), as
+ *    hipMalloc and torch allocations are: kernels use 16-byte vector
+ *    accesses.  A misaligned array is rejected with PSFLIB_ERR_INVALID_ARG.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Every call that touches the device is stream-ordered and returns without
  *    waiting for the GPU.

@@ -628,6 +628,8 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
       return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: scene library index out of range");
     if (!h_scenes[b] || !h_images[b])
       return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: NULL scene or image pointer");
+    if (((uintptr_t)h_scenes[b] & 15u) != 0 || ((uintptr_t)h_images[b] & 15u) != 0)
+      return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: scene and image arrays must be 16-byte aligned");
   }
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != dev)

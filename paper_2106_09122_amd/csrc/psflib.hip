@@ -40,6 +40,9 @@ psflib_status device_fail(hipError_t e, const char* what) {
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Kernels read and write caller arrays with 16-byte vector accesses where the
+// sizes allow; every device array passed in must therefore be 16-byte aligned.
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Stream-ordered scratch (build temporaries, packed scenes, K-split partial
 // images) comes from a memory pool the library owns, one per device, which
@@ -184,6 +187,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   if (!d_cube || !h_radii || !d_lib || !out)
     return fail(PSFLIB_ERR_INVALID_ARG, "d_cube, h_radii, d_lib and out must be non-NULL");
   if (((uintptr_t)d_lib & 255u) != 0) return fail(PSFLIB_ERR_INVALID_ARG, "d_lib must be 256-byte aligned");
+  if (!aligned16(d_cube)) return fail(PSFLIB_ERR_INVALID_ARG, "d_cube must be 16-byte aligned");
   const int K = desc->n_psf;
   for (int k = 0; k < K; ++k) {
     if (!isfinite(h_radii[k])) return fail(PSFLIB_ERR_RADII, "radii must be finite");
@@ -329,6 +333,8 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
   psflib_status st = check_handle(h);
   if (st != PSFLIB_OK) return st;
   if (!d_scene || !d_image) return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be non-NULL");
+  if (!aligned16(d_scene) || !aligned16(d_image))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be 16-byte aligned");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   hipError_t e = psflib::launch_matvec(h->desc.storage, h->lib, exps, d_scene, h->L.M, h->L.ncols,
@@ -343,6 +349,8 @@ psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, flo
   psflib_status st = check_handle(h);
   if (st != PSFLIB_OK) return st;
   if (!d_g || !d_scene_grad) return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be non-NULL");
+  if (!aligned16(d_g) || !aligned16(d_scene_grad))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be 16-byte aligned");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   hipError_t e = psflib::launch_adjoint(h->desc.storage, h->lib, exps, d_g, h->L.M, h->L.ncols,
@@ -359,6 +367,8 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
   if (B < 0) return fail(PSFLIB_ERR_INVALID_ARG, "B must be >= 0");
   if (B == 0) return PSFLIB_OK;
   if (!d_scenes || !d_images) return fail(PSFLIB_ERR_INVALID_ARG, "d_scenes and d_images must be non-NULL");
+  if (!aligned16(d_scenes) || !aligned16(d_images))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_scenes and d_images must be 16-byte aligned");
   // one scene: the matvec streams the library faster than a one-scene product
   if (B == 1) return psflib_apply(h, d_scenes, d_images, stream);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -385,6 +395,7 @@ psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* st
   psflib_status st = check_handle(h);
   if (st != PSFLIB_OK) return st;
   if (!d_tau) return fail(PSFLIB_ERR_INVALID_ARG, "d_tau must be non-NULL");
+  if (!aligned16(d_tau)) return fail(PSFLIB_ERR_INVALID_ARG, "d_tau must be 16-byte aligned");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   hipError_t e = hipMemcpyAsync(d_tau, lib + h->L.off_tau, (size_t)h->L.ncols * 8,
                                 hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
@@ -400,6 +411,8 @@ psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, 
   if (count == 0) return PSFLIB_OK;
   if (count > 65535) return fail(PSFLIB_ERR_INVALID_ARG, "count must be <= 65535");
   if (!d_cols || !d_out) return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be non-NULL");
+  if (!aligned16(d_cols) || !aligned16(d_out))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be 16-byte aligned");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   hipError_t e = psflib::launch_get_columns(h->desc.storage, h->lib, exps, d_cols, count, h->L.M,
@@ -414,6 +427,7 @@ psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void*
   if (h->desc.storage == PSFLIB_FP32)
     return fail(PSFLIB_ERR_UNSUPPORTED, "FP32 storage has no exponents");
   if (!d_exp) return fail(PSFLIB_ERR_INVALID_ARG, "d_exp must be non-NULL");
+  if (!aligned16(d_exp)) return fail(PSFLIB_ERR_INVALID_ARG, "d_exp must be 16-byte aligned");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   hipError_t e = hipMemcpyAsync(d_exp, lib + h->L.off_exp, (size_t)h->L.ncols * 4,
                                 hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
@@ -425,6 +439,8 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
   psflib_status st = check_handle(h);
   if (st != PSFLIB_OK) return st;
   if (!d_geom && !d_k) return PSFLIB_OK;
+  if (!aligned16(d_geom) || !aligned16(d_k))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_geom and d_k must be 16-byte aligned");
   hipError_t e = psflib::launch_export_geometry(h->geo, h->L.ncols, d_geom, d_k,
                                                 reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "export_geometry kernel");
@@ -437,6 +453,7 @@ static psflib_status check_model_args(int32_t N, double S, double rmax, const vo
   if (!(S > 0.0) || !isfinite(S)) return fail(PSFLIB_ERR_INVALID_ARG, "scene_pixscale must be finite and > 0");
   if (isnan(rmax)) return fail(PSFLIB_ERR_INVALID_ARG, "rmax must not be NaN");
   if (!a || !b) return fail(PSFLIB_ERR_INVALID_ARG, "device pointers must be non-NULL");
+  if (!aligned16(a) || !aligned16(b)) return fail(PSFLIB_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
   return PSFLIB_OK;
 }
 
@@ -456,6 +473,7 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_dscene);
   if (st != PSFLIB_OK) return st;
   if (!d_dtheta) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be non-NULL");
+  if (!aligned16(d_dtheta)) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be 16-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);

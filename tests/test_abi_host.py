@@ -84,6 +84,8 @@ def test_build_validation_before_any_device_call():
     assert _err(psflib.build, d, 0, good, FAKE, need, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.build, d, FAKE, good, 0, need, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.build, d, FAKE, good, FAKE + 4, need, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.build, d, FAKE + 4, good, FAKE, need, 0) == psflib.ERR_INVALID_ARG  # cube not 16-byte aligned
+    assert "aligned" in psflib._lib.psflib_last_error().decode()
     assert _err(psflib.build, d, FAKE, [0.0, 2.0, 1.0], FAKE, need, 0) == psflib.ERR_RADII
     assert _err(psflib.build, d, FAKE, [0.0, 1.0, 1.0], FAKE, need, 0) == psflib.ERR_RADII
     assert _err(psflib.build, d, FAKE, [0.0, np.nan, 2.0], FAKE, need, 0) == psflib.ERR_RADII
@@ -114,6 +116,10 @@ def test_grouped_and_model_validation_without_device():
     assert _err(psflib.render_disk, 8, -0.5, 8.0, FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.render_disk, 8, 0.5, float("nan"), FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.render_disk_grad, 8, 0.5, 8.0, FAKE, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+    # device arrays must be 16-byte aligned
+    assert _err(psflib.render_disk, 8, 0.5, 8.0, FAKE + 8, FAKE, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.render_disk, 8, 0.5, 8.0, FAKE, FAKE + 4, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.render_disk_grad, 8, 0.5, 8.0, FAKE, FAKE, FAKE + 8, 0) == psflib.ERR_INVALID_ARG
 
 
 def test_largest_library_size_is_representable():

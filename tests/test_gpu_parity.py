@@ -296,3 +296,33 @@ def test_apply_and_adjoint_in_a_graph(torch, psflib, c1):
         assert torch.equal(grad, eager_grad), rep
     del graph
     lib.close()
+
+
+def test_misaligned_arrays_rejected_before_any_work(torch, psflib, c1):
+    """Device arrays must be 16-byte aligned (kernels use 16-byte accesses):
+    a view 4 bytes into a tensor is rejected with INVALID_ARG and nothing is
+    enqueued, so the output stays as it was."""
+    cube, radii, N, S = c1["cube"], c1["radii"], c1["N"], c1["S"]
+    for storage in ("fp32", "bf16"):
+        lib = _lib(torch, psflib, cube, radii, N, S, storage=storage)
+        st = torch.cuda.current_stream().cuda_stream
+        M, K = lib.M, lib.ncols
+        z = torch.rand(2 * K + 4, device="cuda")
+        out = torch.full((2 * M + 4,), 7.0, device="cuda")
+        cases = [
+            (psflib.apply, (lib.h, z.data_ptr() + 4, out.data_ptr(), st)),
+            (psflib.apply, (lib.h, z.data_ptr(), out.data_ptr() + 4, st)),
+            (psflib.apply_adjoint, (lib.h, out.data_ptr() + 4, z.data_ptr(), st)),
+            (psflib.apply_adjoint, (lib.h, out.data_ptr(), z.data_ptr() + 4, st)),
+            (psflib.apply_batched, (lib.h, z.data_ptr() + 4, out.data_ptr(), 2, st)),
+            (psflib.apply_batched, (lib.h, z.data_ptr(), out.data_ptr() + 8, 2, st)),
+            (psflib.column_sums, (lib.h, out.data_ptr() + 8, st)),
+        ]
+        for fn, args in cases:
+            with pytest.raises(psflib.PsflibError) as e:
+                fn(*args)
+            assert e.value.status == psflib.ERR_INVALID_ARG, fn.__name__
+            assert "aligned" in str(e.value)
+        torch.cuda.synchronize()
+        assert bool((out == 7.0).all()), "a rejected call must enqueue nothing"
+        lib.close()
