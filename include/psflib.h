@@ -187,7 +187,9 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
 psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* stream);
 
 /* Copy `count` library columns, dequantised to float32, into d_out
- * [count][n*n]; d_cols is a device int32 array of column indices in [0, N*N). */
+ * [count][n*n]; d_cols is a device int32 array of column indices in [0, N*N)
+ * (an index outside that range yields a column of zeros; it is never used to
+ * address the library). */
 psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, int32_t count,
                                  float* d_out, void* stream);
 
