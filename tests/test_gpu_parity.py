@@ -326,3 +326,14 @@ def test_misaligned_arrays_rejected_before_any_work(torch, psflib, c1):
         torch.cuda.synchronize()
         assert bool((out == 7.0).all()), "a rejected call must enqueue nothing"
         lib.close()
+
+
+def test_get_columns_out_of_range_indices_give_zeros(torch, psflib, c1, c1_oracle):
+    cube, radii, N, S = c1["cube"], c1["radii"], c1["N"], c1["S"]
+    lib = _lib(torch, psflib, cube, radii, N, S)
+    K = N * N
+    got = lib.get_columns(np.array([-1, 5, K, 2**31 - 1, K - 1])).cpu().numpy()
+    assert np.all(got[[0, 2, 3]] == 0)
+    assert _rel_err_pos(got[1], c1_oracle[:, 5]) <= LIB_REL
+    assert _rel_err_pos(got[4], c1_oracle[:, K - 1]) <= LIB_REL
+    lib.close()
