@@ -398,7 +398,12 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 a, const u32x4 b, const f32
 constexpr int kHRing = 4;    // ring slots
 constexpr int kHUnroll = 16; // stages per main-loop iteration (a multiple of kHRing)
 
-template <bool BF16, int TN>
+// NT: library loads with the non-temporal hint, for grids with one 128-scene
+// tile (no other workgroup re-reads a library block; B <= 128: 130 -> 120 us
+// at 128^2).  With several scene tiles the hint costs the L2 reuse (B = 1024:
+// +12%); the 256-scene tile (128 < B <= 256) measured the same either way and
+// keeps plain loads.
+template <bool BF16, int TN, bool NT>
 __global__ __launch_bounds__(kGemmThreads, TN == 128 ? 2 : 1) void gemm_h16_kernel(
     const u32x4* Mp, const u32x4* Zg, const int32_t* __restrict__ fexp,
     float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t Bp, int64_t mblocks,
@@ -438,8 +443,13 @@ __global__ __launch_bounds__(kGemmThreads, TN == 128 ? 2 : 1) void gemm_h16_kern
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const char* base = Ab + (st * kHG + 2 * ks) * M * 16;
-      a[slot][ks][0] = *reinterpret_cast<const u32x4*>(base + offa0);
-      a[slot][ks][1] = *reinterpret_cast<const u32x4*>(base + offa1);
+      if constexpr (NT) {
+        a[slot][ks][0] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + offa0));
+        a[slot][ks][1] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + offa1));
+      } else {
+        a[slot][ks][0] = *reinterpret_cast<const u32x4*>(base + offa0);
+        a[slot][ks][1] = *reinterpret_cast<const u32x4*>(base + offa1);
+      }
     }
     const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(Zb + st * kHG * Bp * 16), (short)0, 0x7FFFFFFF, 0x00020000);
@@ -590,6 +600,32 @@ static hipError_t launch_gemm_f32(int variant, unsigned grid, const float* A, co
   }
 }
 
+template <bool BF16, int TN, bool NT>
+static hipError_t launch_gemm_h16_t(unsigned grid, const u32x4* Mp, const u32x4* Zg,
+                                    const int32_t* fexp, float* dst, int64_t M, int64_t ngroups,
+                                    int64_t B, int64_t Bp, const GemmPlan& p, hipStream_t s) {
+  gemm_h16_kernel<BF16, TN, NT><<<grid, kGemmThreads, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, B, Bp,
+                                                             p.mblocks, p.nblocks, p.splits, p.per);
+  return hipGetLastError();
+}
+
+static hipError_t launch_gemm_h16(bool bf, bool wide, bool nt, unsigned grid, const u32x4* Mp,
+                                  const u32x4* Zg, const int32_t* fexp, float* dst, int64_t M,
+                                  int64_t ngroups, int64_t B, int64_t Bp, const GemmPlan& p,
+                                  hipStream_t s) {
+  const int v = (bf ? 4 : 0) + (wide ? 2 : 0) + (nt ? 1 : 0);
+  switch (v) {
+    case 0: return launch_gemm_h16_t<false, 128, false>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 1: return launch_gemm_h16_t<false, 128, true>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 2: return launch_gemm_h16_t<false, 256, false>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 3: return launch_gemm_h16_t<false, 256, true>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 4: return launch_gemm_h16_t<true, 128, false>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 5: return launch_gemm_h16_t<true, 128, true>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    case 6: return launch_gemm_h16_t<true, 256, false>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+    default: return launch_gemm_h16_t<true, 256, true>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
+  }
+}
+
 static int64_t chunk_of(int B) { return B < kMaxBatchChunk ? B : kMaxBatchChunk; }
 
 // scenes per group row of the packed 16-bit scene copy (whole scene tiles)
@@ -689,22 +725,9 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
-      if (h16_tile(bc) == 256) {
-        if (bf)
-          gemm_h16_kernel<true, 256><<<grid, kGemmThreads, 0, s>>>(
-              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
-        else
-          gemm_h16_kernel<false, 256><<<grid, kGemmThreads, 0, s>>>(
-              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
-      } else {
-        if (bf)
-          gemm_h16_kernel<true, 128><<<grid, kGemmThreads, 0, s>>>(
-              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
-        else
-          gemm_h16_kernel<false, 128><<<grid, kGemmThreads, 0, s>>>(
-              Mp, Zg, fexp, dst, M, ngroups, bc, Bp, p.mblocks, p.nblocks, p.splits, p.per);
-      }
-      e = hipGetLastError();
+      const bool wide = h16_tile(bc) == 256;
+      e = launch_gemm_h16(bf, wide, !wide && p.nblocks == 1, grid, Mp, Zg, fexp, dst, M, ngroups,
+                          bc, Bp, p, s);
     }
     if (e != hipSuccess) return e;
     if (p.splits > 1) {

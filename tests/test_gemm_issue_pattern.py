@@ -37,7 +37,7 @@ def asm():
 
 def kernel_bodies(text):
     names = re.findall(r"^(_ZN6psflib15gemm_h16_kernel\w+):", text, re.M)
-    assert len(names) == 4  # bf16 and fp16, 128- and 256-scene tiles
+    assert len(names) == 8  # bf16 and fp16, 128- and 256-scene tiles, with and without the NT hint
     for name in names:
         tn = int(re.search(r"ILb[01]ELi(\d+)E", name).group(1))
         body = text[text.index(name + ":"):]
