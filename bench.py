@@ -168,7 +168,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-sample-cols", type=int, default=4096)
+    ap.add_argument("--cpu-sample-cols", type=int, default=12288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="time only the headline matvec")
     ap.add_argument("--copy-probe", action="store_true",
