@@ -31,12 +31,20 @@
  *    PSF pixel scale is not an input: the rotation depends only on the angle.
  *  - Every call returns a status.  Arguments are validated before anything is
  *    enqueued, so a call that fails validation has enqueued nothing.  Errors
- *    raised by the HIP runtime (including faults of earlier asynchronous
- *    work) are returned as PSFLIB_ERR_DEVICE.  psflib_last_error() gives a
- *    human-readable message for the last failing call on the calling thread.
- *  - A handle shares one device workspace between its calls: calls on the
- *    same handle must not run concurrently (issue them on one stream, or
- *    order them with events).  Different handles are independent.
+ *    raised by the HIP runtime are returned as PSFLIB_ERR_DEVICE; so is a
+ *    runtime error still pending on the calling thread when a call starts (a
+ *    fault of earlier asynchronous work, or an earlier failed runtime call),
+ *    which is reported before anything is enqueued and then cleared.
+ *    psflib_last_error() gives a human-readable message for the last failing
+ *    call on the calling thread.
+ *  - After psflib_build returns, a handle is read-only: psflib_apply,
+ *    psflib_apply_adjoint, psflib_apply_batched and the read-back calls may
+ *    run concurrently on different streams with one handle (each call takes
+ *    its temporary device memory for itself, stream-ordered, from a pool the
+ *    library keeps per device).  Work that uses the library must be ordered
+ *    after the build on the build's stream (same stream, or an event).
+ *  - Device memory the library allocates for itself comes from that pool:
+ *    freed blocks are kept for reuse by later calls until the process ends.
  */
 #ifndef PSFLIB_H
 #define PSFLIB_H
@@ -133,8 +141,11 @@ const char* psflib_last_error(void);
 /* Bytes the caller must allocate for the library buffer of `desc`: the matrix
  * (n^2 x N^2 entries in the chosen storage, with the 16-bit forms padded to a
  * multiple of 64 columns), followed by the per-column float64 column sums and,
- * for the 16-bit forms, the int32 exponents.  Fails with PSFLIB_ERR_SIZE if
- * the size does not fit in size_t or exceeds 2^62. */
+ * for the 16-bit forms, the int32 exponents.  The matrix is the paper's
+ * library of Sec. 3 (one flattened n x n PSF per scene pixel, Eq. (5)), whose
+ * stored size Table 2 lists (n^2 N^2 float64 values there).  Host-only: no
+ * device call.  Fails with PSFLIB_ERR_SIZE if the size does not fit in size_t
+ * or exceeds 2^62. */
 psflib_status psflib_library_bytes(const psflib_desc* desc, size_t* bytes);
 
 /* Build the interpolated PSF library (Sec. 2; Eqs. (4)-(5)).
@@ -151,21 +162,28 @@ psflib_status psflib_library_bytes(const psflib_desc* desc, size_t* bytes);
  * interpolated to offset r, Q = (1-w) P_k + w P_{k+1}, rotated about the array
  * centre so that +x turns to the position angle (output pixel at offset u from
  * the centre samples Q at R(-theta) u), bilinearly with zero padding.
- * Allocates the handle's device workspace (hipMalloc) and temporary build
- * buffers (stream-ordered). */
+ * Takes the handle's device workspace (per-column geometry) and temporary
+ * build buffers from the library's device pool, stream-ordered on `stream`. */
 psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const double* h_radii,
                            void* d_lib, size_t lib_bytes, void* stream, psflib_handle** out);
 
 /* Simulated image S = A Z (Sec. 3, Eq. (6)).
  *   d_scene  float32 [N*N] scene (flattened row-major, Sec. 3).
  *   d_image  float32 [n*n] output image.
- * Float32 accumulation in a fixed order (results are bitwise reproducible). */
+ * Float32 accumulation in a fixed order (results are bitwise reproducible).
+ * The split-K partial sums (a few MiB) are taken from the device pool for
+ * this call, stream-ordered on `stream`; under stream capture that
+ * allocation becomes part of the graph, so each graph owns its partials. */
 psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream);
 
-/* Adjoint G = A^T g: the gradient of <g, A Z> with respect to Z.
+/* Adjoint G = A^T g of the simulation S = A Z (Sec. 3, Eq. (6)): the
+ * gradient of <g, A Z> with respect to the scene Z, which a retrieval of
+ * scene parameters from simulated images needs (Sec. 5 plans such a
+ * retrieval; the paper does not define the adjoint itself).
  *   d_g           float32 [n*n] image-space vector.
  *   d_scene_grad  float32 [N*N] output.
- * Float32 accumulation in a fixed order. */
+ * Float32 accumulation in a fixed order.  Partial sums (PSFs larger than
+ * 128 x 128 only) come from the device pool as in psflib_apply. */
 psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
                                    void* stream);
 
@@ -183,7 +201,9 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
                                    int32_t B, void* stream);
 
 /* Column sums tau_j = sum_i A_ij (float64 [N*N]), computed during the build
- * from the float32 values (before 16-bit rounding). */
+ * from the float32 values (before 16-bit rounding): the throughput of each
+ * library PSF, by which a user can normalise the columns in the ways Sec. 3
+ * leaves open (the library itself is not normalised). */
 psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* stream);
 
 /* Copy `count` library columns, dequantised to float32, into d_out
@@ -228,8 +248,8 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
  *                   (running the graph, which writes the images) and keep the
  *                   fastest; the choice is cached per plan shape for the
  *                   process.  Zero: use the cached or default choice.
- * Synchronises `stream` once (libraries built on it must be complete) and
- * allocates the plan's device tables and partials (hipMalloc).  FP32 plans
+ * Synchronises `stream` (libraries built on it must be complete) and takes
+ * the plan's device tables and partials from the library's device pool.  FP32 plans
  * take libraries with n*n <= 2^25 (n <= 5792; PSFLIB_ERR_UNSUPPORTED beyond). */
 typedef struct psflib_grouped psflib_grouped;
 psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t nlibs,
@@ -244,7 +264,9 @@ psflib_status psflib_grouped_run(const psflib_grouped* g, void* stream);
  * if it was autotuned, the measured time of one run in ms (else 0). */
 psflib_status psflib_grouped_chunk(const psflib_grouped* g, int64_t* chunk, float* tuned_ms);
 
-/* Free the plan (waits for the device).  NULL is ignored. */
+/* Free the plan.  Waits on the host for the plan's own launches (events
+ * recorded by psflib_grouped_run on each stream it ran on), not for other
+ * work on the device.  NULL is ignored. */
 void psflib_grouped_destroy(psflib_grouped* g);
 
 /* ---- Fitting model -------------------------------------------------------
@@ -268,8 +290,11 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
                                       const double* d_theta, const float* d_dscene,
                                       double* d_dtheta, void* stream);
 
-/* Release the handle and its workspace.  Waits for the device to finish work
- * that uses the workspace.  NULL is ignored. */
+/* Release the handle and its workspace.  Waits on the host for the handle's
+ * own uses of its workspace (the build and psflib_get_geometry, by events
+ * recorded on their streams), not for other work on the device; the caller
+ * must not destroy a handle while calls that use it are still queued.  NULL
+ * is ignored. */
 void psflib_destroy(psflib_handle* h);
 
 #ifdef __cplusplus

@@ -416,6 +416,7 @@ struct psflib_grouped {
   void* dev;        // items | reductions | scene/image tables | slots | packed operands | partials
   int64_t chunk;    // chosen chunk length (columns, or 8-column groups for 16-bit)
   float ms_tuned;   // time of the chosen shape during autotuning (0 if not tuned)
+  mutable psflib::StreamUses uses;  // streams the graph was launched on
 };
 
 namespace {
@@ -525,29 +526,32 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   const size_t total = align256(o_part + (size_t)p.part_floats * 4);
   if (g->exec) { (void)hipGraphExecDestroy(g->exec); g->exec = nullptr; }
   if (g->graph) { (void)hipGraphDestroy(g->graph); g->graph = nullptr; }
-  if (g->dev) { (void)hipFree(g->dev); g->dev = nullptr; }
+  // the previous tables are idle: every launch of the previous graph was
+  // waited for on `s` (autotuning) before a new shape is instantiated
+  if (g->dev) { (void)pool_release(g->dev, g->device); g->dev = nullptr; }
   hipError_t e = hipSuccess;
   if (total > 0) {
-    e = hipMalloc(&g->dev, total);
+    e = pool_alloc(&g->dev, total, g->device, s);
     if (e != hipSuccess) { g->dev = nullptr; return e; }
   }
   char* d = reinterpret_cast<char*>(g->dev);
   if (!p.items.empty()) {
-    e = hipMemcpy(d + o_items, p.items.data(), p.items.size() * sizeof(GItem), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d + o_reds, p.reds.data(), p.reds.size() * sizeof(GReduce), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d + o_sc, p.scenes.data(), p.scenes.size() * sizeof(void*), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d + o_im, p.images.data(), p.images.size() * sizeof(void*), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d + o_slots, p.slots.data(), p.slots.size() * sizeof(GScene), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    if (!p.packs.empty()) {
-      e = hipMemcpy(d + o_packs, p.packs.data(), p.packs.size() * sizeof(GPack), hipMemcpyHostToDevice);
+    const struct { size_t off; const void* src; size_t bytes; } up[] = {
+        {o_items, p.items.data(), p.items.size() * sizeof(GItem)},
+        {o_reds, p.reds.data(), p.reds.size() * sizeof(GReduce)},
+        {o_sc, p.scenes.data(), p.scenes.size() * sizeof(void*)},
+        {o_im, p.images.data(), p.images.size() * sizeof(void*)},
+        {o_slots, p.slots.data(), p.slots.size() * sizeof(GScene)},
+        {o_packs, p.packs.data(), p.packs.size() * sizeof(GPack)}};
+    for (const auto& u : up) {
+      if (u.bytes == 0) continue;
+      e = hipMemcpyAsync(d + u.off, u.src, u.bytes, hipMemcpyHostToDevice, s);
       if (e != hipSuccess) return e;
     }
   }
+  // the tables are on the device before any launch of the graph
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
   const GItem* items = reinterpret_cast<const GItem*>(d + o_items);
   const GReduce* reds = reinterpret_cast<const GReduce*>(d + o_reds);
   const float* const* sc = reinterpret_cast<const float* const*>(d + o_sc);
@@ -593,7 +597,6 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cap);
   g->chunk = chunk;
-  (void)s;
   return e;
 }
 
@@ -634,6 +637,8 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != dev)
     return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: current device differs from the libraries'");
+  psflib_status pst = psflib::check_pending_error();
+  if (pst != PSFLIB_OK) return pst;
   psflib_grouped* g = new (std::nothrow) psflib_grouped();
   if (!g) return psflib::fail_status(PSFLIB_ERR_DEVICE, "host allocation failed");
   g->storage = storage;
@@ -703,8 +708,13 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
 psflib_status psflib_grouped_run(const psflib_grouped* g, void* stream) {
   if (!g) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped plan is NULL");
   if (!g->exec) return PSFLIB_OK;  // no scenes
-  hipError_t e = hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream));
+  psflib_status pst = psflib::check_pending_error();
+  if (pst != PSFLIB_OK) return pst;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipGraphLaunch(g->exec, s);
   if (e != hipSuccess) return psflib::device_fail_status(e, "hipGraphLaunch");
+  e = g->uses.note(s);
+  if (e != hipSuccess) return psflib::device_fail_status(e, "hipEventRecord(grouped run)");
   return PSFLIB_OK;
 }
 
@@ -717,10 +727,11 @@ psflib_status psflib_grouped_chunk(const psflib_grouped* g, int64_t* chunk, floa
 
 void psflib_grouped_destroy(psflib_grouped* g) {
   if (!g) return;
-  (void)hipDeviceSynchronize();
+  // wait for the plan's own launches (not for the device)
+  g->uses.wait_all();
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
-  if (g->dev) (void)hipFree(g->dev);
+  if (g->dev) (void)psflib::pool_release(g->dev, g->device);
   delete g;
 }
 

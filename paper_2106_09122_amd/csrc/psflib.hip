@@ -17,13 +17,13 @@ struct psflib_handle {
   psflib::Layout L;
   int device;
   void* lib;            // caller-owned library buffer
-  void* ws;             // device workspace (owned)
+  void* ws;             // device workspace (owned, from the library's pool)
   psflib::ColGeom* geo;
   double* radii_dev;
   float* pmax;
-  float* mv_part;
-  float* adj_part;
   std::vector<double> radii;  // host copy (source of the radii upload)
+  // streams that used the workspace (the build, geometry exports)
+  mutable psflib::StreamUses ws_uses;
 };
 
 namespace {
@@ -44,38 +44,43 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // sizes allow; every device array passed in must therefore be 16-byte aligned.
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Stream-ordered scratch (build temporaries, packed scenes, K-split partial
-// images) comes from a memory pool the library owns, one per device, which
-// keeps freed blocks for reuse: after the first call of a given size no call
-// pays for a fresh device allocation.  The pools live until the process ends.
-hipError_t scratch_alloc(void** p, size_t bytes, int dev, hipStream_t s) {
-  static std::mutex mu;
-  static std::map<int, hipMemPool_t> pools;
-  hipMemPool_t pool;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = pools.find(dev);
-    if (it == pools.end()) {
-      hipMemPoolProps props;
-      memset(&props, 0, sizeof(props));
-      props.allocType = hipMemAllocationTypePinned;
-      props.handleTypes = hipMemHandleTypeNone;
-      props.location.type = hipMemLocationTypeDevice;
-      props.location.id = dev;
-      hipError_t e = hipMemPoolCreate(&pool, &props);
-      if (e != hipSuccess) return e;
-      uint64_t keep = ~(uint64_t)0;
-      e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-      if (e != hipSuccess) {
-        (void)hipMemPoolDestroy(pool);
-        return e;
-      }
-      pools[dev] = pool;
-    } else {
-      pool = it->second;
-    }
+// Stream-ordered device memory (the handle's workspace, build temporaries,
+// packed scenes, K-split partial images) comes from a memory pool the library
+// owns, one per device, which keeps freed blocks for reuse: after the first
+// call of a given size no call pays for a fresh device allocation.  The pools
+// live until the process ends.
+struct DevicePool {
+  hipMemPool_t pool = nullptr;
+  hipStream_t release = nullptr;  // internal stream for pool_release
+};
+
+std::mutex g_pool_mu;
+std::map<int, DevicePool> g_pools;
+
+hipError_t device_pool(int dev, DevicePool** out) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  auto it = g_pools.find(dev);
+  if (it != g_pools.end()) {
+    *out = &it->second;
+    return hipSuccess;
   }
-  return hipMallocFromPoolAsync(p, bytes, pool, s);
+  hipMemPoolProps props;
+  memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  DevicePool dp;
+  hipError_t e = hipMemPoolCreate(&dp.pool, &props);
+  if (e != hipSuccess) return e;
+  uint64_t keep = ~(uint64_t)0;
+  e = hipMemPoolSetAttribute(dp.pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) {
+    (void)hipMemPoolDestroy(dp.pool);
+    return e;
+  }
+  *out = &(g_pools[dev] = dp);
+  return hipSuccess;
 }
 
 constexpr int32_t kMaxN = 8192;   // image side: n^2 rows fit comfortably in 32-bit pixel indices
@@ -117,6 +122,64 @@ namespace psflib {
 
 psflib_status fail_status(psflib_status s, const char* msg) { return fail(s, msg); }
 psflib_status device_fail_status(hipError_t e, const char* what) { return device_fail(e, what); }
+
+psflib_status check_pending_error() {
+  // hipErrorNotReady only says that queried work is still running
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess || e == hipErrorNotReady) return PSFLIB_OK;
+  return device_fail(e, "HIP error pending from earlier work");
+}
+
+hipError_t pool_alloc(void** p, size_t bytes, int dev, hipStream_t s) {
+  DevicePool* dp = nullptr;
+  hipError_t e = device_pool(dev, &dp);
+  if (e != hipSuccess) return e;
+  return hipMallocFromPoolAsync(p, bytes, dp->pool, s);
+}
+
+hipError_t pool_release(void* p, int dev) {
+  if (!p) return hipSuccess;
+  DevicePool* dp = nullptr;
+  hipError_t e = device_pool(dev, &dp);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!dp->release) {
+      e = hipStreamCreateWithFlags(&dp->release, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        dp->release = nullptr;
+        return e;
+      }
+    }
+  }
+  return hipFreeAsync(p, dp->release);
+}
+
+hipError_t StreamUses::note(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+  std::lock_guard<std::mutex> lock(mu_);
+  for (auto& se : ev_)
+    if (se.first == s) return hipEventRecord(se.second, s);
+  hipEvent_t ev;
+  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  ev_.emplace_back(s, ev);
+  return hipEventRecord(ev, s);
+}
+
+void StreamUses::wait_all() {
+  std::lock_guard<std::mutex> lock(mu_);
+  for (auto& se : ev_) {
+    (void)hipEventSynchronize(se.second);
+    (void)hipEventDestroy(se.second);
+  }
+  ev_.clear();
+}
+
+StreamUses::~StreamUses() { wait_all(); }
 
 void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
                  int64_t* ncols, int64_t* ncols_pad, int* storage, int* device) {
@@ -200,13 +263,12 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
     return fail(PSFLIB_ERR_SIZE, "library buffer too small: need " + std::to_string(L.total) +
                                      " bytes, got " + std::to_string(lib_bytes));
   const int storage = desc->storage;
-  const int64_t mv_floats = psflib::matvec_partial_floats(storage, L.M, L.ncols, L.ncols_pad);
-  const int64_t adj_floats = psflib::adjoint_partial_floats(storage, L.M, L.ncols, L.ncols_pad);
 
-  (void)hipGetLastError();  // clear a stale error left by unrelated work
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
 
   psflib_handle* h = new (std::nothrow) psflib_handle();
   if (!h) return fail(PSFLIB_ERR_DEVICE, "host allocation failed");
@@ -216,26 +278,22 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   h->lib = d_lib;
   h->radii.assign(h_radii, h_radii + K);
 
-  // Workspace: radii | pmax | per-column geometry | matvec partials | adjoint partials.
+  // Workspace: radii | pmax | per-column geometry.
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   size_t off = 0;
   const size_t off_radii = off; off = align256(off + (size_t)K * 8);
   const size_t off_pmax = off;  off = align256(off + (size_t)K * 4);
   const size_t off_geo = off;   off = align256(off + (size_t)L.ncols_pad * sizeof(psflib::ColGeom));
-  const size_t off_mv = off;    off = align256(off + (size_t)mv_floats * 4);
-  const size_t off_adj = off;   off = align256(off + (size_t)adj_floats * 4);
-  e = hipMalloc(&h->ws, off);
+  e = psflib::pool_alloc(&h->ws, off, dev, s);
   if (e != hipSuccess) {
     delete h;
-    return device_fail(e, "hipMalloc(workspace)");
+    return device_fail(e, "workspace allocation");
   }
   char* ws = reinterpret_cast<char*>(h->ws);
   h->radii_dev = reinterpret_cast<double*>(ws + off_radii);
   h->pmax = reinterpret_cast<float*>(ws + off_pmax);
   h->geo = reinterpret_cast<psflib::ColGeom*>(ws + off_geo);
-  h->mv_part = reinterpret_cast<float*>(ws + off_mv);
-  h->adj_part = reinterpret_cast<float*>(ws + off_adj);
 
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* lib = reinterpret_cast<char*>(d_lib);
   double* tau = reinterpret_cast<double*>(lib + L.off_tau);
   int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
@@ -260,17 +318,19 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
   void* tmp = nullptr;
+  // on failure: wait for what this build enqueued (on its own stream), then
+  // release its memory
   auto bail = [&](hipError_t err, const char* what) {
     psflib_status r = device_fail(err, what);
     if (tmp) (void)hipFreeAsync(tmp, s);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(h->ws);
+    (void)hipStreamSynchronize(s);
+    (void)psflib::pool_release(h->ws, dev);
     delete h;
     return r;
   };
   e = hipMemcpyAsync(h->radii_dev, h->radii.data(), (size_t)K * 8, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return bail(e, "hipMemcpyAsync(radii)");
-  e = scratch_alloc(&tmp, tmp_bytes, dev, s);
+  e = psflib::pool_alloc(&tmp, tmp_bytes, dev, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "scratch allocation (build)"); }
   char* tp = reinterpret_cast<char*>(tmp);
   void* path_tmp = tp;
@@ -325,9 +385,53 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   }
   e = hipFreeAsync(tmp, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipFreeAsync(build scratch)"); }
+  tmp = nullptr;
+  e = h->ws_uses.note(s);
+  if (e != hipSuccess) return bail(e, "hipEventRecord(build)");
   *out = h;
   return PSFLIB_OK;
 }
+
+namespace {
+
+// One split-K product (S = A Z, or G = A^T g when `adjoint`) with its
+// partial sums in `partial` (at least the launcher's partial count).
+hipError_t launch_product(const psflib_handle* h, bool adjoint, const float* in, float* out,
+                          float* partial, hipStream_t s) {
+  const char* lib = reinterpret_cast<const char*>(h->lib);
+  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  if (adjoint)
+    return psflib::launch_adjoint(h->desc.storage, h->lib, exps, in, h->L.M, h->L.ncols,
+                                  h->L.ncols_pad, partial, out, s);
+  return psflib::launch_matvec(h->desc.storage, h->lib, exps, in, h->L.M, h->L.ncols,
+                               h->L.ncols_pad, partial, out, s);
+}
+
+// The product with its partials taken from the device pool for this call
+// only (stream-ordered: freed after the kernels on `s`), so calls on
+// different streams share no memory.  Under stream capture the allocation
+// becomes part of the graph.
+psflib_status pooled_product(const psflib_handle* h, bool adjoint, const float* in, float* out,
+                             hipStream_t s) {
+  const int64_t floats =
+      adjoint ? psflib::adjoint_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad)
+              : psflib::matvec_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad);
+  void* part = nullptr;
+  hipError_t e = hipSuccess;
+  if (floats > 0) {
+    e = psflib::pool_alloc(&part, (size_t)floats * 4, h->device, s);
+    if (e != hipSuccess) return device_fail(e, "partial-sum allocation");
+  }
+  e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
+  if (part) {
+    hipError_t e2 = hipFreeAsync(part, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return device_fail(e, adjoint ? "adjoint kernels" : "matvec kernels");
+  return PSFLIB_OK;
+}
+
+}  // namespace
 
 psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream) {
   psflib_status st = check_handle(h);
@@ -335,13 +439,9 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
   if (!d_scene || !d_image) return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be non-NULL");
   if (!aligned16(d_scene) || !aligned16(d_image))
     return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be 16-byte aligned");
-  const char* lib = reinterpret_cast<const char*>(h->lib);
-  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
-  hipError_t e = psflib::launch_matvec(h->desc.storage, h->lib, exps, d_scene, h->L.M, h->L.ncols,
-                                       h->L.ncols_pad, h->mv_part, d_image,
-                                       reinterpret_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return device_fail(e, "matvec kernel");
-  return PSFLIB_OK;
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  return pooled_product(h, false, d_scene, d_image, reinterpret_cast<hipStream_t>(stream));
 }
 
 psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
@@ -351,13 +451,9 @@ psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, flo
   if (!d_g || !d_scene_grad) return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be non-NULL");
   if (!aligned16(d_g) || !aligned16(d_scene_grad))
     return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be 16-byte aligned");
-  const char* lib = reinterpret_cast<const char*>(h->lib);
-  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
-  hipError_t e = psflib::launch_adjoint(h->desc.storage, h->lib, exps, d_g, h->L.M, h->L.ncols,
-                                        h->L.ncols_pad, h->adj_part, d_scene_grad,
-                                        reinterpret_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return device_fail(e, "adjoint kernel");
-  return PSFLIB_OK;
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  return pooled_product(h, true, d_g, d_scene_grad, reinterpret_cast<hipStream_t>(stream));
 }
 
 psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
@@ -371,12 +467,14 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
     return fail(PSFLIB_ERR_INVALID_ARG, "d_scenes and d_images must be 16-byte aligned");
   // one scene: the matvec streams the library faster than a one-scene product
   if (B == 1) return psflib_apply(h, d_scenes, d_images, stream);
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t bytes = psflib::batched_scratch_bytes(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad, B);
   void* scratch = nullptr;
   hipError_t e;
   if (bytes > 0) {
-    e = scratch_alloc(&scratch, bytes, h->device, s);
+    e = psflib::pool_alloc(&scratch, bytes, h->device, s);
     if (e != hipSuccess) return device_fail(e, "scratch allocation (batched)");
   }
   const char* lib = reinterpret_cast<const char*>(h->lib);
@@ -396,6 +494,8 @@ psflib_status psflib_column_sums(const psflib_handle* h, double* d_tau, void* st
   if (st != PSFLIB_OK) return st;
   if (!d_tau) return fail(PSFLIB_ERR_INVALID_ARG, "d_tau must be non-NULL");
   if (!aligned16(d_tau)) return fail(PSFLIB_ERR_INVALID_ARG, "d_tau must be 16-byte aligned");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   const char* lib = reinterpret_cast<const char*>(h->lib);
   hipError_t e = hipMemcpyAsync(d_tau, lib + h->L.off_tau, (size_t)h->L.ncols * 8,
                                 hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
@@ -413,6 +513,8 @@ psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, 
   if (!d_cols || !d_out) return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be non-NULL");
   if (!aligned16(d_cols) || !aligned16(d_out))
     return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be 16-byte aligned");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   hipError_t e = psflib::launch_get_columns(h->desc.storage, h->lib, exps, d_cols, count, h->L.M,
@@ -428,6 +530,8 @@ psflib_status psflib_get_exponents(const psflib_handle* h, int32_t* d_exp, void*
     return fail(PSFLIB_ERR_UNSUPPORTED, "FP32 storage has no exponents");
   if (!d_exp) return fail(PSFLIB_ERR_INVALID_ARG, "d_exp must be non-NULL");
   if (!aligned16(d_exp)) return fail(PSFLIB_ERR_INVALID_ARG, "d_exp must be 16-byte aligned");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   const char* lib = reinterpret_cast<const char*>(h->lib);
   hipError_t e = hipMemcpyAsync(d_exp, lib + h->L.off_exp, (size_t)h->L.ncols * 4,
                                 hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
@@ -441,9 +545,13 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
   if (!d_geom && !d_k) return PSFLIB_OK;
   if (!aligned16(d_geom) || !aligned16(d_k))
     return fail(PSFLIB_ERR_INVALID_ARG, "d_geom and d_k must be 16-byte aligned");
-  hipError_t e = psflib::launch_export_geometry(h->geo, h->L.ncols, d_geom, d_k,
-                                                reinterpret_cast<hipStream_t>(stream));
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = psflib::launch_export_geometry(h->geo, h->L.ncols, d_geom, d_k, s);
   if (e != hipSuccess) return device_fail(e, "export_geometry kernel");
+  e = h->ws_uses.note(s);  // the export reads the workspace
+  if (e != hipSuccess) return device_fail(e, "hipEventRecord(geometry export)");
   return PSFLIB_OK;
 }
 
@@ -461,6 +569,8 @@ psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
                                  const double* d_theta, float* d_scene, void* stream) {
   psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_scene);
   if (st != PSFLIB_OK) return st;
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   hipError_t e = psflib::launch_render_disk(N, scene_pixscale, rmax, d_theta, d_scene,
                                             reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "render_disk kernel");
@@ -474,12 +584,14 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   if (st != PSFLIB_OK) return st;
   if (!d_dtheta) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be non-NULL");
   if (!aligned16(d_dtheta)) return fail(PSFLIB_ERR_INVALID_ARG, "d_dtheta must be 16-byte aligned");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
   void* scratch = nullptr;
-  e = scratch_alloc(&scratch, psflib::render_disk_grad_scratch_bytes(N), dev, s);
+  e = psflib::pool_alloc(&scratch, psflib::render_disk_grad_scratch_bytes(N), dev, s);
   if (e != hipSuccess) return device_fail(e, "scratch allocation (disk gradient)");
   e = psflib::launch_render_disk_grad(N, scene_pixscale, rmax, d_theta, d_dscene, d_dtheta,
                                       scratch, s);
@@ -491,8 +603,9 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
 
 void psflib_destroy(psflib_handle* h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
-  (void)hipFree(h->ws);
+  // wait for this handle's own uses of its workspace (not for the device)
+  h->ws_uses.wait_all();
+  (void)psflib::pool_release(h->ws, h->device);
   delete h;
 }
 

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "psflib.h"
 
 namespace psflib {
@@ -50,6 +54,35 @@ bool compute_layout(const psflib_desc& d, Layout* L);
 // Error helpers of the ABI layer (record the message for psflib_last_error).
 psflib_status fail_status(psflib_status s, const char* msg);
 psflib_status device_fail_status(hipError_t e, const char* what);
+// PSFLIB_ERR_DEVICE if a HIP error is pending on this thread from earlier
+// work (an asynchronous fault, or a failed runtime call): checked after
+// validation and before anything is enqueued.
+psflib_status check_pending_error();
+
+// Stream-ordered device memory from the library's pool for `dev` (one pool
+// per device, kept until the process ends; freed blocks are reused).
+hipError_t pool_alloc(void** p, size_t bytes, int dev, hipStream_t s);
+// Return pool memory that no queued work uses any more (the caller has waited
+// for its users): freed on a library-internal stream of `dev`, so nothing
+// the caller enqueued waits for it.
+hipError_t pool_release(void* p, int dev);
+
+// The streams that used an object's device memory: one event per stream,
+// re-recorded at every use, so that releasing the object waits for its own
+// work only, not for the whole device.  Uses on a stream that is being
+// captured are not recorded (a graph that uses the object must finish before
+// the object is released).
+class StreamUses {
+ public:
+  hipError_t note(hipStream_t s);
+  void wait_all();  // host-wait for every recorded use, then forget them
+  ~StreamUses();
+
+ private:
+  std::mutex mu_;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> ev_;
+};
+
 // Read-only view of a built library for the grouped apply.
 void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
                  int64_t* ncols, int64_t* ncols_pad, int* storage, int* device);

@@ -308,30 +308,47 @@ class Library:
 
     def _vec(self, x, size, name):
         t = self.torch
-        if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float32 and x.numel() == size):
-            raise ValueError(f"{name} must be a float32 CUDA tensor with {size} elements")
+        if not (isinstance(x, t.Tensor) and x.dtype == t.float32 and x.device == self.device
+                and x.numel() == size):
+            raise ValueError(f"{name} must be a float32 tensor on {self.device} with {size} elements")
         return x.contiguous()
+
+    def _out(self, out, shape, name):
+        """A new output tensor, or the caller's `out` after checking that the
+        kernels can write all of it and nothing past it."""
+        t = self.torch
+        if out is None:
+            return t.empty(shape, dtype=t.float32, device=self.device)
+        numel = 1
+        for s in shape:
+            numel *= int(s)
+        if not (isinstance(out, t.Tensor) and out.dtype == t.float32 and out.device == self.device
+                and out.is_contiguous() and out.numel() == numel):
+            raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device} with "
+                             f"{numel} elements")
+        return out
 
     def apply(self, scene, out=None, stream=None):
         Z = self._vec(scene, self.ncols, "scene")
-        out = self.torch.empty(self.M, dtype=self.torch.float32, device=self.device) if out is None else out
+        out = self._out(out, (self.M,), "out")
         apply(self.h, Z.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
     def apply_adjoint(self, g, out=None, stream=None):
         G = self._vec(g, self.M, "g")
-        out = self.torch.empty(self.ncols, dtype=self.torch.float32, device=self.device) if out is None else out
+        out = self._out(out, (self.ncols,), "out")
         apply_adjoint(self.h, G.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
     def apply_batched(self, scenes, out=None, stream=None):
         t = self.torch
-        if not (isinstance(scenes, t.Tensor) and scenes.is_cuda and scenes.dtype == t.float32
-                and scenes.dim() == 2 and scenes.shape[1] == self.ncols):
-            raise ValueError(f"scenes must be a float32 CUDA tensor [B][{self.ncols}]")
+        if not (isinstance(scenes, t.Tensor) and scenes.dtype == t.float32
+                and scenes.device == self.device and scenes.dim() == 2
+                and scenes.shape[1] == self.ncols):
+            raise ValueError(f"scenes must be a float32 tensor [B][{self.ncols}] on {self.device}")
         Zb = scenes.contiguous()
         B = int(Zb.shape[0])
-        out = t.empty((B, self.M), dtype=t.float32, device=self.device) if out is None else out
+        out = self._out(out, (B, self.M), "out")
         apply_batched(self.h, Zb.data_ptr(), out.data_ptr(), B, self._stream(stream))
         return out
 

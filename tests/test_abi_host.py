@@ -126,3 +126,59 @@ def test_largest_library_size_is_representable():
     d = psflib.make_desc(8192, 2, 46340, 1.0)
     b = psflib.library_bytes(d)
     assert b >= 8192**2 * 46340**2 * 4
+
+
+def _unbuilt_library(device):
+    """A Library wrapper whose checks can run without a GPU: its handle is
+    NULL, so a call that got past the binding's checks would come back from the
+    C ABI as INVALID_ARG (a NULL handle), never reach a device."""
+    import torch
+    lib = object.__new__(psflib.Library)
+    lib.torch = torch
+    lib.device = torch.device(device)
+    lib.M, lib.ncols = 6, 4
+    lib.h = None
+    return lib
+
+
+def test_binding_checks_outputs_before_the_call():
+    """`out=` tensors must be float32, contiguous, on the library's device and
+    exactly the output's size: the kernels write every element and nothing
+    past it, so anything else is rejected before the C call."""
+    import torch
+    lib = _unbuilt_library("cpu")
+    Z, g, Zb = torch.zeros(4), torch.zeros(6), torch.zeros(3, 4)
+    bad = {
+        "apply": (lambda o: lib.apply(Z, out=o, stream=0), 6),
+        "apply_adjoint": (lambda o: lib.apply_adjoint(g, out=o, stream=0), 4),
+        "apply_batched": (lambda o: lib.apply_batched(Zb, out=o, stream=0), 18),
+    }
+    for name, (call, numel) in bad.items():
+        for out in (torch.zeros(numel - 1), torch.zeros(numel + 1),
+                    torch.zeros(numel, dtype=torch.float64), torch.zeros(numel, dtype=torch.float16),
+                    torch.zeros(2 * numel)[::2], "not a tensor"):
+            with pytest.raises(ValueError):
+                call(out)
+        # a valid output gets through the binding and stops at the NULL handle
+        with pytest.raises(psflib.PsflibError) as e:
+            call(torch.zeros(numel))
+        assert e.value.status == psflib.ERR_INVALID_ARG, name
+
+
+def test_binding_checks_input_devices():
+    """Scenes and image-space vectors on another device than the library are
+    rejected (the kernels would read host memory as device memory)."""
+    import torch
+    lib = _unbuilt_library("cuda:0")  # no GPU needed: the check compares devices
+    with pytest.raises(ValueError):
+        lib.apply(torch.zeros(4))
+    with pytest.raises(ValueError):
+        lib.apply_adjoint(torch.zeros(6))
+    with pytest.raises(ValueError):
+        lib.apply_batched(torch.zeros(2, 4))
+    lib2 = _unbuilt_library("cpu")
+    for bad in (torch.zeros(5), torch.zeros(4, dtype=torch.float64), [0.0] * 4):
+        with pytest.raises(ValueError):
+            lib2.apply(bad)
+    with pytest.raises(ValueError):
+        lib2.apply_batched(torch.zeros(2, 5))

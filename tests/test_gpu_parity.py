@@ -262,9 +262,9 @@ def test_batched_multi_pass(torch, psflib, storage):
 
 
 def test_apply_and_adjoint_in_a_graph(torch, psflib, c1):
-    """psflib_apply and psflib_apply_adjoint allocate nothing and launch only
-    kernels, so they can be captured in a HIP graph: every replay (with eager
-    work and synchronisations between replays) equals the eager result
+    """psflib_apply and psflib_apply_adjoint can be captured in a HIP graph
+    (their partial sums become the graph's own allocation): every replay (with
+    eager work and synchronisations between replays) equals the eager result
     bitwise."""
     lib = psflib.Library(torch.from_numpy(c1["cube"]).cuda(), c1["radii"], c1["N"], c1["S"])
     Z = torch.from_numpy(c1["scene"]).cuda()
@@ -295,6 +295,68 @@ def test_apply_and_adjoint_in_a_graph(torch, psflib, c1):
         assert torch.equal(img, eager_img), rep
         assert torch.equal(grad, eager_grad), rep
     del graph
+    lib.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_concurrent_calls_on_one_handle(torch, psflib, storage):
+    """One built handle used from two streams at once (the handle is read-only
+    after the build; every call takes its partial sums for itself): applies,
+    adjoints and batched products interleaved over two streams equal the
+    serial results bitwise.  160 x 160 PSFs give split-K partials in both the
+    forward product and the adjoint (more than 16384 image rows)."""
+    rng = np.random.default_rng(77)
+    n, N, K = 160, 48, 6
+    cube = rng.random((K, n, n)).astype(np.float32)
+    lib = _lib(torch, psflib, cube, np.linspace(0.0, 4.0, K), N, 0.125, storage=storage)
+    M, ncols = n * n, N * N
+    Z = torch.from_numpy(rng.random((8, ncols)).astype(np.float32)).cuda()
+    G = torch.from_numpy(rng.standard_normal((8, M)).astype(np.float32)).cuda()
+    ref_img = torch.stack([lib.apply(Z[k]) for k in range(8)])
+    ref_adj = torch.stack([lib.apply_adjoint(G[k]) for k in range(8)])
+    ref_bat = lib.apply_batched(Z[:5])
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        img = torch.zeros_like(ref_img)
+        adj = torch.zeros_like(ref_adj)
+        bat = torch.zeros_like(ref_bat)
+        for st in streams:
+            st.wait_stream(torch.cuda.current_stream())
+        for k in range(8):
+            with torch.cuda.stream(streams[k % 2]):
+                lib.apply(Z[k], out=img[k])
+                lib.apply_adjoint(G[k], out=adj[k])
+                if k == 3:
+                    lib.apply_batched(Z[:5], out=bat)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref_img), rep
+        assert torch.equal(adj, ref_adj), rep
+        assert torch.equal(bat, ref_bat), rep
+    lib.close()
+
+
+def test_pending_runtime_error_is_reported_before_any_work(torch, psflib, c1):
+    """A HIP runtime error left pending on the thread by an earlier call (here
+    a failed hipSetDevice whose status nobody read) is returned as
+    PSFLIB_ERR_DEVICE before anything is enqueued, and cleared: the next call
+    runs normally."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime torch and psflib share
+    lib = _lib(torch, psflib, c1["cube"], c1["radii"], c1["N"], c1["S"])
+    Z = torch.from_numpy(c1["scene"]).cuda()
+    out = torch.full((lib.M,), 7.0, device="cuda")
+    ref = lib.apply(Z)
+    torch.cuda.synchronize()
+    assert hip.hipSetDevice(ctypes.c_int(1 << 20)) != 0
+    with pytest.raises(psflib.PsflibError) as e:
+        lib.apply(Z, out=out)
+    assert e.value.status == psflib.ERR_DEVICE and "pending" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all()), "nothing may be enqueued"
+    lib.apply(Z, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
     lib.close()
 
 

@@ -489,6 +489,50 @@ def test_scale_exponent_and_bound():
     assert np.all(A.max(axis=0) <= bound * (1 + 1e-15))
 
 
+def test_quantize_library_pins():
+    """Mantissas M_ij = RN(A_ij 2^-e_j): pinned to the formats' own conversions
+    (numpy float16, torch bfloat16), to a worked value, and to the range the
+    exponent rule promises, on columns whose scales span 14 decades."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(13)
+    ncol = 24
+    # float32 entries (as the GPU rounds them), column scales 1e-12 .. 1e2
+    A = (rng.random((300, ncol)) ** 3 * 10.0 ** rng.uniform(-12, 2, ncol)).astype(np.float32)
+    A[rng.random(A.shape) < 0.05] = 0.0
+    A[:, 5] = 0.0  # an identically zero column
+    A = A.astype(np.float64)
+    b = A.max(axis=0)
+    e = O.pow2_exponents(b)
+    live = b > 0
+    assert e[5] == O.ZERO_COLUMN_EXPONENT
+    # worked value: 3 = 0.75 * 2^2, so e = 2 - 15 = -13 and M = 3 * 2^13 = 24576
+    # (an exponent of the wrong sign would give 3 * 2^-13, far below the range)
+    assert O.scale_exponent(3.0) == -13
+    for fmt in ("fp16", "bf16"):
+        assert O.quantize_library(np.array([[3.0]]), np.array([-13]), fmt)[0, 0] == 24576.0
+    scaled = np.ldexp(A, -e.astype(np.int64)[None, :])
+    for fmt, u in (("fp16", 2.0**-11), ("bf16", 2.0**-8)):
+        Mq = O.quantize_library(A, e, fmt)
+        # the formats' own round-to-nearest-even conversions
+        if fmt == "fp16":
+            ref = scaled.astype(np.float16).astype(np.float64)
+        else:
+            ref = torch.from_numpy(scaled.astype(np.float32)).to(torch.bfloat16).double().numpy()
+        np.testing.assert_array_equal(Mq, ref)
+        # the largest mantissa of every live column lands in [2^14, 2^15]
+        top = np.abs(Mq[:, live]).max(axis=0)
+        assert np.all(top >= 2**14) and np.all(top <= 2**15), top
+        # M 2^e reproduces A to the format's unit (FP16: plus half its
+        # subnormal spacing 2^-25 for entries below its normal range)
+        rec = np.ldexp(Mq, e.astype(np.int64)[None, :])
+        sub = 2.0**-25 * np.ldexp(1.0, e.astype(np.int64))[None, :] if fmt == "fp16" else 0.0
+        assert np.all(np.abs(rec - A) <= u * np.abs(A) + sub)
+        assert np.all(Mq[:, 5] == 0) and np.all(Mq[A == 0] == 0)
+        # a sign error in the exponent leaves the range: scaling by 2^+e
+        wrong = O.round_to_format(np.ldexp(A, e.astype(np.int64)[None, :]), fmt)
+        assert not np.all(np.abs(wrong[:, live]).max(axis=0) >= 2**14)
+
+
 # ------------------------------------------------------ fitting model ------
 THETA = (math.radians(55.0), 5.0, 1.2, -1.4, 3e-8)
 
