@@ -176,6 +176,28 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
  * allocation becomes part of the graph, so each graph owns its partials. */
 psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream);
 
+/* ---- Allocation-free apply -------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture that must not record allocations, tight serving loops, harnesses
+ * that forbid hipMalloc.  The same product as psflib_apply (same kernels,
+ * same summation order, so the image is bitwise equal), with the split-K
+ * partial sums in a fixed device array of PSFLIB_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends; the call
+ * allocates and frees nothing.
+ *   The array is shared by every psflib_apply_noalloc call on that GPU and
+ * keeps the last call's contents (nothing in it needs clearing: every
+ * partial is written before it is read).  Calls that overlap on one GPU --
+ * on different streams, or in graph replays running at once -- race on it
+ * and give wrong images: order them (one stream, or events).
+ *   Fails with PSFLIB_ERR_SIZE, before enqueuing anything, if the library needs
+ * more partial sums than the array holds.  FP32 libraries need at most 4 MiB;
+ * 16-bit ones at most max(1.5 MiB, ceil(N*N / 4096) * n*n * 4 bytes), which
+ * can pass 8 MiB only when n*n*N*N > 2^32 (16-bit libraries of more than
+ * 8 GiB, e.g. n = 128 with N >= 1024). */
+#define PSFLIB_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+psflib_status psflib_apply_noalloc(const psflib_handle* h, const float* d_scene, float* d_image,
+                                   void* stream);
+
 /* Adjoint G = A^T g of the simulation S = A Z (Sec. 3, Eq. (6)): the
  * gradient of <g, A Z> with respect to the scene Z, which a retrieval of
  * scene parameters from simulated images needs (Sec. 5 plans such a

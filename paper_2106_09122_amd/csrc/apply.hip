@@ -14,6 +14,9 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <map>
+#include <mutex>
+
 #include "psflib_internal.h"
 
 namespace psflib {
@@ -455,6 +458,31 @@ hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, con
   reduce_cols_kernel<<<(unsigned)((ncols + 255) / 256), 256, 0, s>>>(
       partial, nb, stride, ncols, storage == PSFLIB_FP32 ? nullptr : exps, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------- allocation-free scratch -----
+// Partial sums of psflib_apply_noalloc: a fixed device array on every GPU the
+// library runs on, held until the process ends and shared by every such call
+// on that GPU.  In host code the array's name is not a device address: the
+// address is looked up once per device with hipGetSymbolAddress (that device
+// current) and kept, and only that address is passed to kernels.
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+hipError_t noalloc_scratch(int dev, void** ptr) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) {
+    *ptr = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  addr[dev] = p;
+  *ptr = p;
+  return hipSuccess;
 }
 
 // ----------------------------------------------------------- columns ------

@@ -444,6 +444,31 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
   return pooled_product(h, false, d_scene, d_image, reinterpret_cast<hipStream_t>(stream));
 }
 
+psflib_status psflib_apply_noalloc(const psflib_handle* h, const float* d_scene, float* d_image,
+                                   void* stream) {
+  psflib_status st = check_handle(h);
+  if (st != PSFLIB_OK) return st;
+  if (!d_scene || !d_image) return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be non-NULL");
+  if (!aligned16(d_scene) || !aligned16(d_image))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be 16-byte aligned");
+  const int64_t floats =
+      psflib::matvec_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad);
+  if ((uint64_t)floats * 4 > psflib::kNoAllocScratchBytes)
+    return fail(PSFLIB_ERR_SIZE, "psflib_apply_noalloc: this library needs " +
+                                     std::to_string((uint64_t)floats * 4) +
+                                     " bytes of partial sums, more than the fixed scratch of " +
+                                     std::to_string(psflib::kNoAllocScratchBytes) + " bytes");
+  st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  void* part = nullptr;
+  hipError_t e = psflib::noalloc_scratch(h->device, &part);
+  if (e != hipSuccess) return device_fail(e, "hipGetSymbolAddress(scratch)");
+  e = launch_product(h, false, d_scene, d_image, reinterpret_cast<float*>(part),
+                     reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "matvec kernels");
+  return PSFLIB_OK;
+}
+
 psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
                                    void* stream) {
   psflib_status st = check_handle(h);

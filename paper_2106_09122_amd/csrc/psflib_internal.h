@@ -83,6 +83,13 @@ class StreamUses {
   std::vector<std::pair<hipStream_t, hipEvent_t>> ev_;
 };
 
+// Fixed device scratch of the allocation-free apply (psflib_apply_noalloc):
+// a file-scope device array of kNoAllocScratchBytes on every GPU the library
+// runs on.  noalloc_scratch gives its address on device `dev` (the current
+// device), looked up once per device.
+constexpr size_t kNoAllocScratchBytes = PSFLIB_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch(int dev, void** ptr);
+
 // Read-only view of a built library for the grouped apply.
 void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
                  int64_t* ncols, int64_t* ncols_pad, int* storage, int* device);

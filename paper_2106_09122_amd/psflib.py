@@ -67,6 +67,7 @@ def _load():
         "psflib_build": (I32, [DP, P, ctypes.POINTER(ctypes.c_double), P, SZ, P,
                                ctypes.POINTER(P)]),
         "psflib_apply": (I32, [P, P, P, P]),
+        "psflib_apply_noalloc": (I32, [P, P, P, P]),
         "psflib_apply_adjoint": (I32, [P, P, P, P]),
         "psflib_apply_batched": (I32, [P, P, P, I32, P]),
         "psflib_column_sums": (I32, [P, P, P]),
@@ -93,7 +94,7 @@ _lib = _load()
 #: every symbol the header declares
 SYMBOLS = (
     "psflib_status_string", "psflib_last_error", "psflib_library_bytes", "psflib_build",
-    "psflib_apply", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
+    "psflib_apply", "psflib_apply_noalloc", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
     "psflib_render_disk", "psflib_render_disk_grad", "psflib_grouped_create",
     "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_destroy",
@@ -142,6 +143,12 @@ def build(desc: Desc, d_cube: int, radii, d_lib: int, lib_bytes: int, stream: in
 def apply(h: int, d_scene: int, d_image: int, stream: int):
     _check(_lib.psflib_apply(ctypes.c_void_p(h), ctypes.c_void_p(d_scene), ctypes.c_void_p(d_image),
                              ctypes.c_void_p(stream)), "psflib_apply")
+
+
+def apply_noalloc(h: int, d_scene: int, d_image: int, stream: int):
+    _check(_lib.psflib_apply_noalloc(ctypes.c_void_p(h), ctypes.c_void_p(d_scene),
+                                     ctypes.c_void_p(d_image), ctypes.c_void_p(stream)),
+           "psflib_apply_noalloc")
 
 
 def apply_adjoint(h: int, d_g: int, d_out: int, stream: int):
