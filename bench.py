@@ -122,14 +122,45 @@ def _time_build(torch, psflib, desc, cube, radii, buf, nbytes, reps=3):
     return best
 
 
-def cpu_baseline(d, sample_cols: int):
-    """The FP64 oracle, as it stands, on the host: build a seeded sample of
-    library columns, then time S = A Z over that slice and scale to the full
-    library (the product is linear in the number of columns)."""
+def probes(torch, psflib, dev):
+    """Ceilings measured on this part (the library's probe kernels): the best
+    16-byte-load read rate over a sweep of launch shapes on a 2 GiB buffer,
+    and the matrix cores' issue rate (FP32, BF16, FP16) on register operands.
+    Each is timed with HIP events on the stream the probe runs on."""
+    st = torch.cuda.current_stream().cuda_stream
+    sink = torch.zeros(65536, dtype=torch.float32, device=dev)
+    nbytes = 2 << 30
+    buf = torch.zeros(nbytes // 4, dtype=torch.float32, device=dev)
+    sweep = {}
+    for slice_ in (False, True):
+        for wg in (1024, 2048, 4096, 8192, 16384):
+            for un in (4, 8, 16):
+                ms = _timed(torch, lambda: psflib.probe_hbm_read(buf.data_ptr(), nbytes, wg, un, slice_,
+                                                                 sink.data_ptr(), st), 10, 2)
+                sweep[f"{'slice' if slice_ else 'stride'}_wg{wg}_u{un}"] = nbytes / (ms * 1e-3) / 1e9
+    del buf
+    best = max(sweep, key=sweep.get)
+    out = {"hbm_read_GB_per_s": sweep[best], "hbm_read_shape": best,
+           "hbm_read_sweep_GB_per_s": {k: round(v, 1) for k, v in sweep.items()}}
+    wgs = 1024  # 4 workgroups of 4 waves per CU: four waves on every SIMD
+    for kind, name, flop, iters in ((0, "fp32", 4096, 8000), (1, "bf16", 32768, 16000),
+                                    (2, "fp16", 32768, 16000)):
+        ms = _timed(torch, lambda: psflib.probe_mfma(kind, iters, wgs, sink.data_ptr(), st), 10, 3)
+        out[f"mfma_{name}_TFLOP_per_s"] = wgs * 4 * iters * 4 * flop / (ms * 1e-3) / 1e12
+    return out
+
+
+def cpu_baseline(d, ref_scenes):
+    """The FP64 oracle, as it stands, on the host.  It builds the library
+    columns on which the reference scenes are non-zero (their common support:
+    the field inside the last sampled offset), times S = A Z over them and
+    scales to the full library (the product is linear in the number of
+    columns).  The same columns give the exact FP64 images of every scene in
+    `ref_scenes` (columns outside the support multiply zeros), which the
+    reduced-precision rows are measured against."""
     import numpy as np
 
     import oracle
-    import synth
 
     try:
         import threadpoolctl
@@ -139,9 +170,8 @@ def cpu_baseline(d, sample_cols: int):
         threads = os.cpu_count() or 1
     N = d["N"]
     ncols = N * N
-    rng = synth.rng_for(2, synth.STREAM_SUBSAMPLE)
-    start = int(rng.integers(0, ncols - sample_cols + 1))
-    cols = np.arange(start, start + sample_cols)
+    Zs = np.stack([np.asarray(z, dtype=np.float32).reshape(-1) for z in ref_scenes])
+    cols = np.nonzero(np.any(Zs != 0, axis=0))[0]
     t0 = time.perf_counter()
     A = oracle.build_library(d["cube"], d["radii"], N, d["S"], columns=cols)
     t_build = time.perf_counter() - t0
@@ -151,16 +181,33 @@ def cpu_baseline(d, sample_cols: int):
         t0 = time.perf_counter()
         oracle.apply(A, Z)
         reps.append(time.perf_counter() - t0)
-    t_apply = float(np.median(reps)) * (ncols / sample_cols)
+    t_apply = float(np.median(reps)) * (ncols / cols.size)
+    refs = oracle.apply_batched(A, Zs[:, cols])
+    del A
     return {
         "value": 1.0 / t_apply, "unit": "scenes/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"FP64 oracle: {sample_cols} contiguous library columns built "
-                   f"({sample_cols / t_build:.1f} columns/s, one core), then S = A Z over that "
-                   f"slice with numpy BLAS, median of 10, scaled by {ncols}/{sample_cols} to the "
-                   f"full 16384-column library"),
-        "build_columns_per_s": sample_cols / t_build,
+        "sample": (f"FP64 oracle: the {cols.size} library columns inside the last sampled offset "
+                   f"built ({cols.size / t_build:.1f} columns/s, one core), then S = A Z over them "
+                   f"with numpy BLAS, median of 10, scaled by {ncols}/{cols.size} to the full "
+                   f"16384-column library"),
+        "build_columns_per_s": cols.size / t_build,
         "host_cpu": _lscpu_model(), "host_cpu_count": os.cpu_count(),
-    }
+    }, refs
+
+
+def image_errors(got, ref):
+    """Errors of a float32 image against its FP64 reference: peak-normalised
+    max |dS| / max S, the largest per-pixel relative error over pixels above
+    1e-6 of the peak, and the relative L2 error."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    d = np.abs(got - ref)
+    peak = np.abs(ref).max()
+    big = np.abs(ref) > 1e-6 * peak
+    return {"peak_normalised": float(d.max() / peak),
+            "max_rel_above_1e-6_of_peak": float(np.max(d[big] / np.abs(ref[big]))),
+            "l2_rel": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
 
 
 def main():
@@ -168,8 +215,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-sample-cols", type=int, default=12288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true", help="skip the measured-ceiling probes")
     ap.add_argument("--no-rows", action="store_true", help="time only the headline matvec")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates profiler byte counters)")
@@ -196,6 +243,8 @@ def main():
     print(f"[bench] workload n={n} N={N} K={K}: building FP32 library", file=sys.stderr, flush=True)
 
     rows = {}
+    ref_scenes = [d["scene"]]   # scenes whose FP64 oracle images the CPU leg computes
+    gpu_images = {}             # name -> (index into ref_scenes, float32 image on the host)
     lib = psflib.Library(cube, d["radii"], N, S, storage="fp32")
     torch.cuda.synchronize()
 
@@ -205,6 +254,8 @@ def main():
     alg_bytes = lib_bytes + 4 * (M + ncols)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     print(f"[bench] fp32 apply {ms * 1e3:.1f} us/scene, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    gpu_images["fp32"] = (0, lib.apply(scene).cpu().numpy())
+    ceil = None if args.no_probes else probes(torch, psflib, dev)
     if args.copy_probe:
         src = torch.empty(2**28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -259,6 +310,8 @@ def main():
             fl = 2.0 * M * ncols * B
             ent = {"ms": t_b, "scenes_per_s": B / (t_b * 1e-3), "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
                    "frac_mfma_fp32": fl / (t_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+            if ceil:
+                ent["frac_mfma_fp32_of_measured"] = fl / (t_b * 1e-3) / 1e12 / ceil["mfma_fp32_TFLOP_per_s"]
             if B < 40:  # below the ridge (157.3 TF / 8 TB/s): the library read binds
                 gbs = (lib_bytes + 4 * B * (M + ncols)) / (t_b * 1e-3) / 1e9
                 ent.update({"bound": "hbm", "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS})
@@ -345,25 +398,38 @@ def main():
                 Lb.close()
             del Ls, gp
         del Zm
+        batches = {B: synth.scene_batch(N, S, B, config=2, rmax_mask=8.0) for B in (256, 512, 1024)}
+        NREF = 16  # scenes per batch whose FP64 images the CPU leg computes
+        for B, Zb_h in batches.items():
+            ref_scenes.extend(Zb_h[:NREF])
         for fmt in ("bf16", "fp16"):
             lh = psflib.Library(cube, d["radii"], N, S, storage=fmt)
             torch.cuda.synchronize()
             t_b16 = _time_build(torch, psflib, lh.desc, cube, d["radii"], lh.buf, lh.nbytes)
             ms16 = _timed(torch, lambda: lh.apply(scene, out=image), args.steps, args.warmup)
-            img16 = lh.apply(scene).double()
+            img16 = lh.apply(scene)
+            gpu_images[fmt] = (0, img16.cpu().numpy())
+            img16 = img16.double()
             err = float((img16 - ref_img).abs().max() / ref_img.abs().max())
             ent = {"build_ms": t_b16, "apply_us": ms16 * 1e3, "scenes_per_s": 1e3 / ms16,
                    "GB_per_s": (M * ((ncols + 63) // 64 * 64) * 2 + 4 * (M + 2 * ncols)) / (ms16 * 1e-3) / 1e9,
                    "speedup_vs_fp32": ms / ms16,
                    "peak_normalised_error_vs_fp32": err}
-            for B in (256, 512, 1024):
-                Zb = torch.from_numpy(synth.scene_batch(N, S, B, config=2, rmax_mask=8.0)).to(dev)
+            for bi, (B, Zb_h) in enumerate(batches.items()):
+                Zb = torch.from_numpy(Zb_h).to(dev)
                 out = torch.empty((B, M), device=dev, dtype=torch.float32)
                 t_b = _timed(torch, lambda: lh.apply_batched(Zb, out=out), 10, 3)
                 fl = 2.0 * M * ncols * B
                 ent[f"batched_B{B}"] = {"ms": t_b, "scenes_per_s": B / (t_b * 1e-3),
                                         "TFLOP_per_s": fl / (t_b * 1e-3) / 1e12,
                                         "frac_mfma": fl / (t_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[fmt]}
+                if ceil:
+                    ent[f"batched_B{B}"]["frac_mfma_of_measured"] = (
+                        fl / (t_b * 1e-3) / 1e12 / ceil[f"mfma_{fmt}_TFLOP_per_s"])
+                lh.apply_batched(Zb, out=out)
+                host = out[:NREF].cpu().numpy()
+                for r in range(NREF):
+                    gpu_images[f"{fmt}_B{B}_{r}"] = (1 + bi * NREF + r, host[r])
                 del Zb, out
             rows[f"{fmt}_pow2"] = ent
             lh.close()
@@ -372,7 +438,24 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(d, args.cpu_sample_cols)
+        cpu, refs = cpu_baseline(d, ref_scenes)
+        # every image against the exact FP64 image of the same scene
+        errs = {"fp32": image_errors(gpu_images["fp32"][1], refs[0])}
+        for fmt in ("bf16", "fp16"):
+            if fmt not in gpu_images:
+                continue
+            e16 = image_errors(gpu_images[fmt][1], refs[0])
+            ent = rows[f"{fmt}_pow2"]
+            ent["error_vs_fp64"] = e16
+            ent["meets_1e-3_vs_fp64"] = e16["peak_normalised"] <= 1e-3
+            for key in list(ent):
+                if key.startswith("batched_B"):
+                    B = key[len("batched_B"):]
+                    worst = max(image_errors(img, refs[i])["peak_normalised"]
+                                for name, (i, img) in gpu_images.items()
+                                if name.startswith(f"{fmt}_B{B}_"))
+                    ent[key]["peak_normalised_error_vs_fp64_worst_of_16"] = worst
+        rows["fp32_error_vs_fp64"] = errs["fp32"]
 
     line = {
         "metric": "scenes/sec + % HBM (matvec) / % MFMA (batched) at 128², FP32 vs BF16-scaled",
@@ -394,7 +477,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _profiled_traffic(),
-                     "kernel": "matvec_f32_kernel", "algorithmic_bytes_per_launch": alg_bytes},
+                     "kernel": "matvec_f32_kernel", "algorithmic_bytes_per_launch": alg_bytes,
+                     "measured_peak": ceil["hbm_read_GB_per_s"] if ceil else None,
+                     "frac_of_measured": achieved / ceil["hbm_read_GB_per_s"] if ceil else None},
+        "measured_ceilings": ceil,
         "cpu_baseline": cpu,
         "rows": rows,
     }

@@ -39,12 +39,17 @@
  *    call on the calling thread.
  *  - After psflib_build returns, a handle is read-only: psflib_apply,
  *    psflib_apply_adjoint, psflib_apply_batched and the read-back calls may
- *    run concurrently on different streams with one handle (each call takes
- *    its temporary device memory for itself, stream-ordered, from a pool the
- *    library keeps per device).  Work that uses the library must be ordered
- *    after the build on the build's stream (same stream, or an event).
- *  - Device memory the library allocates for itself comes from that pool:
- *    freed blocks are kept for reuse by later calls until the process ends.
+ *    run concurrently on different streams, and from different host threads,
+ *    with one handle.  No two streams share temporary device memory: the
+ *    batched call takes its scratch per call, stream-ordered, from a pool the
+ *    library keeps per device, and the split-K partial sums of psflib_apply
+ *    and psflib_apply_adjoint live in one buffer per stream (shared, in
+ *    stream order, by every call on that stream).  Work that uses the library
+ *    must be ordered after the build on the build's stream (same stream, or
+ *    an event).
+ *  - Device memory the library allocates for itself comes from that pool and
+ *    is kept for reuse until the process ends (the per-stream partial-sum
+ *    buffers too: a few MiB per stream the products ran on).
  */
 #ifndef PSFLIB_H
 #define PSFLIB_H
@@ -171,9 +176,10 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
  *   d_scene  float32 [N*N] scene (flattened row-major, Sec. 3).
  *   d_image  float32 [n*n] output image.
  * Float32 accumulation in a fixed order (results are bitwise reproducible).
- * The split-K partial sums (a few MiB) are taken from the device pool for
- * this call, stream-ordered on `stream`; under stream capture that
- * allocation becomes part of the graph, so each graph owns its partials. */
+ * The split-K partial sums (a few MiB) sit in the buffer of `stream` (created
+ * from the device pool on the first call on that stream, enlarged when a
+ * larger library needs more); under stream capture they are allocated from
+ * the pool inside the graph instead, so each graph owns its partials. */
 psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream);
 
 /* ---- Allocation-free apply -------------------------------------------------
@@ -205,7 +211,7 @@ psflib_status psflib_apply_noalloc(const psflib_handle* h, const float* d_scene,
  *   d_g           float32 [n*n] image-space vector.
  *   d_scene_grad  float32 [N*N] output.
  * Float32 accumulation in a fixed order.  Partial sums (PSFs larger than
- * 128 x 128 only) come from the device pool as in psflib_apply. */
+ * 128 x 128 only) are kept as in psflib_apply. */
 psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, float* d_scene_grad,
                                    void* stream);
 
@@ -311,6 +317,31 @@ psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
 psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double rmax,
                                       const double* d_theta, const float* d_dscene,
                                       double* d_dtheta, void* stream);
+
+/* ---- Measurement probes ---------------------------------------------------
+ * Not part of the method: they measure, on the part itself, the ceilings the
+ * products are compared against (the paper times its simulation against CPU
+ * hardware, Table 4; here the reference points are the GPU's own memory and
+ * matrix-core rates).
+ *
+ * psflib_probe_hbm_read: one kernel that streams `bytes` (rounded down to a
+ * multiple of 16) of the device buffer d_buf with 16-byte non-temporal
+ * loads over `workgroups` workgroups of 256 threads with `unroll` (4, 8 or
+ * 16) loads in flight per thread, and sums what it reads.  slice = 0: the
+ * workgroups stride over the buffer together (4 KiB runs w, w + grid, ...);
+ * slice != 0: each workgroup streams its own contiguous 1/workgroups of it.
+ * Rate = bytes / kernel time.  d_sink: float32 [workgroups], written only for
+ * an impossible sum (it keeps the loads alive). */
+psflib_status psflib_probe_hbm_read(const void* d_buf, size_t bytes, int32_t workgroups,
+                                    int32_t unroll, int32_t slice, float* d_sink, void* stream);
+
+/* psflib_probe_mfma: `workgroups` workgroups of 4 waves; every wave runs
+ * `iters` rounds of 4 independent matrix-core products on register operands:
+ * kind 0 = v_mfma_f32_32x32x2f32 (4096 flop each), 1 = ..._32x32x16_bf16,
+ * 2 = ..._32x32x16_f16 (32768 flop each).  Rate = workgroups * 4 * iters * 4
+ * * flop / kernel time.  d_sink as above. */
+psflib_status psflib_probe_mfma(int32_t kind, int32_t iters, int32_t workgroups, float* d_sink,
+                                void* stream);
 
 /* Release the handle and its workspace.  Waits on the host for the handle's
  * own uses of its workspace (the build and psflib_get_geometry, by events

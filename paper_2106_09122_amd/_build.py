@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG_DIR, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG_DIR, "libpsflib.so")
-SOURCES = ["psflib.hip", "geometry.hip", "build.hip", "build_lds.hip", "apply.hip", "gemm.hip", "model.hip", "grouped.hip", "spline.hip", "flux.hip"]
+SOURCES = ["psflib.hip", "geometry.hip", "build.hip", "build_lds.hip", "apply.hip", "gemm.hip", "model.hip", "grouped.hip", "spline.hip", "flux.hip", "probe.hip"]
 ARCH = "gfx950"
 
 

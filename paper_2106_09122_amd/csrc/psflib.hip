@@ -407,28 +407,78 @@ hipError_t launch_product(const psflib_handle* h, bool adjoint, const float* in,
                                h->L.ncols_pad, partial, out, s);
 }
 
-// The product with its partials taken from the device pool for this call
-// only (stream-ordered: freed after the kernels on `s`), so calls on
-// different streams share no memory.  Under stream capture the allocation
-// becomes part of the graph.
-psflib_status pooled_product(const psflib_handle* h, bool adjoint, const float* in, float* out,
-                             hipStream_t s) {
+// Split-K partial sums of psflib_apply and psflib_apply_adjoint.  Outside
+// stream capture they live in one buffer per (device, stream), kept like the
+// pool's blocks until the process ends and grown on demand: calls on one
+// stream run in order, so every call on that stream (whatever its handle) can
+// reuse the stream's buffer, and calls on different streams never share one.
+// This adds nothing to the stream per call (a stream-ordered free per call
+// would add a marker, ~3 us between kernels).  Under capture the partials
+// are allocated from the pool inside the graph, so every graph owns its own.
+struct StreamPartials {
+  int dev;
+  hipStream_t s;
+  void* p;
+  size_t bytes;
+};
+std::mutex g_sp_mu;
+std::vector<StreamPartials> g_sp;
+
+// Called with g_sp_mu held.
+hipError_t stream_partials(int dev, hipStream_t s, size_t bytes, void** out) {
+  StreamPartials* slot = nullptr;
+  for (auto& sp : g_sp)
+    if (sp.dev == dev && sp.s == s) slot = &sp;
+  if (slot && slot->bytes >= bytes) {
+    *out = slot->p;
+    return hipSuccess;
+  }
+  size_t want = (size_t)1 << 20;  // grow in powers of two from 1 MiB
+  while (want < bytes) want <<= 1;
+  void* p = nullptr;
+  hipError_t e = psflib::pool_alloc(&p, want, dev, s);
+  if (e != hipSuccess) return e;
+  if (slot) {
+    // the smaller buffer goes back to the pool after the work queued on s
+    e = hipFreeAsync(slot->p, s);
+    slot->p = p;
+    slot->bytes = want;
+  } else {
+    g_sp.push_back(StreamPartials{dev, s, p, want});
+  }
+  *out = p;
+  return e;
+}
+
+psflib_status product(const psflib_handle* h, bool adjoint, const float* in, float* out,
+                      hipStream_t s) {
   const int64_t floats =
       adjoint ? psflib::adjoint_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad)
               : psflib::matvec_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad);
+  const char* what = adjoint ? "adjoint kernels" : "matvec kernels";
+  if (floats == 0) {
+    hipError_t e = launch_product(h, adjoint, in, out, nullptr, s);
+    return e == hipSuccess ? PSFLIB_OK : device_fail(e, what);
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return device_fail(e, "hipStreamIsCapturing");
   void* part = nullptr;
-  hipError_t e = hipSuccess;
-  if (floats > 0) {
+  if (cs == hipStreamCaptureStatusNone) {
+    // held over both launches, so that a call from another host thread on
+    // the same stream cannot slip its kernels in between them
+    std::lock_guard<std::mutex> lock(g_sp_mu);
+    e = stream_partials(h->device, s, (size_t)floats * 4, &part);
+    if (e != hipSuccess) return device_fail(e, "partial-sum buffer");
+    e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
+  } else {
     e = psflib::pool_alloc(&part, (size_t)floats * 4, h->device, s);
     if (e != hipSuccess) return device_fail(e, "partial-sum allocation");
-  }
-  e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
-  if (part) {
+    e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
     hipError_t e2 = hipFreeAsync(part, s);
     if (e == hipSuccess) e = e2;
   }
-  if (e != hipSuccess) return device_fail(e, adjoint ? "adjoint kernels" : "matvec kernels");
-  return PSFLIB_OK;
+  return e == hipSuccess ? PSFLIB_OK : device_fail(e, what);
 }
 
 }  // namespace
@@ -441,7 +491,7 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
     return fail(PSFLIB_ERR_INVALID_ARG, "d_scene and d_image must be 16-byte aligned");
   st = psflib::check_pending_error();
   if (st != PSFLIB_OK) return st;
-  return pooled_product(h, false, d_scene, d_image, reinterpret_cast<hipStream_t>(stream));
+  return product(h, false, d_scene, d_image, reinterpret_cast<hipStream_t>(stream));
 }
 
 psflib_status psflib_apply_noalloc(const psflib_handle* h, const float* d_scene, float* d_image,
@@ -478,7 +528,7 @@ psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, flo
     return fail(PSFLIB_ERR_INVALID_ARG, "d_g and d_scene_grad must be 16-byte aligned");
   st = psflib::check_pending_error();
   if (st != PSFLIB_OK) return st;
-  return pooled_product(h, true, d_g, d_scene_grad, reinterpret_cast<hipStream_t>(stream));
+  return product(h, true, d_g, d_scene_grad, reinterpret_cast<hipStream_t>(stream));
 }
 
 psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
@@ -623,6 +673,39 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e == hipSuccess) e = e2;
   if (e != hipSuccess) return device_fail(e, "render_disk_grad kernels");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_probe_hbm_read(const void* d_buf, size_t bytes, int32_t workgroups,
+                                    int32_t unroll, int32_t slice, float* d_sink, void* stream) {
+  if (!d_buf || !d_sink) return fail(PSFLIB_ERR_INVALID_ARG, "d_buf and d_sink must be non-NULL");
+  if (!aligned16(d_buf) || !aligned16(d_sink))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_buf and d_sink must be 16-byte aligned");
+  if (workgroups < 1 || workgroups > 65536)
+    return fail(PSFLIB_ERR_INVALID_ARG, "workgroups must be in [1, 65536]");
+  if (unroll != 4 && unroll != 8 && unroll != 16)
+    return fail(PSFLIB_ERR_INVALID_ARG, "unroll must be 4, 8 or 16");
+  psflib_status st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  hipError_t e = psflib::launch_probe_hbm_read(d_buf, bytes, workgroups, unroll, slice != 0,
+                                               d_sink, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "HBM read probe");
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_probe_mfma(int32_t kind, int32_t iters, int32_t workgroups, float* d_sink,
+                                void* stream) {
+  if (kind < 0 || kind > 2) return fail(PSFLIB_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+  if (iters < 1) return fail(PSFLIB_ERR_INVALID_ARG, "iters must be >= 1");
+  if (workgroups < 1 || workgroups > 65536)
+    return fail(PSFLIB_ERR_INVALID_ARG, "workgroups must be in [1, 65536]");
+  if (!d_sink || !aligned16(d_sink))
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_sink must be non-NULL and 16-byte aligned");
+  psflib_status st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  hipError_t e = psflib::launch_probe_mfma(kind, iters, workgroups, d_sink,
+                                           reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "MFMA probe");
   return PSFLIB_OK;
 }
 

@@ -182,6 +182,15 @@ hipError_t launch_render_disk(int N, double S, double rmax, const double* theta,
 size_t render_disk_grad_scratch_bytes(int N);
 hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
                                    const float* dZ, double* dtheta, void* scratch, hipStream_t s);
+// Measurement probes (probe.hip): a 16-byte-load read stream over `bytes`
+// of `buf` (unroll 4, 8 or 16 loads in flight per thread; grid-stride, or one
+// contiguous slice per workgroup), and chains of
+// independent MFMAs (kind 0 FP32 32x32x2, 1 BF16 32x32x16, 2 FP16 32x32x16;
+// 4 waves per workgroup, 4 chains per wave); `sink` holds >= workgroups
+// floats and is written only for an impossible value.
+hipError_t launch_probe_hbm_read(const void* buf, size_t bytes, int workgroups, int unroll,
+                                 bool slice, float* sink, hipStream_t s);
+hipError_t launch_probe_mfma(int kind, int iters, int workgroups, float* sink, hipStream_t s);
 hipError_t launch_export_geometry(const ColGeom* geo, int64_t ncols, double* geom, int32_t* k,
                                   hipStream_t s);
 

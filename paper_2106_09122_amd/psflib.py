@@ -81,6 +81,8 @@ def _load():
         "psflib_grouped_destroy": (None, [P]),
         "psflib_render_disk_grad": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P, P]),
         "psflib_destroy": (None, [P]),
+        "psflib_probe_hbm_read": (I32, [P, SZ, I32, I32, I32, P, P]),
+        "psflib_probe_mfma": (I32, [I32, I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -98,6 +100,7 @@ SYMBOLS = (
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
     "psflib_render_disk", "psflib_render_disk_grad", "psflib_grouped_create",
     "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_destroy",
+    "psflib_probe_hbm_read", "psflib_probe_mfma",
 )
 
 
@@ -195,6 +198,21 @@ def render_disk_grad(N: int, S: float, rmax: float, d_theta: int, d_dscene: int,
                                         ctypes.c_void_p(d_theta), ctypes.c_void_p(d_dscene),
                                         ctypes.c_void_p(d_dtheta), ctypes.c_void_p(stream)),
            "psflib_render_disk_grad")
+
+
+def probe_hbm_read(d_buf: int, nbytes: int, workgroups: int, unroll: int, slice: bool,
+                   d_sink: int, stream: int):
+    _check(_lib.psflib_probe_hbm_read(ctypes.c_void_p(d_buf), ctypes.c_size_t(nbytes),
+                                      ctypes.c_int32(workgroups), ctypes.c_int32(unroll),
+                                      ctypes.c_int32(1 if slice else 0),
+                                      ctypes.c_void_p(d_sink), ctypes.c_void_p(stream)),
+           "psflib_probe_hbm_read")
+
+
+def probe_mfma(kind: int, iters: int, workgroups: int, d_sink: int, stream: int):
+    _check(_lib.psflib_probe_mfma(ctypes.c_int32(kind), ctypes.c_int32(iters),
+                                  ctypes.c_int32(workgroups), ctypes.c_void_p(d_sink),
+                                  ctypes.c_void_p(stream)), "psflib_probe_mfma")
 
 
 def destroy(h: int):

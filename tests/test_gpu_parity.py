@@ -333,6 +333,26 @@ def test_concurrent_calls_on_one_handle(torch, psflib, storage):
         assert torch.equal(img, ref_img), rep
         assert torch.equal(adj, ref_adj), rep
         assert torch.equal(bat, ref_bat), rep
+    # the same from two host threads, each on its own stream
+    import threading
+    img = torch.zeros_like(ref_img)
+    adj = torch.zeros_like(ref_adj)
+    torch.cuda.synchronize()
+
+    def worker(t):
+        with torch.cuda.stream(streams[t]):
+            for rep in range(3):
+                for k in range(t, 8, 2):
+                    lib.apply(Z[k], out=img[k])
+                    lib.apply_adjoint(G[k], out=adj[k])
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img)
+    assert torch.equal(adj, ref_adj)
     lib.close()
 
 
