@@ -220,7 +220,11 @@ bool compute_layout(const psflib_desc& d, Layout* L) {
 extern "C" {
 
 const char* psflib_status_string(psflib_status s) {
-  switch (s) {
+  // C callers may pass any int: read the bits as an int rather than load an
+  // enumeration value outside the enumeration's range
+  int v;
+  memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case PSFLIB_OK: return "PSFLIB_OK";
     case PSFLIB_ERR_INVALID_ARG: return "PSFLIB_ERR_INVALID_ARG";
     case PSFLIB_ERR_RADII: return "PSFLIB_ERR_RADII";
