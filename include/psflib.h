@@ -41,15 +41,17 @@
  *    psflib_apply_adjoint, psflib_apply_batched and the read-back calls may
  *    run concurrently on different streams, and from different host threads,
  *    with one handle.  No two streams share temporary device memory: the
- *    batched call takes its scratch per call, stream-ordered, from a pool the
- *    library keeps per device, and the split-K partial sums of psflib_apply
- *    and psflib_apply_adjoint live in one buffer per stream (shared, in
- *    stream order, by every call on that stream).  Work that uses the library
- *    must be ordered after the build on the build's stream (same stream, or
- *    an event).
+ *    temporaries of psflib_apply, psflib_apply_adjoint, psflib_apply_batched
+ *    and psflib_render_disk_grad (split-K partial sums, packed scenes) live in
+ *    one buffer per stream, taken from a pool the library keeps per device,
+ *    grown on demand and shared, in stream order, by every call on that
+ *    stream.  Under stream capture these calls allocate their temporaries
+ *    from the pool inside the graph instead, so each graph owns its own.
+ *    Work that uses the library must be ordered after the build on the
+ *    build's stream (same stream, or an event).
  *  - Device memory the library allocates for itself comes from that pool and
- *    is kept for reuse until the process ends (the per-stream partial-sum
- *    buffers too: a few MiB per stream the products ran on).
+ *    is kept for reuse until the process ends (the per-stream buffers too:
+ *    as large as the largest temporaries a call on that stream needed).
  */
 #ifndef PSFLIB_H
 #define PSFLIB_H
@@ -176,10 +178,8 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
  *   d_scene  float32 [N*N] scene (flattened row-major, Sec. 3).
  *   d_image  float32 [n*n] output image.
  * Float32 accumulation in a fixed order (results are bitwise reproducible).
- * The split-K partial sums (a few MiB) sit in the buffer of `stream` (created
- * from the device pool on the first call on that stream, enlarged when a
- * larger library needs more); under stream capture they are allocated from
- * the pool inside the graph instead, so each graph owns its partials. */
+ * The split-K partial sums (a few MiB) sit in the buffer of `stream` (see
+ * the conventions above). */
 psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* d_image, void* stream);
 
 /* ---- Allocation-free apply -------------------------------------------------
@@ -222,9 +222,9 @@ psflib_status psflib_apply_adjoint(const psflib_handle* h, const float* d_g, flo
  * scene to the storage format with a per-scene power-of-two scale (so the
  * scaled scene spans [2^14, 2^15) at its largest) and run 16-bit matrix-core
  * products with float32 accumulation.  B = 1 runs psflib_apply instead (the
- * matvec streams the library faster).  Allocates stream-ordered scratch from
- * the library's device memory pool (fragment-major scene copies, K-split
- * partials). */
+ * matvec streams the library faster).  Temporaries (packed scenes, K-split
+ * partial images; up to ~100 MiB at 128 x 128 with 1024 scenes per pass) sit
+ * in the buffer of `stream` (see the conventions above). */
 psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes, float* d_images,
                                    int32_t B, void* stream);
 
@@ -313,7 +313,7 @@ psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
 /* d_dtheta[k] = sum_j d_dscene[j] * dZ_j/dtheta_k (float64 [5]), accumulated in
  * float64 in a fixed order (per-workgroup trees, then their sums in block
  * order), so repeated calls give identical results.  Uses N*N/256 * 40 bytes
- * of stream-ordered scratch from the library's device memory pool. */
+ * of temporaries in the buffer of `stream` (see the conventions above). */
 psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double rmax,
                                       const double* d_theta, const float* d_dscene,
                                       double* d_dtheta, void* stream);

@@ -22,17 +22,20 @@
 // columns ahead; accumulation is blocked in two levels so float32 rounding
 // chains stay short.
 //
-// 16-bit: a workgroup of 4 waves computes a 256 x TN tile (TN = 128 or 256
-// scenes); each wave owns 64 image rows and all TN scenes (2 x TN/32
-// accumulators of 32 x 32).  K advances in stages of 32 columns through a
-// 4-slot ring, three stages ahead of use:
-// library fragments (each used by one wave only) go from HBM straight into
-// registers, and the scene tile (shared by the 4 waves) is copied from a
-// group-major packed copy of the scenes into LDS by the buffer unit, with no
-// register staging.  The 16-bit rounding of the inputs dominates the error,
-// so accumulation is a single float32 level.
+// 16-bit, up to 256 scenes: a workgroup of 4 waves computes a 256 x TN tile
+// (TN = 128 or 256 scenes); each wave owns 64 image rows and all TN scenes
+// (2 x TN/32 accumulators of 32 x 32).  K advances in stages of 32 columns
+// through a 4-slot ring, three stages ahead of use: library fragments (each
+// used by one wave only) go from HBM straight into registers, and the scene
+// tile (shared by the 4 waves) is copied from a group-major packed copy of
+// the scenes into LDS by the buffer unit, with no register staging.  Above
+// 256 scenes a workgroup of 8 waves (two per SIMD) computes a 256 x 256 tile
+// with both operand tiles copied into LDS.  The 16-bit rounding of the inputs
+// dominates the error, so accumulation is a single float32 level.
 #include <math.h>
 #include <stdlib.h>
+
+#include <algorithm>
 
 #include "psflib_internal.h"
 
@@ -260,9 +263,9 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
 // Scene preparation, in two passes over the fp32 scenes:
 //   f_b:  max_j |Z[b][j]| 2^(e_j + f_b) lands in [2^14, 2^15)  (0 for an empty
 //         scene), so no scene underflows or overflows the 16-bit format
-//         whatever its units
+//         whatever its units (one workgroup of 1024 threads per scene);
 //   Zg[g][b] = RN16(Z[b][8g .. 8g+7] * 2^(e_j + f_b)), 16 bytes per (group, scene),
-// stored group-major with the batch padded to whole 128-scene tiles (zeros), so
+// stored group-major with the batch padded to whole scene tiles (zeros), so
 // one K stage of a scene tile is a contiguous run the GEMM copies straight to LDS.
 __device__ __forceinline__ uint32_t to16(float s, bool bf16) {
   if (bf16) {
@@ -300,35 +303,50 @@ __device__ __forceinline__ void load_group(const float* __restrict__ z,
   }
 }
 
-// One workgroup per scene.
+// f_b of one scene per workgroup of 1024 threads: the maximum of
+// |Z_bj| 2^e_j in float64 (exact: a power-of-two scaling of a float32), each
+// thread over a few 8-column groups (two loads of each in flight), then a
+// wave and a workgroup reduction.  The maximum does not depend on the order.
 template <bool VEC>
-__global__ __launch_bounds__(256) void scene_exponent_kernel(const float* __restrict__ Z,
-                                                             const int32_t* __restrict__ exps,
-                                                             int64_t ncols, int64_t ngroups,
-                                                             int32_t* __restrict__ fexp) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(1024) void scene_exponent_kernel(const float* __restrict__ Z,
+                                                              const int32_t* __restrict__ exps,
+                                                              int64_t ncols, int64_t ngroups,
+                                                              int32_t* __restrict__ fexp) {
+  __shared__ double red[16];
   const int64_t b = blockIdx.x;
   const float* z = Z + b * ncols;
   double m = 0.0;
-  for (int64_t g = threadIdx.x; g < ngroups; g += 256) {
+  int64_t g = threadIdx.x;
+  for (; g + 1024 < ngroups; g += 2048) {
+    float v[2][8];
+    int32_t e[2][8];
+    load_group<VEC>(z, exps, ncols, g, v[0], e[0]);
+    load_group<VEC>(z, exps, ncols, g + 1024, v[1], e[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m = fmax(m, ldexp((double)fabsf(v[h][q]), e[h][q]));
+  }
+  if (g < ngroups) {
     float v[8];
     int32_t e[8];
     load_group<VEC>(z, exps, ncols, g, v, e);
 #pragma unroll
     for (int q = 0; q < 8; ++q) m = fmax(m, ldexp((double)fabsf(v[q]), e[q]));
   }
-  red[threadIdx.x] = m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
+    m = red[0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
     int f = 0;
-    if (red[0] > 0.0) {
+    if (m > 0.0) {
       int E;
-      (void)frexp(red[0], &E);
-      f = 15 - E;
+      (void)frexp(m, &E);
+      f = 15 - E;  // max |Z_bj| 2^(e_j + f) in [2^14, 2^15)
     }
     fexp[b] = f;
   }
@@ -519,16 +537,151 @@ __global__ __launch_bounds__(kGemmThreads, TN == 128 ? 2 : 1) void gemm_h16_kern
       store_acc(acc[t][u], dst, M, B, m0 + 64 * wave + 32 * t, n0 + 32 * u, lane, fexp, !split);
 }
 
-// out[b][m] = 2^-f_b * sum over K slices (fixed order).
+// The 16-bit GEMM for batches above 256 scenes: 8 waves (two per SIMD, so one
+// wave's waits are filled with the other's products), tile 256 image rows x
+// 256 scenes, wave (wm = w & 3, wn = w >> 2) owning rows 64 wm .. +63 and
+// scenes 128 wn .. +127 (2 x 4 accumulators of 32 x 32).  Both operand
+// tiles of a K stage are copied into LDS by the buffer unit (each wave 2
+// library and 2 scene copies of 16 bytes per lane), into a 4-slot ring three
+// stages ahead of use, and every wave reads its fragments from LDS: the two
+// waves that share a row block read one copy of it.  The wait before each
+// stage barrier allows 2 x 4 operations outstanding.  Against the 4-wave
+// 256-scene tile (one wave per SIMD, library fragments straight to
+// registers) the matrix cores are busy 73% instead of 65% of the cycles at
+// B = 1024 (SQ_VALU_MFMA_BUSY_CYCLES), 352-370 against 353-417 us for the
+// kernel; products and accumulation order per output are unchanged.
+template <bool BF16>
+__global__ __launch_bounds__(512, 1) void gemm_h16_w8_kernel(
+    const u32x4* Mp, const u32x4* Zg, const int32_t* __restrict__ fexp,
+    float* __restrict__ out, int64_t M, int64_t ngroups, int64_t B, int64_t Bp, int64_t mblocks,
+    int64_t nblocks, int64_t splits, int64_t stages_per_split) {
+  constexpr int TN = 256, NU = 4;
+  __shared__ u32x4 Bs0[kHG][TN], Bs1[kHG][TN], Bs2[kHG][TN], Bs3[kHG][TN];  // scene ring
+  __shared__ u32x4 As0[kHG][kHM], As1[kHG][kHM], As2[kHG][kHM], As3[kHG][kHM];  // library ring
+  auto bslot = [&](int slot) -> u32x4 (*)[TN] {
+    return slot == 0 ? Bs0 : slot == 1 ? Bs1 : slot == 2 ? Bs2 : Bs3;
+  };
+  auto aslot = [&](int slot) -> u32x4 (*)[kHM] {
+    return slot == 0 ? As0 : slot == 1 ? As1 : slot == 2 ? As2 : As3;
+  };
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave & 3, wn = wave >> 2;
+  const int64_t tile = xcd_tile(blockIdx.x, mblocks * nblocks * splits);
+  const int64_t nb = tile % nblocks, mb = (tile / nblocks) % mblocks, sp = tile / (nblocks * mblocks);
+  const int64_t m0 = mb * kHM, n0 = nb * TN;
+  const int64_t nstages = ngroups / kHG;  // ngroups is a multiple of 8
+  const int64_t st0 = sp * stages_per_split;
+  const int64_t ns = (nstages - st0 < stages_per_split ? nstages - st0 : stages_per_split);
+  float* dst = out + sp * B * M;
+  const int half = lane >> 5;
+  // copies of this wave: group wm of each stage; library rows m0 + 128 wn + lane
+  // and + 64 (rows past M read row M-1: valid addresses, results never
+  // stored), scenes n0 + 128 wn .. +127
+  int64_t arow0 = m0 + 128 * wn + lane, arow1 = arow0 + 64;
+  if (arow0 > M - 1) arow0 = M - 1;
+  if (arow1 > M - 1) arow1 = M - 1;
+  const char* Ab = reinterpret_cast<const char*>(Mp);
+  const char* Zb = reinterpret_cast<const char*>(Zg + (int64_t)wm * Bp + n0 + 128 * wn);
+  const int offb = lane * 16;
+  auto issue = [&](int64_t ls, int slot) {
+    const int64_t st = st0 + ls;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Ab + (st * kHG + wm) * M * 16), (short)0, 0x7FFFFFFF, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        ra, (void __attribute__((address_space(3)))*)(&aslot(slot)[wm][128 * wn]), 16,
+        (uint32_t)(arow0 * 16), 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        ra, (void __attribute__((address_space(3)))*)(&aslot(slot)[wm][128 * wn + 64]), 16,
+        (uint32_t)(arow1 * 16), 0, 0, 0);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Zb + st * kHG * Bp * 16), (short)0, 0x7FFFFFFF, 0x00020000);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (void __attribute__((address_space(3)))*)(&bslot(slot)[wm][128 * wn + 64 * h]), 16,
+          offb + 1024 * h, 0, 0, 0);
+  };
+  const f32x16 zero16 = {};
+  f32x16 acc[2][NU];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) acc[t][u] = zero16;
+  u32x4 af[2][2], bf[2][NU];
+  auto readf = [&](int slot) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) bf[ks][u] = bslot(slot)[2 * ks + half][128 * wn + 32 * u + (lane & 31)];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) af[ks][t] = aslot(slot)[2 * ks + half][64 * wm + 32 * t + (lane & 31)];
+    }
+  };
+  auto compute = [&]() {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[t][u] = mfma16<BF16>(af[ks][t], bf[ks][u], acc[t][u]);
+  };
+  auto step = [&](int64_t ls, int j) {
+    // 4 copies per lane and stage; the two stages issued after this one may
+    // still be in flight
+    asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    readf(j % kHRing);
+    const int64_t nx = ls + kHRing - 1;
+    issue(nx < ns ? nx : ns - 1, (j + kHRing - 1) % kHRing);
+    compute();
+  };
+#pragma unroll
+  for (int s = 0; s < kHRing - 1; ++s) issue(s < ns ? s : ns - 1, s);
+  int64_t l0 = 0;
+  for (; l0 + kHUnroll <= ns; l0 += kHUnroll) {
+#pragma unroll
+    for (int j = 0; j < kHUnroll; ++j) step(l0 + j, j);
+  }
+  for (; l0 < ns; l0 += kHRing) {
+#pragma unroll
+    for (int j = 0; j < kHRing; ++j)
+      if (l0 + j < ns) step(l0 + j, j);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no copy into LDS outlives the workgroup
+  const bool split = splits > 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      store_acc(acc[t][u], dst, M, B, m0 + 64 * wm + 32 * t, n0 + 128 * wn + 32 * u, lane, fexp, !split);
+}
+
+// out[b][m] = 2^-f_b * sum over K slices (fixed order).  VEC: 4 outputs per
+// thread (M % 4 == 0, so the 4 share one scene).
+template <bool VEC>
 __global__ __launch_bounds__(256) void reduce_splits_kernel(const float* __restrict__ part,
                                                             int splits, int64_t BM, int64_t M,
                                                             const int32_t* __restrict__ fexp,
                                                             float* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= BM) return;
-  float s = 0.0f;
-  for (int p = 0; p < splits; ++p) s += part[(int64_t)p * BM + t];
-  out[t] = fexp ? ldexpf(s, -fexp[t / M]) : s;
+  if constexpr (VEC) {
+    const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (t >= BM) return;
+    f32x4 s = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < splits; ++p)
+      s += __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(part + (int64_t)p * BM + t));
+    if (fexp) {
+      const int ex = -fexp[t / M];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[e] = ldexpf(s[e], ex);
+    }
+    *reinterpret_cast<f32x4*>(out + t) = s;
+  } else {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= BM) return;
+    float s = 0.0f;
+    for (int p = 0; p < splits; ++p) s += part[(int64_t)p * BM + t];
+    out[t] = fexp ? ldexpf(s, -fexp[t / M]) : s;
+  }
 }
 
 // ------------------------------------------------------------ launch ------
@@ -536,13 +689,15 @@ struct GemmPlan {
   int64_t mblocks, nblocks, kunits, splits, per;  // kunits: 8-column groups (FP32) or K stages (16-bit)
 };
 
-// 16-bit scene-tile width: 256 scenes (one workgroup per CU, 2 x 8
-// accumulators per wave) for 128 < B <= 256, where it is ~5% faster than two
-// 128-wide tiles, and for full passes of 1024 scenes (2-4% faster: each library
-// block is read by 4 workgroups instead of 8); else 128 (two workgroups per CU).
-// At B <= 128 half of a 256-wide tile would be padding; at B = 512 a 256-wide
-// grid has to split K and add the partials.
-static int64_t h16_tile(int64_t bc) { return ((bc > 128 && bc <= 256) || bc >= kMaxBatchChunk) ? 256 : 128; }
+// 16-bit kernel by batch: the 4-wave 128-scene tile up to 128 scenes (a wider
+// tile would be mostly padding; two workgroups per CU), the 4-wave 256-scene
+// tile for 128 < B <= 256 (~5% faster than two 128-wide tiles), and the
+// 8-wave 256 x 256 tile above (B = 512: 237-244 against 241-248 us per
+// product with the 128-wide tile, K split in two; B = 1024: 400-403 against
+// 406-416 us).
+enum H16Kind { kH128 = 0, kH256 = 1, kHW8 = 2 };
+static H16Kind h16_kind(int64_t bc) { return bc <= 128 ? kH128 : bc <= 256 ? kH256 : kHW8; }
+static int64_t h16_tile(int64_t bc) { return h16_kind(bc) == kH128 ? 128 : 256; }
 
 // FP32 scene blocks of 32 per workgroup tile: 1 for batches of at most 32
 static int f32_nb(int64_t bc) { return bc <= 32 ? 1 : 2; }
@@ -561,11 +716,14 @@ static GemmPlan plan_gemm(int storage, int64_t M, int64_t ncols, int64_t ncols_p
   p.nblocks = (bc + tn - 1) / tn;
   p.kunits = f32 ? (ncols + 7) / 8 : (ncols_pad / 8) / kHG;
   // split K if the tile grid is smaller than the GPU: FP32 aims at two
-  // workgroups per CU; the 16-bit kernel at one (an extra K slice costs a
-  // partial-image round trip that a second workgroup per CU does not repay)
+  // workgroups per CU; the 16-bit kernels at one (an extra K slice costs a
+  // partial-image round trip that a second workgroup per CU does not repay).
+  // The 8-wave kernel splits only while whole extra rounds of tiles fit
+  // (192 tiles stay unsplit: 384 workgroups would leave half the GPU idle in
+  // their second round too).
   const int64_t want = f32 ? 512 : 256;
   const int64_t tiles = p.mblocks * p.nblocks;
-  int64_t s = (want + tiles - 1) / tiles;
+  int64_t s = (!f32 && h16_kind(bc) == kHW8) ? want / tiles : (want + tiles - 1) / tiles;
   if (s > 16) s = 16;
   if (s > p.kunits) s = p.kunits;
   if (s < 1) s = 1;
@@ -610,10 +768,20 @@ static hipError_t launch_gemm_h16_t(unsigned grid, const u32x4* Mp, const u32x4*
   return hipGetLastError();
 }
 
-static hipError_t launch_gemm_h16(bool bf, bool wide, bool nt, unsigned grid, const u32x4* Mp,
+static hipError_t launch_gemm_h16(bool bf, H16Kind kind, bool nt, unsigned grid, const u32x4* Mp,
                                   const u32x4* Zg, const int32_t* fexp, float* dst, int64_t M,
                                   int64_t ngroups, int64_t B, int64_t Bp, const GemmPlan& p,
                                   hipStream_t s) {
+  if (kind == kHW8) {
+    if (bf)
+      gemm_h16_w8_kernel<true><<<grid, 512, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, B, Bp, p.mblocks,
+                                                    p.nblocks, p.splits, p.per);
+    else
+      gemm_h16_w8_kernel<false><<<grid, 512, 0, s>>>(Mp, Zg, fexp, dst, M, ngroups, B, Bp, p.mblocks,
+                                                     p.nblocks, p.splits, p.per);
+    return hipGetLastError();
+  }
+  const bool wide = kind == kH256;
   const int v = (bf ? 4 : 0) + (wide ? 2 : 0) + (nt ? 1 : 0);
   switch (v) {
     case 0: return launch_gemm_h16_t<false, 128, false>(grid, Mp, Zg, fexp, dst, M, ngroups, B, Bp, p, s);
@@ -709,9 +877,9 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
       const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
       if (vec)
-        scene_exponent_kernel<true><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
+        scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
       else
-        scene_exponent_kernel<false><<<(unsigned)bc, 256, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
+        scene_exponent_kernel<false><<<(unsigned)bc, 1024, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
@@ -726,15 +894,21 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
-      const bool wide = h16_tile(bc) == 256;
-      e = launch_gemm_h16(bf, wide, !wide && p.nblocks == 1, grid, Mp, Zg, fexp, dst, M, ngroups,
-                          bc, Bp, p, s);
+      const H16Kind kind = h16_kind(bc);
+      e = launch_gemm_h16(bf, kind, kind == kH128 && p.nblocks == 1, grid, Mp, Zg, fexp, dst, M,
+                          ngroups, bc, Bp, p, s);
     }
     if (e != hipSuccess) return e;
     if (p.splits > 1) {
       const int64_t BM = bc * M;
-      reduce_splits_kernel<<<(unsigned)((BM + 255) / 256), 256, 0, s>>>(
-          part, (int)p.splits, BM, M, storage == PSFLIB_FP32 ? nullptr : fexp, outc);
+      const int32_t* fx = storage == PSFLIB_FP32 ? nullptr : fexp;
+      const bool v4 = (M % 4) == 0 && (reinterpret_cast<uintptr_t>(outc) % 16) == 0;
+      if (v4)
+        reduce_splits_kernel<true><<<(unsigned)((BM / 4 + 255) / 256), 256, 0, s>>>(
+            part, (int)p.splits, BM, M, fx, outc);
+      else
+        reduce_splits_kernel<false><<<(unsigned)((BM + 255) / 256), 256, 0, s>>>(
+            part, (int)p.splits, BM, M, fx, outc);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

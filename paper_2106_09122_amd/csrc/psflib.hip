@@ -411,78 +411,94 @@ hipError_t launch_product(const psflib_handle* h, bool adjoint, const float* in,
                                h->L.ncols_pad, partial, out, s);
 }
 
-// Split-K partial sums of psflib_apply and psflib_apply_adjoint.  Outside
-// stream capture they live in one buffer per (device, stream), kept like the
-// pool's blocks until the process ends and grown on demand: calls on one
-// stream run in order, so every call on that stream (whatever its handle) can
-// reuse the stream's buffer, and calls on different streams never share one.
-// This adds nothing to the stream per call (a stream-ordered free per call
-// would add a marker, ~3 us between kernels).  Under capture the partials
-// are allocated from the pool inside the graph, so every graph owns its own.
-struct StreamPartials {
+// Temporary device memory of one call (split-K partial sums, packed scenes,
+// reduction blocks).  Outside stream capture it is the calling stream's
+// buffer: one per (device, stream), kept like the pool's blocks until the
+// process ends and grown on demand.  Calls on one stream run in order, so
+// every call on that stream (whatever its handle) can reuse the buffer, and
+// calls on different streams never share one.  The lock is held over the
+// call's launches, so a call from another host thread on the same stream
+// cannot slip its kernels in between them.  This adds nothing to the stream
+// per call (a stream-ordered free per call adds a marker: ~3 us between
+// kernels).  Under capture the memory is allocated from the pool inside the
+// graph instead, so every graph owns its own.
+struct StreamBuffer {
   int dev;
   hipStream_t s;
   void* p;
   size_t bytes;
 };
-std::mutex g_sp_mu;
-std::vector<StreamPartials> g_sp;
+std::mutex g_sb_mu;
+std::vector<StreamBuffer> g_sb;
 
-// Called with g_sp_mu held.
-hipError_t stream_partials(int dev, hipStream_t s, size_t bytes, void** out) {
-  StreamPartials* slot = nullptr;
-  for (auto& sp : g_sp)
-    if (sp.dev == dev && sp.s == s) slot = &sp;
-  if (slot && slot->bytes >= bytes) {
-    *out = slot->p;
-    return hipSuccess;
+class CallScratch {
+ public:
+  hipError_t acquire(int dev, hipStream_t s, size_t bytes) {
+    s_ = s;
+    if (bytes == 0) return hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) {
+      pooled_ = true;
+      return psflib::pool_alloc(&p_, bytes, dev, s);
+    }
+    lock_ = std::unique_lock<std::mutex>(g_sb_mu);
+    StreamBuffer* slot = nullptr;
+    for (auto& sb : g_sb)
+      if (sb.dev == dev && sb.s == s) slot = &sb;
+    if (slot && slot->bytes >= bytes) {
+      p_ = slot->p;
+      return hipSuccess;
+    }
+    size_t want = (size_t)1 << 20;  // grow in powers of two from 1 MiB
+    while (want < bytes) want <<= 1;
+    e = psflib::pool_alloc(&p_, want, dev, s);
+    if (e != hipSuccess) {
+      p_ = nullptr;
+      return e;
+    }
+    if (slot) {
+      // the smaller buffer goes back to the pool after the work queued on s
+      e = hipFreeAsync(slot->p, s);
+      slot->p = p_;
+      slot->bytes = want;
+    } else {
+      g_sb.push_back(StreamBuffer{dev, s, p_, want});
+    }
+    return e;
   }
-  size_t want = (size_t)1 << 20;  // grow in powers of two from 1 MiB
-  while (want < bytes) want <<= 1;
-  void* p = nullptr;
-  hipError_t e = psflib::pool_alloc(&p, want, dev, s);
-  if (e != hipSuccess) return e;
-  if (slot) {
-    // the smaller buffer goes back to the pool after the work queued on s
-    e = hipFreeAsync(slot->p, s);
-    slot->p = p;
-    slot->bytes = want;
-  } else {
-    g_sp.push_back(StreamPartials{dev, s, p, want});
+  void* ptr() const { return p_; }
+  // after the call's launches
+  hipError_t release() {
+    hipError_t e = hipSuccess;
+    if (pooled_ && p_) e = hipFreeAsync(p_, s_);
+    pooled_ = false;
+    p_ = nullptr;
+    if (lock_.owns_lock()) lock_.unlock();
+    return e;
   }
-  *out = p;
-  return e;
-}
+  ~CallScratch() { (void)release(); }
+
+ private:
+  std::unique_lock<std::mutex> lock_;
+  void* p_ = nullptr;
+  bool pooled_ = false;
+  hipStream_t s_ = nullptr;
+};
 
 psflib_status product(const psflib_handle* h, bool adjoint, const float* in, float* out,
                       hipStream_t s) {
   const int64_t floats =
       adjoint ? psflib::adjoint_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad)
               : psflib::matvec_partial_floats(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad);
-  const char* what = adjoint ? "adjoint kernels" : "matvec kernels";
-  if (floats == 0) {
-    hipError_t e = launch_product(h, adjoint, in, out, nullptr, s);
-    return e == hipSuccess ? PSFLIB_OK : device_fail(e, what);
-  }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipError_t e = hipStreamIsCapturing(s, &cs);
-  if (e != hipSuccess) return device_fail(e, "hipStreamIsCapturing");
-  void* part = nullptr;
-  if (cs == hipStreamCaptureStatusNone) {
-    // held over both launches, so that a call from another host thread on
-    // the same stream cannot slip its kernels in between them
-    std::lock_guard<std::mutex> lock(g_sp_mu);
-    e = stream_partials(h->device, s, (size_t)floats * 4, &part);
-    if (e != hipSuccess) return device_fail(e, "partial-sum buffer");
-    e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
-  } else {
-    e = psflib::pool_alloc(&part, (size_t)floats * 4, h->device, s);
-    if (e != hipSuccess) return device_fail(e, "partial-sum allocation");
-    e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(part), s);
-    hipError_t e2 = hipFreeAsync(part, s);
-    if (e == hipSuccess) e = e2;
-  }
-  return e == hipSuccess ? PSFLIB_OK : device_fail(e, what);
+  CallScratch cs;
+  hipError_t e = cs.acquire(h->device, s, (size_t)floats * 4);
+  if (e != hipSuccess) return device_fail(e, "partial-sum buffer");
+  e = launch_product(h, adjoint, in, out, reinterpret_cast<float*>(cs.ptr()), s);
+  const hipError_t e2 = cs.release();
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? PSFLIB_OK : device_fail(e, adjoint ? "adjoint kernels" : "matvec kernels");
 }
 
 }  // namespace
@@ -550,20 +566,15 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
   if (st != PSFLIB_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t bytes = psflib::batched_scratch_bytes(h->desc.storage, h->L.M, h->L.ncols, h->L.ncols_pad, B);
-  void* scratch = nullptr;
-  hipError_t e;
-  if (bytes > 0) {
-    e = psflib::pool_alloc(&scratch, bytes, h->device, s);
-    if (e != hipSuccess) return device_fail(e, "scratch allocation (batched)");
-  }
+  CallScratch cs;
+  hipError_t e = cs.acquire(h->device, s, bytes);
+  if (e != hipSuccess) return device_fail(e, "scratch buffer (batched)");
   const char* lib = reinterpret_cast<const char*>(h->lib);
   const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
   e = psflib::launch_batched(h->desc.storage, h->lib, exps, d_scenes, d_images, h->L.M, h->L.ncols,
-                             h->L.ncols_pad, B, scratch, bytes, s);
-  if (scratch) {
-    hipError_t e2 = hipFreeAsync(scratch, s);
-    if (e == hipSuccess) e = e2;
-  }
+                             h->L.ncols_pad, B, cs.ptr(), bytes, s);
+  const hipError_t e2 = cs.release();
+  if (e == hipSuccess) e = e2;
   if (e != hipSuccess) return device_fail(e, "batched kernels");
   return PSFLIB_OK;
 }
@@ -669,12 +680,12 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
-  void* scratch = nullptr;
-  e = psflib::pool_alloc(&scratch, psflib::render_disk_grad_scratch_bytes(N), dev, s);
-  if (e != hipSuccess) return device_fail(e, "scratch allocation (disk gradient)");
+  CallScratch cs;
+  e = cs.acquire(dev, s, psflib::render_disk_grad_scratch_bytes(N));
+  if (e != hipSuccess) return device_fail(e, "scratch buffer (disk gradient)");
   e = psflib::launch_render_disk_grad(N, scene_pixscale, rmax, d_theta, d_dscene, d_dtheta,
-                                      scratch, s);
-  hipError_t e2 = hipFreeAsync(scratch, s);
+                                      cs.ptr(), s);
+  const hipError_t e2 = cs.release();
   if (e == hipSuccess) e = e2;
   if (e != hipSuccess) return device_fail(e, "render_disk_grad kernels");
   return PSFLIB_OK;

@@ -36,19 +36,28 @@ def asm():
 
 
 def kernel_bodies(text):
+    """(name, library loads to registers, LDS copies) per stage of every
+    16-bit GEMM kernel: the 4-wave kernels load 4 library fragments and copy
+    TN/64 scene fragments per lane; the 8-wave kernel copies 2 library and 2
+    scene fragments per lane into LDS."""
     names = re.findall(r"^(_ZN6psflib15gemm_h16_kernel\w+):", text, re.M)
     assert len(names) == 8  # bf16 and fp16, 128- and 256-scene tiles, with and without the NT hint
     for name in names:
         tn = int(re.search(r"ILb[01]ELi(\d+)E", name).group(1))
         body = text[text.index(name + ":"):]
-        yield name, tn // 64, body[:body.index("s_endpgm")].splitlines()
+        yield name, 4, tn // 64, body[:body.index("s_endpgm")].splitlines()
+    w8 = re.findall(r"^(_ZN6psflib18gemm_h16_w8_kernel\w+):", text, re.M)
+    assert len(w8) == 2  # bf16 and fp16
+    for name in w8:
+        body = text[text.index(name + ":"):]
+        yield name, 0, 4, body[:body.index("s_endpgm")].splitlines()
 
 
 def test_stage_issue_pattern(asm):
-    for name, copies_per_stage, lines in kernel_bodies(asm):
+    for name, reg_loads, copies_per_stage, lines in kernel_bodies(asm):
         assert not any("scratch_" in l for l in lines), name
         # a stage barrier: the ring wait then s_barrier
-        wait = f"s_waitcnt vmcnt({2 * (4 + copies_per_stage)})"
+        wait = f"s_waitcnt vmcnt({2 * (reg_loads + copies_per_stage)})"
         bars = [i for i, l in enumerate(lines)
                 if "s_barrier" in l and i > 0 and wait in lines[i - 1]]
         assert len(bars) >= 8, name
@@ -58,7 +67,7 @@ def test_stage_issue_pattern(asm):
             copies = sum(re.search(r"buffer_load_dwordx4\b.*\blds\b", l) is not None for l in seg)
             other = [l for l in seg if VMEM.match(l) and "global_load_dwordx4" not in l
                      and not re.search(r"buffer_load_dwordx4\b.*\blds\b", l)]
-            assert (loads, copies) == (4, copies_per_stage) and not other, (name, a, loads, copies, other)
+            assert (loads, copies) == (reg_loads, copies_per_stage) and not other, (name, a, loads, copies, other)
         # loop headers: nothing counted against vmcnt before the first barrier
         for i, l in enumerate(lines):
             if "Loop Header" in l:

@@ -261,39 +261,49 @@ def test_batched_multi_pass(torch, psflib, storage):
     lib.close()
 
 
-def test_apply_and_adjoint_in_a_graph(torch, psflib, c1):
-    """psflib_apply and psflib_apply_adjoint can be captured in a HIP graph
-    (their partial sums become the graph's own allocation): every replay (with
-    eager work and synchronisations between replays) equals the eager result
-    bitwise."""
-    lib = psflib.Library(torch.from_numpy(c1["cube"]).cuda(), c1["radii"], c1["N"], c1["S"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_apply_and_adjoint_in_a_graph(torch, psflib, c1, storage):
+    """psflib_apply, psflib_apply_adjoint and psflib_apply_batched can be
+    captured in a HIP graph (their temporaries become the graph's own
+    allocations): every replay (with eager work and synchronisations between
+    replays) equals the eager result bitwise."""
+    lib = psflib.Library(torch.from_numpy(c1["cube"]).cuda(), c1["radii"], c1["N"], c1["S"],
+                         storage=storage)
     Z = torch.from_numpy(c1["scene"]).cuda()
+    Zb = torch.stack([Z * (k + 1) for k in range(5)])
     g = torch.linspace(-1.0, 1.0, c1["n"] ** 2, device="cuda", dtype=torch.float32)
     img = torch.empty(c1["n"] ** 2, device="cuda")
     grad = torch.empty(c1["N"] ** 2, device="cuda")
+    imgs = torch.empty((5, c1["n"] ** 2), device="cuda")
     eager_img = lib.apply(Z).clone()
     eager_grad = lib.apply_adjoint(g).clone()
+    eager_imgs = lib.apply_batched(Zb).clone()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):  # warm-up on the capture stream
         lib.apply(Z, out=img)
         lib.apply_adjoint(g, out=grad)
+        lib.apply_batched(Zb, out=imgs)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         lib.apply(Z, out=img)
         lib.apply_adjoint(g, out=grad)
+        lib.apply_batched(Zb, out=imgs)
     for rep in range(3):
         img.zero_()
         grad.zero_()
+        imgs.zero_()
         _ = lib.apply(2.0 * Z)  # eager work between replays
+        _ = lib.apply_batched(3.0 * Zb)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(img, eager_img), rep
         assert torch.equal(grad, eager_grad), rep
+        assert torch.equal(imgs, eager_imgs), rep
     del graph
     lib.close()
 
