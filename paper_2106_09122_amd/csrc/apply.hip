@@ -110,9 +110,10 @@ __global__ __launch_bounds__(kMvThreads) void matvec_f32_kernel(const float* __r
   }
 }
 
-// 16-bit storage: element (i, j) at ((j/8)*M + i)*8 + j%8.  One thread per
-// row; one 16-byte load covers 8 columns.  The chunk's scene values, scaled by
-// 2^e_j, are staged in LDS and read as broadcasts.
+// 16-bit storage: element (i, slot s) at ((s/8)*M + i)*8 + s%8, slot s holding
+// column perm[s].  One thread per row; one 16-byte load covers 8 slots.  The
+// chunk's scene values Z[perm[s]] scaled by 2^eslot[s] are staged in LDS and
+// read as broadcasts.
 __device__ __forceinline__ float h16_to_f32(uint32_t h, bool bf16) {
   if (bf16) return __uint_as_float(h << 16);
   return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
@@ -143,12 +144,13 @@ __device__ __forceinline__ void unpack8(const u32x4 p, float* f) {
 
 template <bool BF16>
 __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* __restrict__ Mp,
-                                                                  const int32_t* __restrict__ exps,
+                                                                  const int32_t* __restrict__ perm,
+                                                                  const int32_t* __restrict__ eslot,
                                                                   const float* __restrict__ Z,
                                                                   float* __restrict__ part,
                                                                   float* __restrict__ out,
-                                                                  int64_t M, int64_t ncols,
-                                                                  int64_t ngroups, int64_t chunk_g) {
+                                                                  int64_t M, int64_t ngroups,
+                                                                  int64_t chunk_g) {
   __shared__ f32x4 zs[kMv16MaxChunkGroups * 2];
   const int tid = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kMv16Threads + tid;
@@ -159,8 +161,9 @@ __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* _
   const int64_t ng = g1 - g0;
   float* zsf = reinterpret_cast<float*>(zs);
   for (int64_t t = tid; t < ng * 8; t += kMv16Threads) {
-    const int64_t j = g0 * 8 + t;
-    zsf[t] = (j < ncols) ? ldexpf(Z[j], exps[j]) : 0.0f;
+    const int64_t slot = g0 * 8 + t;
+    const int32_t j = perm[slot];
+    zsf[t] = (j >= 0) ? ldexpf(Z[j], eslot[slot]) : 0.0f;
   }
   __syncthreads();
   const bool active = i < M;
@@ -271,7 +274,7 @@ int64_t matvec_partial_floats(int storage, int64_t M, int64_t ncols, int64_t nco
   return sh.nchunks > 1 ? sh.nchunks * M : 0;
 }
 
-hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
+hipError_t launch_matvec(int storage, const void* lib, const Cols16& cx, const float* Z,
                          int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                          hipStream_t s) {
   const MvShape sh = mv_shape(storage, M, ncols, ncols_pad);
@@ -286,9 +289,9 @@ hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, cons
     const int64_t ngroups = ncols_pad / 8;
     const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
     if (storage == PSFLIB_BF16_POW2)
-      matvec_h16_kernel<true><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, out, M, ncols, ngroups, sh.chunk);
+      matvec_h16_kernel<true><<<grid, kMv16Threads, 0, s>>>(Mp, cx.perm, cx.eslot, Z, partial, out, M, ngroups, sh.chunk);
     else
-      matvec_h16_kernel<false><<<grid, kMv16Threads, 0, s>>>(Mp, exps, Z, partial, out, M, ncols, ngroups, sh.chunk);
+      matvec_h16_kernel<false><<<grid, kMv16Threads, 0, s>>>(Mp, cx.perm, cx.eslot, Z, partial, out, M, ngroups, sh.chunk);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || sh.nchunks == 1) return e;
@@ -355,13 +358,15 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_f32_kernel(const float* _
   }
 }
 
+// 16-bit: the sums of group grp belong to slots 8 grp + q, i.e. columns
+// perm[8 grp + q]; they are written at the column's index.
 template <bool BF16>
 __global__ __launch_bounds__(kAdjThreads) void adjoint_h16_kernel(const u32x4* __restrict__ Mp,
-                                                                  const int32_t* __restrict__ exps,
+                                                                  const int32_t* __restrict__ perm,
+                                                                  const int32_t* __restrict__ eslot,
                                                                   const float* __restrict__ g,
                                                                   float* __restrict__ out,
-                                                                  int64_t M, int64_t ncols,
-                                                                  int64_t ngroups,
+                                                                  int64_t M, int64_t ngroups,
                                                                   int64_t out_stride,
                                                                   int apply_exp) {
   constexpr int U = kAdj16Rows / kAdjThreads;  // rows per thread
@@ -401,11 +406,12 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_h16_kernel(const u32x4* _
     }
     __syncthreads();
     if (tid < 8) {
-      const int64_t j = grp * 8 + tid;
+      const int64_t slot = grp * 8 + tid;
+      const int32_t j = perm[slot];
       float tot = 0.0f;
 #pragma unroll
       for (int w = 0; w < kAdjThreads / 64; ++w) tot += red[t & 1][w][tid];
-      if (j < ncols) out[rb * out_stride + j] = apply_exp ? ldexpf(tot, exps[j]) : tot;
+      if (j >= 0) out[rb * out_stride + j] = apply_exp ? ldexpf(tot, eslot[slot]) : tot;
     }
   }
 }
@@ -429,7 +435,7 @@ int64_t adjoint_partial_floats(int storage, int64_t M, int64_t ncols, int64_t nc
   return nb > 1 ? nb * ncols_pad : 0;
 }
 
-hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, const float* g,
+hipError_t launch_adjoint(int storage, const void* lib, const Cols16& cx, const float* g,
                           int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                           hipStream_t s) {
   const int64_t rows = (storage == PSFLIB_FP32) ? kAdjF32Rows : kAdj16Rows;
@@ -449,14 +455,14 @@ hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, con
     const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
     const int apply_exp = (nb > 1) ? 0 : 1;
     if (storage == PSFLIB_BF16_POW2)
-      adjoint_h16_kernel<true><<<grid, kAdjThreads, 0, s>>>(Mp, exps, g, dst, M, ncols, ngroups, stride, apply_exp);
+      adjoint_h16_kernel<true><<<grid, kAdjThreads, 0, s>>>(Mp, cx.perm, cx.eslot, g, dst, M, ngroups, stride, apply_exp);
     else
-      adjoint_h16_kernel<false><<<grid, kAdjThreads, 0, s>>>(Mp, exps, g, dst, M, ncols, ngroups, stride, apply_exp);
+      adjoint_h16_kernel<false><<<grid, kAdjThreads, 0, s>>>(Mp, cx.perm, cx.eslot, g, dst, M, ngroups, stride, apply_exp);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nb == 1) return e;
   reduce_cols_kernel<<<(unsigned)((ncols + 255) / 256), 256, 0, s>>>(
-      partial, nb, stride, ncols, storage == PSFLIB_FP32 ? nullptr : exps, out);
+      partial, nb, stride, ncols, storage == PSFLIB_FP32 ? nullptr : cx.exps, out);
   return hipGetLastError();
 }
 
@@ -489,6 +495,7 @@ hipError_t noalloc_scratch(int dev, void** ptr) {
 template <int STORE>
 __global__ __launch_bounds__(256) void get_columns_kernel(const void* __restrict__ lib,
                                                           const int32_t* __restrict__ exps,
+                                                          const int32_t* __restrict__ slot_of,
                                                           const int32_t* __restrict__ cols,
                                                           int64_t M, int64_t ncols,
                                                           float* __restrict__ out) {
@@ -502,29 +509,51 @@ __global__ __launch_bounds__(256) void get_columns_kernel(const void* __restrict
       v = reinterpret_cast<const float*>(lib)[j * M + i];
     } else {
       const uint16_t* Mh = reinterpret_cast<const uint16_t*>(lib);
-      const uint32_t h = Mh[((j >> 3) * M + i) * 8 + (j & 7)];
+      const int64_t slot = slot_of[j];
+      const uint32_t h = Mh[((slot >> 3) * M + i) * 8 + (slot & 7)];
       v = ldexpf(h16_to_f32(h, STORE == PSFLIB_BF16_POW2), exps[j]);
     }
   }
   out[t * M + i] = v;
 }
 
-hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
+hipError_t launch_get_columns(int storage, const void* lib, const Cols16& cx,
                               const int32_t* cols, int count, int64_t M, int64_t ncols,
                               float* out, hipStream_t s) {
   if (count == 0) return hipSuccess;
   const dim3 grid((unsigned)((M + 255) / 256), (unsigned)count);
   switch (storage) {
     case PSFLIB_FP32:
-      get_columns_kernel<PSFLIB_FP32><<<grid, 256, 0, s>>>(lib, exps, cols, M, ncols, out);
+      get_columns_kernel<PSFLIB_FP32><<<grid, 256, 0, s>>>(lib, cx.exps, cx.slot_of, cols, M, ncols, out);
       break;
     case PSFLIB_BF16_POW2:
-      get_columns_kernel<PSFLIB_BF16_POW2><<<grid, 256, 0, s>>>(lib, exps, cols, M, ncols, out);
+      get_columns_kernel<PSFLIB_BF16_POW2><<<grid, 256, 0, s>>>(lib, cx.exps, cx.slot_of, cols, M, ncols, out);
       break;
     default:
-      get_columns_kernel<PSFLIB_FP16_POW2><<<grid, 256, 0, s>>>(lib, exps, cols, M, ncols, out);
+      get_columns_kernel<PSFLIB_FP16_POW2><<<grid, 256, 0, s>>>(lib, cx.exps, cx.slot_of, cols, M, ncols, out);
       break;
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ column order -----
+__global__ __launch_bounds__(256) void identity_order_kernel(int32_t* __restrict__ perm,
+                                                             int32_t* __restrict__ eslot,
+                                                             int32_t* __restrict__ slot_of,
+                                                             const int32_t* __restrict__ exps,
+                                                             int64_t ncols, int64_t ncols_pad) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= ncols_pad) return;
+  perm[s] = s < ncols ? (int32_t)s : -1;
+  eslot[s] = exps[s];
+  if (s < ncols) slot_of[s] = (int32_t)s;
+}
+
+hipError_t launch_identity_order(int32_t* perm, int32_t* eslot, int32_t* slot_of,
+                                 const int32_t* exps, int64_t ncols, int64_t ncols_pad,
+                                 hipStream_t s) {
+  identity_order_kernel<<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(perm, eslot, slot_of,
+                                                                           exps, ncols, ncols_pad);
   return hipGetLastError();
 }
 

@@ -464,6 +464,290 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   if (lane == 0) tau[j] = tsum;
 }
 
+// ------------------------------------------- 16-bit build, slot order -----
+// The 16-bit forms store columns in groups of 8 slots.  So that one workgroup
+// can write whole 16-byte groups straight from LDS-staged PSFs, the slots
+// are ordered by radial bracket: a stable counting sort (bracket, then column
+// index) gives slot s -> column perm[s], and the buckets are cut into work
+// items along 16-slot windows.  A workgroup builds the (up to 16) columns of
+// one item from its bracket's pair, one wave per column, a few image rows at
+// a time: each wave rounds its values to the 16-bit format into an LDS tile,
+// and after a barrier every thread gathers the 8 slots of one (group, pixel)
+// and writes them as one 16-byte store (2-byte stores for the slots of a
+// group that belong to the neighbouring bucket's item).  The float32 values,
+// their rounding and the column sums are those of the float32 build.
+
+constexpr int kSortBlock = 1024;  // columns per block of the stable sort
+
+// counts of every bucket in every block of kSortBlock columns: cnt[blk][b]
+__global__ __launch_bounds__(kSortBlock) void sort_count_kernel(const ColGeom* __restrict__ geo,
+                                                                int64_t ncols, int nb,
+                                                                int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // nb
+  for (int b = threadIdx.x; b < nb; b += kSortBlock) hist[b] = 0;
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
+  if (j < ncols) atomicAdd(hist + bucket_of(geo, j, nb), 1);  // counts: order-free
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kSortBlock) cnt[(int64_t)blockIdx.x * nb + b] = hist[b];
+}
+
+// One workgroup.  cnt[blk][b] becomes the first slot of bucket b's columns of
+// block blk (bucket start + the bucket's columns in earlier blocks); items
+// (bucket, first slot, length, 16-slot window start) cover every bucket along
+// 16-slot windows.
+__global__ __launch_bounds__(1024) void sort_scan_kernel(int32_t* __restrict__ cnt, int64_t nblk,
+                                                         int nb, int4* __restrict__ items,
+                                                         int32_t* __restrict__ nitems) {
+  __shared__ int32_t s_cols[1024], s_items[1024];
+  __shared__ int32_t tot[kLdsMaxBuckets];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < nb; b += 1024) {  // independent loads: no store in between
+    int32_t run = 0;
+    for (int64_t k = 0; k < nblk; ++k) run += cnt[k * nb + b];
+    tot[b] = run;
+  }
+  __syncthreads();
+  const int per = (nb + 1023) / 1024;
+  const int b0 = tid * per, b1 = (b0 + per < nb) ? b0 + per : nb;
+  int my_cols = 0;
+  for (int b = b0; b < b1; ++b) my_cols += tot[b];
+  s_cols[tid] = my_cols;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int c = tid >= off ? s_cols[tid - off] : 0;
+    __syncthreads();
+    s_cols[tid] += c;
+    __syncthreads();
+  }
+  // bucket starts, then the items of each bucket
+  int start = s_cols[tid] - my_cols, my_items = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int c = tot[b];
+    if (c > 0) my_items += (start + c - 1) / 16 - start / 16 + 1;
+    start += c;
+  }
+  s_items[tid] = my_items;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int c = tid >= off ? s_items[tid - off] : 0;
+    __syncthreads();
+    s_items[tid] += c;
+    __syncthreads();
+  }
+  start = s_cols[tid] - my_cols;
+  int item = s_items[tid] - my_items;
+  for (int b = b0; b < b1; ++b) {
+    const int c = tot[b];
+    int32_t run = start;  // first slot of bucket b in each block
+    for (int64_t k0 = 0; k0 < nblk; k0 += 16) {
+      int32_t v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = (k0 + u < nblk) ? cnt[(k0 + u) * nb + b] : 0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < nblk) {
+          cnt[(k0 + u) * nb + b] = run;
+          run += v[u];
+        }
+    }
+    for (int w = start / 16 * 16; c > 0 && w < start + c; w += 16) {
+      const int lo = w > start ? w : start;
+      const int hi = (w + 16 < start + c) ? w + 16 : start + c;
+      items[item++] = make_int4(b, lo, hi - lo, w);
+    }
+    start += c;
+  }
+  if (tid == 1023) *nitems = s_items[1023];
+}
+
+// Slots: a column's slot is its block's first slot of the bucket plus its
+// rank among the block's earlier columns of the same bucket.  Each wave ranks
+// its 64 columns with one ballot per bucket present; then the waves take
+// their slots in order, each adding its counts to a per-bucket cursor in LDS
+// that starts at the block's first slots.  Also the slot's exponent.
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const ColGeom* __restrict__ geo,
+                                                                  int64_t ncols, int nb,
+                                                                  const int32_t* __restrict__ first,
+                                                                  int32_t* __restrict__ perm,
+                                                                  int32_t* __restrict__ slot_of,
+                                                                  int32_t* __restrict__ eslot) {
+  extern __shared__ int32_t cursor[];  // nb
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = tid; q < nb; q += kSortBlock) cursor[q] = first[(int64_t)blockIdx.x * nb + q];
+  const int64_t j = (int64_t)blockIdx.x * kSortBlock + tid;
+  const bool valid = j < ncols;
+  const int b = valid ? bucket_of(geo, j, nb) : -1;
+  uint64_t todo = __ballot(valid);
+  int rank = 0, count = 0;
+  while (todo) {  // uniform: one pass per bucket present in the wave
+    const int bl = __shfl(b, __builtin_ctzll(todo), 64);
+    const uint64_t m = __ballot(valid && b == bl);
+    if (valid && b == bl) {
+      rank = __popcll(m & ((1ull << lane) - 1ull));
+      count = __popcll(m);
+    }
+    todo &= ~m;
+  }
+  __syncthreads();
+  int slot = 0;
+  for (int w = 0; w < kSortBlock / 64; ++w) {
+    if (wave == w && valid) {
+      slot = cursor[b] + rank;  // every lane reads before the wave's leaders add
+      __builtin_amdgcn_wave_barrier();
+      if (rank == 0) cursor[b] += count;
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  perm[slot] = (int32_t)j;
+  slot_of[j] = slot;
+  eslot[slot] = geo[j].e;
+}
+
+template <int E, bool FULL, bool BF16>
+__global__ __launch_bounds__(1024) void build_lds16_kernel(const float* __restrict__ cube, int K,
+                                                           const ColGeom* __restrict__ geo,
+                                                           const int32_t* __restrict__ perm,
+                                                           const int4* __restrict__ items,
+                                                           const int32_t* __restrict__ nitems,
+                                                           int nb, int n, int ls, int R, int64_t M,
+                                                           uint16_t* __restrict__ Mh,
+                                                           double* __restrict__ tau) {
+  extern __shared__ float2 P2[];  // bordered pair, (n+2) rows of stride ls; then the 16-bit tile
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int np = n + 2;
+  uint16_t* T = reinterpret_cast<uint16_t*>(P2 + (size_t)np * ls);  // [16][R * n]
+  const int tstride = R * n;
+  if (!zero_bucket) {
+    const float* Pk = cube + (int64_t)bkt * M;
+    const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+    for (int idx = tid; idx < 4 * np; idx += 1024) {
+      const int side = idx / np, t = idx % np;
+      const int pos = side == 0 ? t : side == 1 ? (np - 1) * ls + t
+                    : side == 2 ? t * ls : t * ls + np - 1;
+      P2[pos] = make_float2(0.0f, 0.0f);
+    }
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(cube) & 15) == 0) {
+      const int nq = n >> 2;
+      for (int q = tid; q < n * nq; q += 1024) {
+        const int rr = q / nq, cc = 4 * (q - rr * nq);
+        const f32x4 a = *reinterpret_cast<const f32x4*>(Pk + rr * n + cc);
+        const f32x4 b = Pk1 ? *reinterpret_cast<const f32x4*>(Pk1 + rr * n + cc)
+                            : (f32x4){0.f, 0.f, 0.f, 0.f};
+        float2* dst = P2 + (rr + 1) * ls + cc + 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = make_float2(a[e], b[e]);
+      }
+    } else {
+      for (int q = tid; q < n * n; q += 1024) {
+        const int rr = q / n, cc = q - rr * n;
+        P2[(rr + 1) * ls + cc + 1] = make_float2(Pk[q], Pk1 ? Pk1[q] : 0.0f);
+      }
+    }
+  }
+  const int slot = w0 + wave;
+  const bool live = slot >= first && slot < first + len;  // uniform per wave
+  int64_t j = 0;
+  ColGeom g;
+  g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
+  if (live) {
+    j = perm[slot];
+    g = geo[j];
+  }
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  double ctux[E], mstux[E];
+#pragma unroll
+  for (int v = 0; v < E; ++v) {
+#pragma clang fp contract(off)
+    const double ux = (double)(lane + 64 * v) - c;
+    ctux[v] = g.ct * ux;
+    mstux[v] = (-g.st) * ux;
+  }
+  double tsum = 0.0;
+  // the slots of this item among the item's two groups
+  const int64_t grp0 = w0 / 8;
+  for (int a0 = 0; a0 < n; a0 += R) {
+    const int rows = (n - a0 < R) ? n - a0 : R;
+    __syncthreads();  // the pair is staged; the previous tile has been stored
+    if (live) {
+      for (int r = 0; r < rows; ++r) {
+        const int a = a0 + r;
+        double stuy, ctuy;
+        {
+#pragma clang fp contract(off)
+          const double uy = (double)a - c;
+          stuy = g.st * uy;
+          ctuy = g.ct * uy;
+        }
+        float rowsum = 0.0f;
+#pragma unroll
+        for (int v = 0; v < E; ++v) {
+          const int b = lane + 64 * v;
+          if (FULL || b < n) {
+            float val = 0.0f;
+            if (!zero_bucket) {
+              const Tap t = tap_coords(ctux[v], mstux[v], stuy, ctuy, c, n, ls);
+              const float2 p00 = P2[t.idx], p01 = P2[t.idx + 1];
+              const float2 p10 = P2[t.idx + ls], p11 = P2[t.idx + ls + 1];
+              const float q00 = fmaf(wk1, p00.y, wk0 * p00.x);
+              const float q01 = fmaf(wk1, p01.y, wk0 * p01.x);
+              const float q10 = fmaf(wk1, p10.y, wk0 * p10.x);
+              const float q11 = fmaf(wk1, p11.y, wk0 * p11.x);
+              val = (t.gy * t.gx) * q00;
+              val = fmaf(t.gy * t.fx, q01, val);
+              val = fmaf(t.fy * t.gx, q10, val);
+              val = fmaf(t.fy * t.fx, q11, val);
+              val = t.ok ? val : 0.0f;
+            }
+            rowsum += val;
+            const float x = ldexpf(val, -g.e);  // exact power-of-two scaling
+            uint32_t h;
+            if constexpr (BF16) {
+              uint32_t u = __float_as_uint(x);
+              u += 0x7FFFu + ((u >> 16) & 1u);  // finite: round to nearest, ties to even
+              h = u >> 16;
+            } else {
+              h = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+            }
+            T[wave * tstride + r * n + b] = (uint16_t)h;
+          }
+        }
+        tsum += (double)rowsum;
+      }
+    }
+    __syncthreads();
+    // (group gi, pixel p of the tile): the 8 slots of the group at that pixel
+    const int units = 2 * rows * n;
+    for (int u = tid; u < units; u += 1024) {
+      const int gi = u / (rows * n), p = u - gi * (rows * n);
+      const int s0 = 8 * gi;  // first slot of the group, relative to w0
+      const int lo = (first - w0 > s0) ? first - w0 : s0;
+      const int hi = (first + len - w0 < s0 + 8) ? first + len - w0 : s0 + 8;
+      if (lo >= hi) continue;  // no slot of this group in the item
+      const int64_t i = (int64_t)a0 * n + p;
+      uint16_t* dst = Mh + ((grp0 + gi) * M + i) * 8;
+      if (lo == s0 && hi == s0 + 8) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          w[q] = (uint32_t)T[(s0 + 2 * q) * tstride + p] | ((uint32_t)T[(s0 + 2 * q + 1) * tstride + p] << 16);
+        __builtin_nontemporal_store((u32x4){w[0], w[1], w[2], w[3]}, reinterpret_cast<u32x4*>(dst));
+      } else {
+        for (int q = lo; q < hi; ++q) dst[q - s0] = T[q * tstride + p];
+      }
+    }
+  }
+  if (!live) return;
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) tau[j] = tsum;
+}
+
 // 16-bit packing: M16[g][i][u] = RN16(A32[8g+u][i] * 2^-e), zeros past ncols.
 // Two rows per thread: 8 x 8-byte loads (one per column; 512 B per wave and
 // column) and 32 contiguous bytes stored.
@@ -519,6 +803,17 @@ __global__ __launch_bounds__(256) void pack16_kernel(const float* __restrict__ A
     pk.w = h[6] | (h[7] << 16);
     __builtin_nontemporal_store(pk, Mp + grp * M + i0 + r);
   }
+}
+
+// Zero mantissas of the padding slots [ncols, ncols_pad): thread = (group, row).
+__global__ __launch_bounds__(256) void zero_pad16_kernel(uint16_t* __restrict__ Mh, int64_t M,
+                                                         int64_t ncols, int64_t g0) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int64_t grp = g0 + blockIdx.y;
+  uint16_t* dst = Mh + (grp * M + i) * 8;
+  for (int q = 0; q < 8; ++q)
+    if (grp * 8 + q >= ncols) dst[q] = 0;
 }
 
 // ------------------------------------------------------------- launch -----
@@ -607,6 +902,84 @@ hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int6
   else
     pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
   return hipGetLastError();
+}
+
+// rows of the 16-bit tile that fit next to the bordered pair (0: none)
+static int lds16_rows(int n) {
+  const size_t pair = (size_t)(n + 2) * lds_stride(n) * sizeof(float2);
+  for (int R = 4; R >= 1; R >>= 1)
+    if (pair + (size_t)16 * R * n * 2 <= (size_t)kLdsBuildMaxBytes) return R;
+  return 0;
+}
+
+bool build_lds16_supported(int n, int K, int64_t ncols) {
+  if (K > kLdsMaxBuckets - 1 || n > 141 || lds16_rows(n) == 0) return false;
+  const int64_t nblk = (ncols + kSortBlock - 1) / kSortBlock;
+  return nblk * nbuckets(K) <= ((int64_t)1 << 24) && ncols < ((int64_t)1 << 31);
+}
+
+size_t build_lds16_scratch_bytes(int K, int64_t ncols) {
+  const int64_t nb = nbuckets(K);
+  const int64_t nblk = (ncols + kSortBlock - 1) / kSortBlock;
+  const int64_t items_max = (ncols + 15) / 16 + 2 * nb + 1;
+  return (((size_t)nblk * nb * 4 + 255) & ~(size_t)255) + (((size_t)items_max * 16 + 16 + 255) & ~(size_t)255);
+}
+
+hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                              int64_t M, int64_t ncols, int64_t ncols_pad, const int32_t* exps,
+                              int32_t* perm, int32_t* eslot, int32_t* slot_of, void* lib,
+                              double* tau, void* scratch, hipStream_t s) {
+  const int nb = nbuckets(K);
+  const int64_t nblk = (ncols + kSortBlock - 1) / kSortBlock;
+  const int64_t items_max = (ncols + 15) / 16 + 2 * nb + 1;
+  char* p = reinterpret_cast<char*>(scratch);
+  int32_t* cnt = reinterpret_cast<int32_t*>(p);
+  p += ((size_t)nblk * nb * 4 + 255) & ~(size_t)255;
+  int4* items = reinterpret_cast<int4*>(p);
+  int32_t* nitems = reinterpret_cast<int32_t*>(items + items_max);
+  // padding slots (and defaults) first; the sort then places every column
+  hipError_t e = launch_identity_order(perm, eslot, slot_of, exps, ncols, ncols_pad, s);
+  if (e != hipSuccess) return e;
+  sort_count_kernel<<<(unsigned)nblk, kSortBlock, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt);
+  sort_scan_kernel<<<1, 1024, 0, s>>>(cnt, nblk, nb, items, nitems);
+  sort_scatter_kernel<<<(unsigned)nblk, kSortBlock, (size_t)nb * 4, s>>>(geo, ncols, nb, cnt, perm,
+                                                                         slot_of, eslot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ls = lds_stride(n), R = lds16_rows(n);
+  const size_t lds = (size_t)(n + 2) * ls * sizeof(float2) + (size_t)16 * R * n * 2;
+  const bool full = (n % 64) == 0;
+  const bool bf = storage == PSFLIB_BF16_POW2;
+  uint16_t* Mh = reinterpret_cast<uint16_t*>(lib);
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<(unsigned)items_max, 1024, lds, s>>>(cube, K, geo, perm, items, nitems, nb, n, ls, R, M,
+                                                Mh, tau);
+    return hipGetLastError();
+  };
+  switch (lds_e(n)) {
+    case 1:
+      e = full ? (bf ? launch(build_lds16_kernel<1, true, true>) : launch(build_lds16_kernel<1, true, false>))
+               : (bf ? launch(build_lds16_kernel<1, false, true>) : launch(build_lds16_kernel<1, false, false>));
+      break;
+    case 2:
+      e = full ? (bf ? launch(build_lds16_kernel<2, true, true>) : launch(build_lds16_kernel<2, true, false>))
+               : (bf ? launch(build_lds16_kernel<2, false, true>) : launch(build_lds16_kernel<2, false, false>));
+      break;
+    default:
+      e = bf ? launch(build_lds16_kernel<3, false, true>) : launch(build_lds16_kernel<3, false, false>);
+      break;
+  }
+  if (e != hipSuccess) return e;
+  if (ncols_pad > ncols) {
+    const int64_t g0 = ncols / 8;
+    zero_pad16_kernel<<<dim3((unsigned)((M + 255) / 256), (unsigned)(ncols_pad / 8 - g0)), 256, 0, s>>>(
+        Mh, M, ncols, g0);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,

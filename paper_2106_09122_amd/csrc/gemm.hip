@@ -352,24 +352,38 @@ __global__ __launch_bounds__(1024) void scene_exponent_kernel(const float* __res
   }
 }
 
-// Thread = (group g, scene n): 8 lanes cover one group of 8 consecutive
-// scenes, so each wave reads 8 runs of 256 contiguous bytes (8 groups of 8
-// scenes) and writes 8 whole 128-byte lines of Zg.
-template <bool BF16, bool VEC>
+// Thread = (slot group g, scene n): 8 lanes cover one group of 8 consecutive
+// scenes and write 8 whole 128-byte lines of Zg per wave.  Slot s of the
+// group holds column perm[s] of the library (the scene value gathered from
+// it) with exponent eslot[s]; padding slots (perm -1) get zeros.
+template <bool BF16>
 __global__ __launch_bounds__(256) void pack_scenes_kernel(const float* __restrict__ Z,
-                                                          const int32_t* __restrict__ exps,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ eslot,
                                                           const int32_t* __restrict__ fexp,
                                                           int64_t ncols, int64_t ngroups,
                                                           int64_t bc, int64_t Bp,
                                                           u32x4* __restrict__ Zg) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   const int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
   if (g >= ngroups) return;
   const int64_t n = (int64_t)blockIdx.y * 8 + (threadIdx.x & 7);
   u32x4 pk = {0u, 0u, 0u, 0u};
   if (n < bc) {
+    const i32x4 p0 = *reinterpret_cast<const i32x4*>(perm + 8 * g);
+    const i32x4 p1 = *reinterpret_cast<const i32x4*>(perm + 8 * g + 4);
+    const i32x4 e0 = *reinterpret_cast<const i32x4*>(eslot + 8 * g);
+    const i32x4 e1 = *reinterpret_cast<const i32x4*>(eslot + 8 * g + 4);
+    const float* z = Z + n * ncols;
     float v[8];
     int32_t e[8];
-    load_group<VEC>(Z + n * ncols, exps, ncols, g, v, e);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = p0[q] >= 0 ? z[p0[q]] : 0.0f;
+      v[4 + q] = p1[q] >= 0 ? z[p1[q]] : 0.0f;
+      e[q] = e0[q];
+      e[4 + q] = e1[q];
+    }
     const int f = fexp[n];
     uint32_t h[8];
 #pragma unroll
@@ -828,7 +842,7 @@ size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncol
   return bytes + part;
 }
 
-hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, const float* Z,
+hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const float* Z,
                           float* out, int64_t M, int64_t ncols, int64_t ncols_pad, int B,
                           void* scratch, size_t scratch_bytes, hipStream_t s) {
   if (B <= 0) return hipSuccess;
@@ -877,20 +891,16 @@ hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, con
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
       const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
       if (vec)
-        scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
+        scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
       else
-        scene_exponent_kernel<false><<<(unsigned)bc, 1024, 0, s>>>(Zc, exps, ncols, ngroups, fexp);
+        scene_exponent_kernel<false><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
-      if (bf && vec)
-        pack_scenes_kernel<true, true><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
-      else if (bf)
-        pack_scenes_kernel<true, false><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
-      else if (vec)
-        pack_scenes_kernel<false, true><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
+      if (bf)
+        pack_scenes_kernel<true><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
       else
-        pack_scenes_kernel<false, false><<<pgrid, 256, 0, s>>>(Zc, exps, fexp, ncols, ngroups, bc, Bp, Zg);
+        pack_scenes_kernel<false><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);

@@ -11,20 +11,32 @@
 namespace psflib {
 
 // Largest value of each sampled PSF (exact float32 max); used for the 16-bit
-// column exponents.  One workgroup per PSF.
-__global__ __launch_bounds__(256) void cube_max_kernel(const float* __restrict__ cube, int64_t M,
-                                                       float* __restrict__ pmax) {
-  __shared__ float red[256];
+// column exponents.  One workgroup per PSF, four independent loads in flight
+// per thread.
+__global__ __launch_bounds__(1024) void cube_max_kernel(const float* __restrict__ cube, int64_t M,
+                                                        float* __restrict__ pmax) {
+  __shared__ float red[16];
   const float* P = cube + (int64_t)blockIdx.x * M;
-  float m = 0.0f;
-  for (int64_t i = threadIdx.x; i < M; i += 256) m = fmaxf(m, P[i]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * 1024 < M; i += 4 * 1024) {
+    m0 = fmaxf(m0, P[i]);
+    m1 = fmaxf(m1, P[i + 1024]);
+    m2 = fmaxf(m2, P[i + 2 * 1024]);
+    m3 = fmaxf(m3, P[i + 3 * 1024]);
   }
-  if (threadIdx.x == 0) pmax[blockIdx.x] = red[0];
+  for (; i < M; i += 1024) m0 = fmaxf(m0, P[i]);
+  float m = fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    m = threadIdx.x < 16 ? red[threadIdx.x] : 0.0f;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+  }
 }
 
 // pairs[k][p] = (P_k[p], P_{k+1}[p]) for k < max(K-1, 1), so one 8-byte load
@@ -141,7 +153,7 @@ __global__ __launch_bounds__(256) void export_geometry_kernel(const ColGeom* __r
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t launch_cube_max(const float* cube, int K, int64_t M, float* pmax, hipStream_t s) {
-  cube_max_kernel<<<K, 256, 0, s>>>(cube, M, pmax);
+  cube_max_kernel<<<K, 1024, 0, s>>>(cube, M, pmax);
   return hipGetLastError();
 }
 

@@ -51,11 +51,13 @@ struct GScene {
 };
 
 // A scene group: slots slot0 .. slot0+nscenes-1 of one library, packed into
-// the matrix-core operand at bpk: 16-bit, ngroups 8-column groups x 32 columns
-// x 16 bytes; FP32, ngroups 16-column blocks x 64 lanes x 16 bytes.
+// the matrix-core operand at bpk: 16-bit, ngroups 8-slot groups x 32 columns
+// x 16 bytes (library slot s holds column perm[s], exponent eslot[s]); FP32,
+// ngroups 16-column blocks x 64 lanes x 16 bytes.
 struct GPack {
   int64_t bpk, ncols, ngroups;
-  const int32_t* exps;
+  const int32_t* perm;
+  const int32_t* eslot;
   int32_t slot0, nscenes;
 };
 
@@ -290,9 +292,10 @@ __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restri
       const int f = fexp[pk.slot0 + r];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int64_t j = g * 8 + u;
+        const int64_t slot = g * 8 + u;
+        const int32_t j = pk.perm[slot];
         float v = 0.0f;
-        if (j < pk.ncols) v = ldexpf(z[j], pk.exps[j] + f);
+        if (j >= 0) v = ldexpf(z[j], pk.eslot[slot] + f);
         const uint16_t h = g16_round<BF16>(v);
         const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
         hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
@@ -423,7 +426,7 @@ namespace {
 
 struct LibInfo {
   const void* A;
-  const int32_t* exps;
+  psflib::Cols16 cx;
   int64_t M, ncols, ncols_pad;
 };
 
@@ -461,10 +464,10 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
       for (int r = 0; r < ns; ++r) {
         p.scenes.push_back(scenes[sc[g0 + r]]);
         p.images.push_back(images[sc[g0 + r]]);
-        p.slots.push_back(psflib::GScene{scenes[sc[g0 + r]], li.exps, li.ncols});
+        p.slots.push_back(psflib::GScene{scenes[sc[g0 + r]], li.cx.exps, li.ncols});
       }
       const int64_t bpk = p.bpk_vecs;
-      p.packs.push_back(psflib::GPack{bpk, li.ncols, pk_units, li.exps, scene0, ns});
+      p.packs.push_back(psflib::GPack{bpk, li.ncols, pk_units, li.cx.perm, li.cx.eslot, scene0, ns});
       p.bpk_vecs += pk_units * (f32 ? 64 : 32);
       for (int64_t rb = 0; rb < nrb; ++rb) {
         psflib::GReduce rd;
@@ -481,7 +484,7 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
         for (int64_t c = 0; c < nchunks; ++c) {
           psflib::GItem it;
           it.A = li.A;
-          it.exps = li.exps;
+          it.exps = li.cx.exps;
           it.M = li.M;
           it.ncols = li.ncols;
           it.row0 = rb * rows_per;
@@ -616,7 +619,7 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
     if (!h_libs[L]) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: NULL library handle");
     LibInfo li;
     int st, d;
-    psflib::handle_info(h_libs[L], &li.A, &li.exps, &li.M, &li.ncols, &li.ncols_pad, &st, &d);
+    psflib::handle_info(h_libs[L], &li.A, &li.cx, &li.M, &li.ncols, &li.ncols_pad, &st, &d);
     if (storage < 0) { storage = st; dev = d; }
     if (st != storage)
       return psflib::fail_status(PSFLIB_ERR_UNSUPPORTED, "grouped: all libraries must share one storage form");

@@ -181,12 +181,21 @@ void StreamUses::wait_all() {
 
 StreamUses::~StreamUses() { wait_all(); }
 
-void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
-                 int64_t* ncols, int64_t* ncols_pad, int* storage, int* device) {
+Cols16 cols16_of(const psflib_handle* h) {
+  Cols16 cx = {nullptr, nullptr, nullptr, nullptr};
+  if (h->desc.storage == PSFLIB_FP32) return cx;
   const char* lib = reinterpret_cast<const char*>(h->lib);
+  cx.exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  cx.perm = reinterpret_cast<const int32_t*>(lib + h->L.off_perm);
+  cx.eslot = reinterpret_cast<const int32_t*>(lib + h->L.off_eslot);
+  cx.slot_of = reinterpret_cast<const int32_t*>(lib + h->L.off_slot);
+  return cx;
+}
+
+void handle_info(const psflib_handle* h, const void** A, Cols16* cx, int64_t* M,
+                 int64_t* ncols, int64_t* ncols_pad, int* storage, int* device) {
   *A = h->lib;
-  *exps = (h->desc.storage == PSFLIB_FP32) ? nullptr
-                                          : reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  *cx = cols16_of(h);
   *M = h->L.M;
   *ncols = h->L.ncols;
   *ncols_pad = h->L.ncols_pad;
@@ -209,8 +218,16 @@ bool compute_layout(const psflib_desc& d, Layout* L) {
   L->ncols_pad = ncols_pad;
   L->off_tau = off;
   off = align256(off + (size_t)ncols * 8);
-  L->off_exp = off;
-  if (d.storage != PSFLIB_FP32) off = align256(off + (size_t)ncols_pad * 4);
+  L->off_exp = L->off_perm = L->off_eslot = L->off_slot = off;
+  if (d.storage != PSFLIB_FP32) {
+    off = align256(off + (size_t)ncols_pad * 4);  // exponent per column
+    L->off_perm = off;
+    off = align256(off + (size_t)ncols_pad * 4);  // slot -> column
+    L->off_eslot = off;
+    off = align256(off + (size_t)ncols_pad * 4);  // exponent per slot
+    L->off_slot = off;
+    off = align256(off + (size_t)ncols * 4);      // column -> slot
+  }
   L->total = off;
   return L->total <= ((size_t)1 << 62);
 }
@@ -312,12 +329,18 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
   const bool lds = cubic ? psflib::build_cubic_lds_supported(desc->n)
                          : psflib::build_lds_supported(desc->n, K);
-  const bool stage32 = storage != PSFLIB_FP32 && (lds || flux);
+  // 16-bit libraries of bilinear, unrescaled columns whose pair fits the LDS
+  // are written directly in bracket order; the other 16-bit builds go through
+  // float32 columns and a packing pass (natural order)
+  const bool direct16 = storage != PSFLIB_FP32 && !cubic && !flux && lds &&
+                        psflib::build_lds16_supported(desc->n, K, L.ncols);
+  const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
-      spline_bytes + align256(lds ? psflib::bucket_scratch_bytes(K, L.ncols)
-                              : cubic ? 0
-                                      : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
+      spline_bytes + align256(direct16 ? psflib::build_lds16_scratch_bytes(K, L.ncols)
+                              : lds    ? psflib::bucket_scratch_bytes(K, L.ncols)
+                              : cubic  ? 0
+                                       : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
   const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
   const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
@@ -365,6 +388,13 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
     e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
                                    desc->n, L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "cubic build kernel");
+  } else if (direct16) {
+    e = psflib::launch_build_lds16(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
+                                   exps, reinterpret_cast<int32_t*>(lib + L.off_perm),
+                                   reinterpret_cast<int32_t*>(lib + L.off_eslot),
+                                   reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
+                                   path_tmp, s);
+    if (e != hipSuccess) return bail(e, "16-bit LDS build kernels");
   } else if (lds) {
     e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, L.M, L.ncols,
                                  reinterpret_cast<float*>(bdst), tau, path_tmp, s);
@@ -387,6 +417,14 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
     e = psflib::launch_pack16(storage, A32, h->geo, L.M, L.ncols, L.ncols_pad, d_lib, s);
     if (e != hipSuccess) return bail(e, "16-bit packing kernel");
   }
+  if (storage != PSFLIB_FP32 && !direct16) {
+    // natural column order: slot s holds column s
+    e = psflib::launch_identity_order(reinterpret_cast<int32_t*>(lib + L.off_perm),
+                                      reinterpret_cast<int32_t*>(lib + L.off_eslot),
+                                      reinterpret_cast<int32_t*>(lib + L.off_slot), exps, L.ncols,
+                                      L.ncols_pad, s);
+    if (e != hipSuccess) return bail(e, "column order kernel");
+  }
   e = hipFreeAsync(tmp, s);
   if (e != hipSuccess) { tmp = nullptr; return bail(e, "hipFreeAsync(build scratch)"); }
   tmp = nullptr;
@@ -402,12 +440,11 @@ namespace {
 // partial sums in `partial` (at least the launcher's partial count).
 hipError_t launch_product(const psflib_handle* h, bool adjoint, const float* in, float* out,
                           float* partial, hipStream_t s) {
-  const char* lib = reinterpret_cast<const char*>(h->lib);
-  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
+  const psflib::Cols16 cx = psflib::cols16_of(h);
   if (adjoint)
-    return psflib::launch_adjoint(h->desc.storage, h->lib, exps, in, h->L.M, h->L.ncols,
+    return psflib::launch_adjoint(h->desc.storage, h->lib, cx, in, h->L.M, h->L.ncols,
                                   h->L.ncols_pad, partial, out, s);
-  return psflib::launch_matvec(h->desc.storage, h->lib, exps, in, h->L.M, h->L.ncols,
+  return psflib::launch_matvec(h->desc.storage, h->lib, cx, in, h->L.M, h->L.ncols,
                                h->L.ncols_pad, partial, out, s);
 }
 
@@ -569,10 +606,8 @@ psflib_status psflib_apply_batched(const psflib_handle* h, const float* d_scenes
   CallScratch cs;
   hipError_t e = cs.acquire(h->device, s, bytes);
   if (e != hipSuccess) return device_fail(e, "scratch buffer (batched)");
-  const char* lib = reinterpret_cast<const char*>(h->lib);
-  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
-  e = psflib::launch_batched(h->desc.storage, h->lib, exps, d_scenes, d_images, h->L.M, h->L.ncols,
-                             h->L.ncols_pad, B, cs.ptr(), bytes, s);
+  e = psflib::launch_batched(h->desc.storage, h->lib, psflib::cols16_of(h), d_scenes, d_images,
+                             h->L.M, h->L.ncols, h->L.ncols_pad, B, cs.ptr(), bytes, s);
   const hipError_t e2 = cs.release();
   if (e == hipSuccess) e = e2;
   if (e != hipSuccess) return device_fail(e, "batched kernels");
@@ -605,9 +640,7 @@ psflib_status psflib_get_columns(const psflib_handle* h, const int32_t* d_cols, 
     return fail(PSFLIB_ERR_INVALID_ARG, "d_cols and d_out must be 16-byte aligned");
   st = psflib::check_pending_error();
   if (st != PSFLIB_OK) return st;
-  const char* lib = reinterpret_cast<const char*>(h->lib);
-  const int32_t* exps = reinterpret_cast<const int32_t*>(lib + h->L.off_exp);
-  hipError_t e = psflib::launch_get_columns(h->desc.storage, h->lib, exps, d_cols, count, h->L.M,
+  hipError_t e = psflib::launch_get_columns(h->desc.storage, h->lib, psflib::cols16_of(h), d_cols, count, h->L.M,
                                             h->L.ncols, d_out, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "get_columns kernel");
   return PSFLIB_OK;

@@ -41,12 +41,26 @@ constexpr int32_t kZeroColumnExp = PSFLIB_ZERO_COLUMN_EXPONENT;  // exponent of 
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter
+constexpr int kLdsMaxBuckets = 8193; // LDS builds: radial brackets + the zero-column bucket, at most
 
 struct Layout {
   int64_t M;          // n*n image pixels (rows of A)
   int64_t ncols;      // N*N scene pixels (columns of A)
   int64_t ncols_pad;  // columns stored (multiple of kColPad for 16-bit forms)
-  size_t off_tau, off_exp, total;
+  // byte offsets in the library buffer: column sums; 16-bit forms: exponents
+  // per column, slot -> column map, exponents per slot, column -> slot map
+  size_t off_tau, off_exp, off_perm, off_eslot, off_slot, total;
+};
+
+// Column order of the 16-bit storage forms: mantissa slot s (in groups of 8
+// slots) holds column perm[s] (-1 for padding) with exponent eslot[s];
+// column j sits in slot slot_of[j] and has exponent exps[j].  All nullptr for
+// FP32 storage (natural column order).
+struct Cols16 {
+  const int32_t* exps;     // [ncols_pad] per column
+  const int32_t* perm;     // [ncols_pad] slot -> column
+  const int32_t* eslot;    // [ncols_pad] per slot
+  const int32_t* slot_of;  // [ncols] column -> slot
 };
 
 bool compute_layout(const psflib_desc& d, Layout* L);
@@ -91,8 +105,13 @@ constexpr size_t kNoAllocScratchBytes = PSFLIB_NOALLOC_SCRATCH_BYTES;
 hipError_t noalloc_scratch(int dev, void** ptr);
 
 // Read-only view of a built library for the grouped apply.
-void handle_info(const psflib_handle* h, const void** A, const int32_t** exps, int64_t* M,
+void handle_info(const psflib_handle* h, const void** A, Cols16* cx, int64_t* M,
                  int64_t* ncols, int64_t* ncols_pad, int* storage, int* device);
+// Natural column order for a 16-bit library (slot s = column s) and the
+// per-slot exponents, once the per-column exponents are final.
+hipError_t launch_identity_order(int32_t* perm, int32_t* eslot, int32_t* slot_of,
+                                 const int32_t* exps, int64_t ncols, int64_t ncols_pad,
+                                 hipStream_t s);
 
 // The four cubic B-spline weights of the taps at offsets -1, 0, +1, +2 from
 // floor(x), for t = x - floor(x) in [0, 1): beta3 at distances 1+t, t, 1-t,
@@ -152,6 +171,16 @@ hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* sc
 // float32 columns (A32[j*M + i]) and their float64 sums
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
                             int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s);
+// 16-bit storage built directly (bilinear rotation, no column rescale, the
+// pair and a 16-bit tile in LDS): columns ordered by radial bracket (perm,
+// slot_of, eslot written here, exps per column given), mantissas written as
+// whole 8-slot groups; column sums in tau.
+bool build_lds16_supported(int n, int K, int64_t ncols);
+size_t build_lds16_scratch_bytes(int K, int64_t ncols);
+hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                              int64_t M, int64_t ncols, int64_t ncols_pad, const int32_t* exps,
+                              int32_t* perm, int32_t* eslot, int32_t* slot_of, void* lib,
+                              double* tau, void* scratch, hipStream_t s);
 // 16-bit storage from float32 columns with the exponents in geo
 hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int64_t M,
                          int64_t ncols, int64_t ncols_pad, void* lib, hipStream_t s);
@@ -162,19 +191,19 @@ hipError_t launch_psf_sums(const float* cube, int K, int64_t M, double* sums, hi
 hipError_t launch_flux_rescale(float* A32, ColGeom* geo, int K, const double* sums,
                                const float* pmax, int64_t M, int64_t ncols, double* tau,
                                int32_t* exps, bool want_exp, hipStream_t s);
-hipError_t launch_matvec(int storage, const void* lib, const int32_t* exps, const float* Z,
+hipError_t launch_matvec(int storage, const void* lib, const Cols16& cx, const float* Z,
                          int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                          hipStream_t s);
 int64_t matvec_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad);
-hipError_t launch_adjoint(int storage, const void* lib, const int32_t* exps, const float* g,
+hipError_t launch_adjoint(int storage, const void* lib, const Cols16& cx, const float* g,
                           int64_t M, int64_t ncols, int64_t ncols_pad, float* partial, float* out,
                           hipStream_t s);
 int64_t adjoint_partial_floats(int storage, int64_t M, int64_t ncols, int64_t ncols_pad);
-hipError_t launch_batched(int storage, const void* lib, const int32_t* exps, const float* Z,
+hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const float* Z,
                           float* out, int64_t M, int64_t ncols, int64_t ncols_pad, int B,
                           void* scratch, size_t scratch_bytes, hipStream_t s);
 size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncols_pad, int B);
-hipError_t launch_get_columns(int storage, const void* lib, const int32_t* exps,
+hipError_t launch_get_columns(int storage, const void* lib, const Cols16& cx,
                               const int32_t* cols, int count, int64_t M, int64_t ncols,
                               float* out, hipStream_t s);
 hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,

@@ -53,8 +53,13 @@ def test_library_bytes_layout(n, N, storage):
     if storage == "fp32":
         want = _align(_align(M * nc * 4) + nc * 8)
     else:
+        # mantissas | column sums | exponent per column | slot -> column |
+        # exponent per slot | column -> slot
         ncp = (nc + 63) // 64 * 64
-        want = _align(_align(_align(M * ncp * 2) + nc * 8) + ncp * 4)
+        off = _align(M * ncp * 2)
+        for part in (nc * 8, ncp * 4, ncp * 4, ncp * 4, nc * 4):
+            off = _align(off + part)
+        want = off
     assert psflib.library_bytes(d) == want
 
 

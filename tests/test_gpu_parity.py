@@ -429,3 +429,43 @@ def test_get_columns_out_of_range_indices_give_zeros(torch, psflib, c1, c1_oracl
     assert _rel_err_pos(got[1], c1_oracle[:, 5]) <= LIB_REL
     assert _rel_err_pos(got[4], c1_oracle[:, K - 1]) <= LIB_REL
     lib.close()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("case", ["c1", "odd", "c2"])
+def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
+    """The 16-bit library (built directly from the LDS-staged pair, columns
+    in bracket order where it applies) holds exactly RN16(A32 2^-e_j) 2^e_j of
+    the float32 build's entries A32: the same float32 arithmetic, one
+    rounding.  Checked on every column at 32^2 and on an odd shape whose
+    column count leaves a partial 8-slot group (padding), and on 512 sampled
+    columns at 128^2."""
+    if case == "c1":
+        d = synth.config_inputs(1)
+        cube, radii, N, S = d["cube"], d["radii"], d["N"], d["S"]
+    elif case == "odd":
+        rng = np.random.default_rng(5)
+        cube = (rng.random((5, 33, 33)) ** 3).astype(np.float32)
+        radii, N, S = np.array([0.0, 1.3, 2.0, 3.1, 4.5]), 7, 0.9
+    else:
+        d = synth.config_inputs(2)
+        cube, radii, N, S = d["cube"], d["radii"], d["N"], d["S"]
+    K = N * N
+    cols = np.arange(K) if case != "c2" else np.unique(np.concatenate(
+        [np.random.default_rng(7).choice(K, 500, replace=False), [0, K - 1, K // 2, K // 2 + 64]]))
+    l32 = _lib(torch, psflib, cube, radii, N, S)
+    l16 = _lib(torch, psflib, cube, radii, N, S, storage=fmt)
+    A32 = l32.get_columns(cols).cpu().numpy()
+    e = l16.exponents().cpu().numpy()[cols].astype(np.int64)
+    got = l16.get_columns(cols).cpu().numpy()
+    x = np.ldexp(A32.astype(np.float64), -e[:, None]).astype(np.float32)  # exact
+    if fmt == "fp16":
+        r = x.astype(np.float16).astype(np.float64)
+    else:
+        r = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    want = np.ldexp(r, e[:, None])
+    assert np.array_equal(got.astype(np.float64), want)
+    # column sums are those of the float32 build
+    assert torch.equal(l16.column_sums(), l32.column_sums())
+    l32.close()
+    l16.close()
