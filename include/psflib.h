@@ -87,9 +87,18 @@ typedef enum { PSFLIB_OOB_CLAMP = 0, PSFLIB_OOB_ZERO = 1 } psflib_oob;
  *             value the column can reach, (1-w) max P_k + w max P_{k+1}, land
  *             in [2^14, 2^15) after scaling, so binary16 neither overflows nor
  *             loses the column's faint wings to underflow.  Mantissas are
- *             stored in groups of 8 columns: element (i, j) sits at
- *             ((j/8)*n*n + i)*8 + j%8, so one 16-byte load holds row i of 8
- *             adjacent columns (the operand shape of the matrix cores).
+ *             stored by slot, in groups of 8 slots: element i of slot s sits
+ *             at ((s/8)*n*n + i)*8 + s%8, so one 16-byte load holds row i of
+ *             8 slots (the operand shape of the matrix cores).  Slot s holds
+ *             column perm[s]; the build picks the order so that one workgroup
+ *             can write whole 16-byte groups: for N a multiple of 8 (bilinear,
+ *             no flux rescale, the PSF pair within the LDS) slots 32b + 8k + u
+ *             hold the k-th quarter turn about the star of the u-th of the
+ *             b-th eight base columns (one quadrant, sorted by radial
+ *             bracket); in other such builds the columns sorted by bracket;
+ *             otherwise the natural order (slot j = column j).  The slot
+ *             order is part of the library buffer (see psflib_library_bytes);
+ *             psflib_get_columns reads columns by index whatever the order.
  *             Products accumulate in float32. */
 typedef enum { PSFLIB_FP32 = 0, PSFLIB_BF16_POW2 = 1, PSFLIB_FP16_POW2 = 2 } psflib_storage;
 
@@ -147,8 +156,10 @@ const char* psflib_last_error(void);
 
 /* Bytes the caller must allocate for the library buffer of `desc`: the matrix
  * (n^2 x N^2 entries in the chosen storage, with the 16-bit forms padded to a
- * multiple of 64 columns), followed by the per-column float64 column sums and,
- * for the 16-bit forms, the int32 exponents.  The matrix is the paper's
+ * multiple of 64 slots), followed by the per-column float64 column sums and,
+ * for the 16-bit forms, four int32 arrays: the exponent per column, the
+ * column per slot, the exponent per slot and the slot per column (each part
+ * starting 256-byte aligned).  The matrix is the paper's
  * library of Sec. 3 (one flattened n x n PSF per scene pixel, Eq. (5)), whose
  * stored size Table 2 lists (n^2 N^2 float64 values there).  Host-only: no
  * device call.  Fails with PSFLIB_ERR_SIZE if the size does not fit in size_t

@@ -2,26 +2,35 @@
 //
 // Columns are grouped by their radial bracket k on the device (a counting sort:
 // histogram, scan, scatter), so a workgroup can stage the two sampled PSFs it
-// needs, P_k and P_{k+1}, once in LDS and build up to kLdsCols columns from
-// them.  The pair is stored interleaved (one 8-byte LDS read returns both
-// radial neighbours of a tap) inside a one-pixel zero border, so the bilinear
-// taps of the rotated sample need no per-tap bounds tests.  One wave builds one
-// column, row by row, lane l owning image columns l, l+64, l+128: every store
-// is a coalesced 256-byte run, and the column sum is a wave reduction.
+// needs, P_k and P_{k+1}, once in LDS and build many columns from them.  The
+// pair is stored interleaved (one 8-byte LDS read returns both radial
+// neighbours of a tap) inside a one-pixel zero border, so the bilinear taps of
+// the rotated sample need no per-tap bounds tests.
 //
 // Coordinates follow the oracle's float64 operations exactly (same products,
-// no contraction): per column and lane the products cos*(b-c) and -sin*(b-c)
-// of the lane's image columns are formed once, per row sin*(a-c) and
-// cos*(a-c), and each element adds them.  The fractional offsets and their
-// complements are exact float64 values rounded once to float32; the bilinear
-// weights are their float32 products, the radial blend and the weighted sum
-// are float32 (relative error a few float32 units, as the entries are
-// non-negative combinations).
+// no contraction): per column the products cos*(b-c) and -sin*(b-c) of an
+// image column and sin*(a-c), cos*(a-c) of an image row are formed once and
+// each element adds them.  The fractional offsets and their complements are
+// exact float64 values rounded once to float32; the bilinear weights are their
+// float32 products, the radial blend and the weighted sum are float32
+// (relative error a few float32 units, as the entries are non-negative
+// combinations).
 //
-// The kernel writes float32 columns; the 16-bit storage forms are built into
-// scratch and packed by a second kernel (scale by 2^-e_j, round to nearest
-// even, 8 columns per 16 B), which the gather builds also use when a column
-// needs float32 post-processing (the flux-preserving rescale).
+// Paths, by what fits:
+//  * rotation orbits (the pair fits the LDS): the four quarter turns of a
+//    scene pixel about the star have bitwise-rotated columns, so one wave
+//    forms a base column and writes all four (float32: 16-byte runs straight
+//    from registers; 16-bit: rounded into an LDS tile of 8-slot units, slots
+//    ordered so that a group holds one quarter turn of 8 base columns);
+//  * columns in bracket order (16-bit forms whose scene size is not a multiple
+//    of 8): one wave per column, 16 columns per workgroup, units assembled
+//    from an LDS tile;
+//  * row bands (pairs larger than the LDS, up to 256 x 256): one wave per
+//    column, the pair staged a band of rows at a time.
+// The 16-bit forms of the other builds (and of columns that need float32
+// post-processing, the flux-preserving rescale) are built as float32 columns
+// into scratch and packed by a second kernel (scale by 2^-e_j, round to
+// nearest even, 8 columns per 16 B).
 #include <math.h>
 
 #include "psflib_internal.h"
@@ -685,7 +694,6 @@ __global__ __launch_bounds__(1024) void build_lds16_kernel(const float* __restri
           stuy = g.st * uy;
           ctuy = g.ct * uy;
         }
-        float rowsum = 0.0f;
 #pragma unroll
         for (int v = 0; v < E; ++v) {
           const int b = lane + 64 * v;
@@ -705,7 +713,7 @@ __global__ __launch_bounds__(1024) void build_lds16_kernel(const float* __restri
               val = fmaf(t.fy * t.fx, q11, val);
               val = t.ok ? val : 0.0f;
             }
-            rowsum += val;
+            tsum += (double)val;
             const float x = ldexpf(val, -g.e);  // exact power-of-two scaling
             uint32_t h;
             if constexpr (BF16) {
@@ -718,7 +726,6 @@ __global__ __launch_bounds__(1024) void build_lds16_kernel(const float* __restri
             T[wave * tstride + r * n + b] = (uint16_t)h;
           }
         }
-        tsum += (double)rowsum;
       }
     }
     __syncthreads();
@@ -816,6 +823,479 @@ __global__ __launch_bounds__(256) void zero_pad16_kernel(uint16_t* __restrict__ 
     if (grp * 8 + q >= ncols) dst[q] = 0;
 }
 
+// --------------------------------------------- rotation-orbit builds -----
+// The scene grid (centre ((N-1)/2, (N-1)/2)) and the PSF grid (centre
+// ((n-1)/2, (n-1)/2)) are both invariant under quarter turns.  Turning a
+// scene pixel by 90 degrees about the star maps (x, y) to (-y, x) exactly
+// (index arithmetic: (p, q) -> (q, N-1-p)), so the turned column has
+// cos' = -sin and sin' = cos exactly and the same radius, bracket and
+// weight; its source coordinates at image pixel (b', a') = (N-1-a, b) are
+// the base column's at (b, a) -- the same float64 products added in the
+// other order, which is exact.  Every entry of the turned column is
+// therefore bitwise the base column's at the turned image pixel:
+//   C1[b][n-1-a] = C2[n-1-a][n-1-b] = C3[n-1-b][a] = C0[a][b]
+// for the orbit (j0, j1, j2, j3) of a base column j0 in the quadrant
+// x > 0, y >= 0 (the centre pixel of an odd grid is its own orbit).  The
+// orbit builds compute C0 once and write all four columns: a quarter of the
+// coordinate and interpolation work per stored entry.  Base columns are
+// sorted by bracket (stable), cut into windows of 16; a work item is the run
+// of one bracket inside a window times a range of image rows (so a launch has
+// many more items than compute units), and each wave builds one base column
+// over the item's rows.  Column sums: per (row range, base column) partial
+// sums in float64, added in row-range order by a last kernel.
+
+// quadrant bases p in [N/2, N), q in [(N+1)/2, N); the centre last (odd N)
+struct OrbitGrid {
+  int N, plo, qlo, hq;
+  int64_t n4;      // base columns with a 4-column orbit
+  int64_t nreps;   // n4, plus the centre for odd N
+};
+
+__host__ __device__ inline OrbitGrid orbit_grid(int N) {
+  OrbitGrid o;
+  o.N = N;
+  o.plo = N / 2;
+  o.qlo = (N + 1) / 2;
+  o.hq = N - o.qlo;
+  o.n4 = (int64_t)(N - o.plo) * o.hq;
+  o.nreps = o.n4 + (N & 1);
+  return o;
+}
+
+__device__ __forceinline__ int64_t orbit_base(const OrbitGrid& o, int64_t t) {
+  if (t < o.n4) {
+    const int64_t p = o.plo + t / o.hq, q = o.qlo + t % o.hq;
+    return p * o.N + q;
+  }
+  return (int64_t)(o.N / 2) * o.N + o.N / 2;  // centre
+}
+
+// rotation partners of base column j0 = p N + q (k quarter turns)
+__device__ __forceinline__ int64_t orbit_member(int64_t j0, int N, int k) {
+  const int64_t p = j0 / N, q = j0 - p * N;
+  switch (k) {
+    case 0: return j0;
+    case 1: return q * N + (N - 1 - p);
+    case 2: return (N - 1 - p) * N + (N - 1 - q);
+    default: return (N - 1 - q) * N + p;
+  }
+}
+
+__device__ __forceinline__ bool orbit_is_centre(int64_t j0, int N) {
+  return (N & 1) && j0 == (int64_t)(N / 2) * N + N / 2;
+}
+
+// rows of an image-row range: a multiple of 32, about a quarter of the image
+static inline int orbit_rows_per_range(int n) {
+  const int q = (n + 3) / 4;
+  return ((q + 31) / 32) * 32;
+}
+
+__global__ __launch_bounds__(kSortBlock) void orbit_count_kernel(const ColGeom* __restrict__ geo,
+                                                                 OrbitGrid o, int nb,
+                                                                 int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // nb
+  for (int b = threadIdx.x; b < nb; b += kSortBlock) hist[b] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
+  if (t < o.nreps) atomicAdd(hist + bucket_of(geo, orbit_base(o, t), nb), 1);  // order-free
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kSortBlock) cnt[(int64_t)blockIdx.x * nb + b] = hist[b];
+}
+
+// Stable placement of the base columns (as sort_scatter_kernel); with
+// `perm` set (16-bit forms, N a multiple of 8, no centre) also the slots of
+// every orbit member: base position s in block s/8 of 8 bases, member k in
+// group 4 (s/8) + k, slot 32 (s/8) + 8 k + s%8.
+__global__ __launch_bounds__(kSortBlock) void orbit_scatter_kernel(const ColGeom* __restrict__ geo,
+                                                                   OrbitGrid o, int nb,
+                                                                   const int32_t* __restrict__ first,
+                                                                   int32_t* __restrict__ reps,
+                                                                   int32_t* __restrict__ perm,
+                                                                   int32_t* __restrict__ slot_of,
+                                                                   int32_t* __restrict__ eslot) {
+  extern __shared__ int32_t cursor[];  // nb
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int q = tid; q < nb; q += kSortBlock) cursor[q] = first[(int64_t)blockIdx.x * nb + q];
+  const int64_t t = (int64_t)blockIdx.x * kSortBlock + tid;
+  const bool valid = t < o.nreps;
+  const int64_t j0 = valid ? orbit_base(o, t) : 0;
+  const int b = valid ? bucket_of(geo, j0, nb) : -1;
+  uint64_t todo = __ballot(valid);
+  int rank = 0, count = 0;
+  while (todo) {  // uniform: one pass per bucket present in the wave
+    const int bl = __shfl(b, __builtin_ctzll(todo), 64);
+    const uint64_t m = __ballot(valid && b == bl);
+    if (valid && b == bl) {
+      rank = __popcll(m & ((1ull << lane) - 1ull));
+      count = __popcll(m);
+    }
+    todo &= ~m;
+  }
+  __syncthreads();
+  int pos = 0;
+  for (int w = 0; w < kSortBlock / 64; ++w) {
+    if (wave == w && valid) {
+      pos = cursor[b] + rank;  // every lane reads before the wave's leaders add
+      __builtin_amdgcn_wave_barrier();
+      if (rank == 0) cursor[b] += count;
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  reps[pos] = (int32_t)j0;
+  if (perm) {
+    const int32_t e = geo[j0].e;  // the members share the radius, hence the exponent
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t j = orbit_member(j0, o.N, k);
+      const int32_t slot = (pos / 8) * 32 + 8 * k + pos % 8;
+      perm[slot] = (int32_t)j;
+      slot_of[j] = slot;
+      eslot[slot] = e;
+    }
+  }
+}
+
+// column sums: the partial sums of the row ranges in order, for every member
+__global__ __launch_bounds__(256) void orbit_tau_kernel(const int32_t* __restrict__ reps,
+                                                        const double* __restrict__ part,
+                                                        int nranges, int64_t nreps, int N,
+                                                        double* __restrict__ tau) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nreps) return;
+  double t = 0.0;
+  for (int r = 0; r < nranges; ++r) t += part[(int64_t)r * nreps + s];
+  const int64_t j0 = reps[s];
+  if (orbit_is_centre(j0, N)) {
+    tau[j0] = t;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tau[orbit_member(j0, N, k)] = t;
+}
+
+// the bordered pair (P_k, P_{k+1}) with its zero border, as the LDS build
+__device__ __forceinline__ void stage_pair(float2* __restrict__ P2, const float* __restrict__ cube,
+                                           int bkt, int K, int n, int ls, int64_t M, int tid) {
+  const int np = n + 2;
+  const float* Pk = cube + (int64_t)bkt * M;
+  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+  for (int idx = tid; idx < 4 * np; idx += 1024) {
+    const int side = idx / np, t = idx % np;
+    const int pos = side == 0 ? t : side == 1 ? (np - 1) * ls + t : side == 2 ? t * ls : t * ls + np - 1;
+    P2[pos] = make_float2(0.0f, 0.0f);
+  }
+  if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(cube) & 15) == 0) {
+    const int nq = n >> 2;
+    for (int q = tid; q < n * nq; q += 1024) {
+      const int rr = q / nq, cc = 4 * (q - rr * nq);
+      const f32x4 a = *reinterpret_cast<const f32x4*>(Pk + rr * n + cc);
+      const f32x4 b = Pk1 ? *reinterpret_cast<const f32x4*>(Pk1 + rr * n + cc) : (f32x4){0.f, 0.f, 0.f, 0.f};
+      float2* dst = P2 + (rr + 1) * ls + cc + 1;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[e] = make_float2(a[e], b[e]);
+    }
+  } else {
+    for (int q = tid; q < n * n; q += 1024) {
+      const int rr = q / n, cc = q - rr * n;
+      P2[(rr + 1) * ls + cc + 1] = make_float2(Pk[q], Pk1 ? Pk1[q] : 0.0f);
+    }
+  }
+}
+
+// One element of the base column (the LDS build's arithmetic).
+__device__ __forceinline__ float orbit_value(const float2* __restrict__ P2, double ctux, double mstux,
+                                             double stuy, double ctuy, double c, int n, int ls,
+                                             float wk0, float wk1) {
+  const Tap t = tap_coords(ctux, mstux, stuy, ctuy, c, n, ls);
+  const float2 p00 = P2[t.idx], p01 = P2[t.idx + 1];
+  const float2 p10 = P2[t.idx + ls], p11 = P2[t.idx + ls + 1];
+  const float q00 = fmaf(wk1, p00.y, wk0 * p00.x);
+  const float q01 = fmaf(wk1, p01.y, wk0 * p01.x);
+  const float q10 = fmaf(wk1, p10.y, wk0 * p10.x);
+  const float q11 = fmaf(wk1, p11.y, wk0 * p11.x);
+  float val = (t.gy * t.gx) * q00;
+  val = fmaf(t.gy * t.fx, q01, val);
+  val = fmaf(t.fy * t.gx, q10, val);
+  val = fmaf(t.fy * t.fx, q11, val);
+  return t.ok ? val : 0.0f;
+}
+
+// Float32 orbit build.  Wave = base column over the item's rows in tiles of
+// 32 x 32 pixels; lane (i, k) = (lane / 8, lane % 8) forms the 4 x 4 block
+// at rows 4i.., columns 4k.. of a tile.  Each lane then holds four runs of
+// four entries for every member (C0, C2 along rows; C1, C3 along the base
+// column's image columns), so every store is 16 bytes and each store
+// instruction fills eight whole 128-byte lines of one member (VEC: n % 4 ==
+// 0, every 4 x 4 block is wholly inside or outside the image, runs 16-byte
+// aligned; otherwise scalar stores).
+template <bool VEC>
+__global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restrict__ cube, int K,
+                                                           const ColGeom* __restrict__ geo,
+                                                           const int32_t* __restrict__ reps,
+                                                           const int4* __restrict__ items,
+                                                           const int32_t* __restrict__ nitems,
+                                                           int nb, int n, int ls, int N, int64_t M,
+                                                           int rpr, int64_t nreps,
+                                                           float* __restrict__ A,
+                                                           double* __restrict__ part) {
+  extern __shared__ float2 P2[];
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  if (!zero_bucket) stage_pair(P2, cube, bkt, K, n, ls, M, tid);
+  __syncthreads();
+  const int sp = w0 + wave;
+  if (sp < first || sp >= first + len) return;  // uniform per wave; no barrier below
+  const int64_t j0 = reps[sp];
+  const bool centre = orbit_is_centre(j0, N);
+  float* C0 = A + j0 * M;
+  float* C1 = A + orbit_member(j0, N, 1) * M;
+  float* C2 = A + orbit_member(j0, N, 2) * M;
+  float* C3 = A + orbit_member(j0, N, 3) * M;
+  if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
+    for (int x = lane; x < (rb - ra) * n; x += 64) {
+      const int64_t p = (int64_t)ra * n + x;
+      __builtin_nontemporal_store(0.0f, C0 + p);
+      if (!centre) {
+        __builtin_nontemporal_store(0.0f, C1 + p);
+        __builtin_nontemporal_store(0.0f, C2 + p);
+        __builtin_nontemporal_store(0.0f, C3 + p);
+      }
+    }
+    if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = 0.0;
+    return;
+  }
+  const ColGeom g = geo[j0];
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const int li = lane >> 3, lk = lane & 7;
+  double tsum = 0.0;
+  for (int a0 = ra; a0 < rb; a0 += 32) {
+    const int ab = a0 + 4 * li;
+    if (ab >= rb) continue;  // VEC: the whole block is below the range
+    for (int b0 = 0; b0 < n; b0 += 32) {
+      const int bb = b0 + 4 * lk;
+      if (bb >= n) continue;
+      double ctux[4], mstux[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma clang fp contract(off)
+        const double ux = (double)(bb + q) - c;
+        ctux[q] = g.ct * ux;
+        mstux[q] = (-g.st) * ux;
+      }
+      float x[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = ab + r;
+        double stuy, ctuy;
+        {
+#pragma clang fp contract(off)
+          const double uy = (double)a - c;
+          stuy = g.st * uy;
+          ctuy = g.ct * uy;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[r][q] = 0.0f;
+          if (VEC || (a < rb && bb + q < n)) {
+            x[r][q] = orbit_value(P2, ctux[q], mstux[q], stuy, ctuy, c, n, ls, wk0, wk1);
+            tsum += (double)x[r][q];
+          }
+          if (q == 1) __builtin_amdgcn_sched_barrier(0);  // two elements in flight
+        }
+        if constexpr (VEC) {  // the row's runs of C0 and C2
+          __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
+                                      reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
+          if (!centre)
+            __builtin_nontemporal_store((f32x4){x[r][3], x[r][2], x[r][1], x[r][0]},
+                                        reinterpret_cast<f32x4*>(C2 + (int64_t)(n - 1 - a) * n + (n - 4 - bb)));
+        }
+        // one row of the block at a time: bounds the live coordinate temporaries
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (VEC) {
+        if (!centre) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = bb + q;
+            __builtin_nontemporal_store((f32x4){x[3][q], x[2][q], x[1][q], x[0][q]},
+                                        reinterpret_cast<f32x4*>(C1 + (int64_t)b * n + (n - 4 - ab)));
+            __builtin_nontemporal_store((f32x4){x[0][q], x[1][q], x[2][q], x[3][q]},
+                                        reinterpret_cast<f32x4*>(C3 + (int64_t)(n - 1 - b) * n + ab));
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int a = ab + r, b = bb + q;
+            if (a >= rb || b >= n) continue;
+            __builtin_nontemporal_store(x[r][q], C0 + (int64_t)a * n + b);
+            if (centre) continue;
+            __builtin_nontemporal_store(x[r][q], C1 + (int64_t)b * n + (n - 1 - a));
+            __builtin_nontemporal_store(x[r][q], C2 + (int64_t)(n - 1 - a) * n + (n - 1 - b));
+            __builtin_nontemporal_store(x[r][q], C3 + (int64_t)(n - 1 - b) * n + a);
+          }
+      }
+    }
+  }
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
+// 16-bit orbit build (N a multiple of 8: no centre, whole blocks of 8 bases).
+// A window of 16 bases is two blocks; block h's member k is group
+// 4 (w0/8 + h) + k, whose unit at an image pixel holds the 8 bases' member
+// values there.  Per step every wave forms a 16 x 32 pixel tile of its base
+// column (lane (i, k): rows 2i, 2i+1, columns 4k..4k+3), rounds the values
+// into an LDS tile [2][16][33][8] (unit-major: the 8 bases of a block and
+// pixel are one 16-byte LDS word; one unit of padding per row keeps the
+// column-wise reads conflict-free); then each unit is read once per store
+// pattern and written to two groups: along rows for members 0 and 2 (runs of
+// 32 units in rows a and n-1-a), along columns for members 1 and 3 (runs of
+// 16 units in rows b and n-1-b).  Slots of a block outside the item (the
+// block straddles two brackets) are left to the other item: 2-byte stores.
+template <bool BF16>
+__global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __restrict__ cube, int K,
+                                                             const ColGeom* __restrict__ geo,
+                                                             const int32_t* __restrict__ reps,
+                                                             const int4* __restrict__ items,
+                                                             const int32_t* __restrict__ nitems,
+                                                             int nb, int n, int ls, int64_t M,
+                                                             int rpr, int64_t nreps,
+                                                             uint16_t* __restrict__ Mh,
+                                                             double* __restrict__ part) {
+  constexpr int TA = 16, TB = 32, TP = TB + 1;
+  extern __shared__ float2 P2[];  // bordered pair, then the tile
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  uint16_t* tile = reinterpret_cast<uint16_t*>(P2 + ((((size_t)(n + 2) * ls) + 1) & ~(size_t)1));
+  if (!zero_bucket) stage_pair(P2, cube, bkt, K, n, ls, M, tid);
+  const int sp = w0 + wave;
+  const bool live = sp >= first && sp < first + len;  // uniform per wave
+  const int h = wave >> 3, u = wave & 7;
+  ColGeom g;
+  g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
+  if (live) g = geo[reps[sp]];
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const int64_t G0 = (int64_t)(w0 / 8) * 4;
+  int lo[2], hi[2];  // the item's slots of each block, relative to the block
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int s0 = w0 + 8 * q;
+    lo[q] = (first > s0) ? first - s0 : 0;
+    hi[q] = (first + len < s0 + 8) ? first + len - s0 : 8;
+  }
+  const int li = lane >> 3, lk = lane & 7;
+  double tsum = 0.0;
+  for (int a0 = ra; a0 < rb; a0 += TA) {
+    for (int b0 = 0; b0 < n; b0 += TB) {
+      __syncthreads();  // the pair is staged; the previous tile has been stored
+      if (live) {
+        const int ta = 2 * li, tb = 4 * lk;  // the lane's block inside the tile
+        double ctux[4], mstux[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma clang fp contract(off)
+          const double ux = (double)(b0 + tb + q) - c;
+          ctux[q] = g.ct * ux;
+          mstux[q] = (-g.st) * ux;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int a = a0 + ta + r;
+          if (a >= rb) continue;
+          double stuy, ctuy;
+          {
+#pragma clang fp contract(off)
+            const double uy = (double)a - c;
+            stuy = g.st * uy;
+            ctuy = g.ct * uy;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (b0 + tb + q >= n) continue;
+            const float val = zero_bucket
+                                  ? 0.0f
+                                  : orbit_value(P2, ctux[q], mstux[q], stuy, ctuy, c, n, ls, wk0, wk1);
+            tsum += (double)val;
+            const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
+            uint32_t hv;
+            if constexpr (BF16) {
+              uint32_t w = __float_as_uint(xs);
+              w += 0x7FFFu + ((w >> 16) & 1u);  // finite: round to nearest, ties to even
+              hv = w >> 16;
+            } else {
+              hv = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)xs);
+            }
+            tile[((h * TA + ta + r) * TP + tb + q) * 8 + u] = (uint16_t)hv;
+          }
+        }
+      }
+      __syncthreads();
+      // one unit per thread and pattern: 2 blocks x 16 rows x 32 columns
+      {
+        const int q = tid >> 9, rem = tid & 511;
+        const bool any = lo[q] < hi[q];
+        // members 0 and 2: columns fastest
+        {
+          const int r = rem >> 5, cb = rem & 31, a = a0 + r, b = b0 + cb;
+          if (any && a < rb && b < n) {
+            const uint16_t* src = tile + ((q * TA + r) * TP + cb) * 8;
+            uint16_t* d0 = Mh + ((G0 + 4 * q + 0) * M + (int64_t)a * n + b) * 8;
+            uint16_t* d2 = Mh + ((G0 + 4 * q + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
+            if (lo[q] == 0 && hi[q] == 8) {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d0));
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d2));
+            } else {
+              for (int s = lo[q]; s < hi[q]; ++s) {
+                d0[s] = src[s];
+                d2[s] = src[s];
+              }
+            }
+          }
+        }
+        // members 1 and 3: rows fastest
+        {
+          const int cb = rem >> 4, r = rem & 15, a = a0 + r, b = b0 + cb;
+          if (any && a < rb && b < n) {
+            const uint16_t* src = tile + ((q * TA + r) * TP + cb) * 8;
+            uint16_t* d1 = Mh + ((G0 + 4 * q + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
+            uint16_t* d3 = Mh + ((G0 + 4 * q + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
+            if (lo[q] == 0 && hi[q] == 8) {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d1));
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d3));
+            } else {
+              for (int s = lo[q]; s < hi[q]; ++s) {
+                d1[s] = src[s];
+                d3[s] = src[s];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!live) return;
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
 // ------------------------------------------------------------- launch -----
 static int lds_e(int n) { return (n + 63) / 64; }
 
@@ -861,7 +1341,7 @@ size_t bucket_scratch_bytes(int K, int64_t ncols) {
   return b;
 }
 
-size_t build_lds_scratch_bytes(int K, int64_t ncols) { return bucket_scratch_bytes(K, ncols); }
+
 
 hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* scratch,
                               BucketPlan* plan, hipStream_t s) {
@@ -982,8 +1462,14 @@ hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGe
   return e;
 }
 
-hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
-                            int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s) {
+static bool build_orbit_supported(int n, int K, int N);
+static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                     int64_t M, float* A32, double* tau, void* scratch, hipStream_t s);
+
+hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int N, int64_t M,
+                            float* A32, double* tau, void* scratch, hipStream_t s) {
+  if (build_orbit_supported(n, K, N)) return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, s);
+  const int64_t ncols = (int64_t)N * N;
   BucketPlan bp;
   hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
@@ -1029,6 +1515,132 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+// ------------------------------------------------- orbit launches -----
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct OrbitPlan {
+  OrbitGrid o;
+  int nb, rpr, nranges;
+  int64_t nblk, items_max;
+  int32_t* cnt;
+  int4* items;
+  int32_t* nitems;
+  int32_t* reps;
+  double* part;
+};
+
+static OrbitPlan orbit_plan(int K, int N, int n, void* scratch) {
+  OrbitPlan pl;
+  pl.o = orbit_grid(N);
+  pl.nb = nbuckets(K);
+  pl.rpr = orbit_rows_per_range(n);
+  pl.nranges = (n + pl.rpr - 1) / pl.rpr;
+  pl.nblk = (pl.o.nreps + kSortBlock - 1) / kSortBlock;
+  pl.items_max = (pl.o.nreps + 15) / 16 + 2 * (int64_t)pl.nb + 1;
+  char* p = reinterpret_cast<char*>(scratch);
+  pl.cnt = reinterpret_cast<int32_t*>(p);
+  p += al256((size_t)pl.nblk * pl.nb * 4);
+  pl.items = reinterpret_cast<int4*>(p);
+  pl.nitems = reinterpret_cast<int32_t*>(pl.items + pl.items_max);
+  p += al256((size_t)pl.items_max * 16 + 16);
+  pl.reps = reinterpret_cast<int32_t*>(p);
+  p += al256((size_t)pl.o.nreps * 4);
+  pl.part = reinterpret_cast<double*>(p);
+  return pl;
+}
+
+size_t build_orbit_scratch_bytes(int K, int N, int n) {
+  const OrbitPlan pl = orbit_plan(K, N, n, nullptr);
+  return al256((size_t)pl.nblk * pl.nb * 4) + al256((size_t)pl.items_max * 16 + 16) +
+         al256((size_t)pl.o.nreps * 4) + al256((size_t)pl.nranges * pl.o.nreps * 8);
+}
+
+static bool orbit_sort_fits(int K, int N) {
+  const OrbitGrid o = orbit_grid(N);
+  const int64_t nblk = (o.nreps + kSortBlock - 1) / kSortBlock;
+  return K <= kLdsMaxBuckets - 1 && nblk * nbuckets(K) <= ((int64_t)1 << 24) &&
+         (int64_t)N * N < ((int64_t)1 << 31);
+}
+
+// counting sort of the base columns by bracket, and the work items
+static hipError_t orbit_sort(const ColGeom* geo, const OrbitPlan& pl, int32_t* perm,
+                             int32_t* slot_of, int32_t* eslot, hipStream_t s) {
+  orbit_count_kernel<<<(unsigned)pl.nblk, kSortBlock, (size_t)pl.nb * 4, s>>>(geo, pl.o, pl.nb, pl.cnt);
+  sort_scan_kernel<<<1, 1024, 0, s>>>(pl.cnt, pl.nblk, pl.nb, pl.items, pl.nitems);
+  orbit_scatter_kernel<<<(unsigned)pl.nblk, kSortBlock, (size_t)pl.nb * 4, s>>>(
+      geo, pl.o, pl.nb, pl.cnt, pl.reps, perm, slot_of, eslot);
+  return hipGetLastError();
+}
+
+static hipError_t orbit_finish(const OrbitPlan& pl, double* tau, hipStream_t s) {
+  orbit_tau_kernel<<<(unsigned)((pl.o.nreps + 255) / 256), 256, 0, s>>>(pl.reps, pl.part, pl.nranges,
+                                                                       pl.o.nreps, pl.o.N, tau);
+  return hipGetLastError();
+}
+
+static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                     int64_t M, float* A32, double* tau, void* scratch, hipStream_t s) {
+  const OrbitPlan pl = orbit_plan(K, N, n, scratch);
+  hipError_t e = orbit_sort(geo, pl, nullptr, nullptr, nullptr, s);
+  if (e != hipSuccess) return e;
+  const int ls = lds_stride(n);
+  const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
+  const bool vec = (n % 4) == 0;
+  const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, ls, N, M,
+                                 pl.rpr, pl.o.nreps, A32, pl.part);
+    return hipGetLastError();
+  };
+  e = vec ? launch(build_orbit_kernel<true>) : launch(build_orbit_kernel<false>);
+  if (e != hipSuccess) return e;
+  return orbit_finish(pl, tau, s);
+}
+
+// 16-bit orbit build: the pair (ending 16-byte aligned), then the 2 x 16 x 33 unit tile
+static size_t orbit16_pair_bytes(int n) {
+  return (((size_t)(n + 2) * lds_stride(n) * sizeof(float2)) + 15) & ~(size_t)15;
+}
+static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)2 * 16 * 33 * 16; }
+
+bool build_orbit16_supported(int n, int K, int N) {
+  return N % 8 == 0 && pair_fits_lds(n) && orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes &&
+         orbit_sort_fits(K, N);
+}
+
+static bool build_orbit_supported(int n, int K, int N) { return pair_fits_lds(n) && orbit_sort_fits(K, N); }
+
+size_t build_lds_scratch_bytes(int K, int N, int n) {
+  return build_orbit_supported(n, K, N) ? build_orbit_scratch_bytes(K, N, n)
+                                        : bucket_scratch_bytes(K, (int64_t)N * N);
+}
+
+hipError_t launch_build_orbit16(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                                int N, int64_t M, int32_t* perm, int32_t* eslot, int32_t* slot_of,
+                                void* lib, double* tau, void* scratch, hipStream_t s) {
+  const OrbitPlan pl = orbit_plan(K, N, n, scratch);
+  hipError_t e = orbit_sort(geo, pl, perm, slot_of, eslot, s);
+  if (e != hipSuccess) return e;
+  const int ls = lds_stride(n);
+  const size_t lds = orbit16_lds_bytes(n);
+  uint16_t* Mh = reinterpret_cast<uint16_t*>(lib);
+  const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, ls, M,
+                                 pl.rpr, pl.o.nreps, Mh, pl.part);
+    return hipGetLastError();
+  };
+  e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_kernel<true>) : launch(build_orbit16_kernel<false>);
+  if (e != hipSuccess) return e;
+  return orbit_finish(pl, tau, s);
 }
 
 }  // namespace psflib

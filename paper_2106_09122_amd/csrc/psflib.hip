@@ -334,11 +334,14 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // float32 columns and a packing pass (natural order)
   const bool direct16 = storage != PSFLIB_FP32 && !cubic && !flux && lds &&
                         psflib::build_lds16_supported(desc->n, K, L.ncols);
+  const bool orbit16 = direct16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
-      spline_bytes + align256(direct16 ? psflib::build_lds16_scratch_bytes(K, L.ncols)
-                              : lds    ? psflib::bucket_scratch_bytes(K, L.ncols)
+      spline_bytes + align256(orbit16    ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
+                              : direct16 ? psflib::build_lds16_scratch_bytes(K, L.ncols)
+                              : cubic && lds ? psflib::build_cubic_lds_scratch_bytes(K, L.ncols)
+                              : lds    ? psflib::build_lds_scratch_bytes(K, desc->N, desc->n)
                               : cubic  ? 0
                                        : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
   const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
@@ -388,6 +391,13 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
     e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
                                    desc->n, L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "cubic build kernel");
+  } else if (orbit16) {
+    e = psflib::launch_build_orbit16(storage, d_cube, K, h->geo, desc->n, desc->N, L.M,
+                                     reinterpret_cast<int32_t*>(lib + L.off_perm),
+                                     reinterpret_cast<int32_t*>(lib + L.off_eslot),
+                                     reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
+                                     path_tmp, s);
+    if (e != hipSuccess) return bail(e, "16-bit orbit build kernels");
   } else if (direct16) {
     e = psflib::launch_build_lds16(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
                                    exps, reinterpret_cast<int32_t*>(lib + L.off_perm),
@@ -396,7 +406,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                    path_tmp, s);
     if (e != hipSuccess) return bail(e, "16-bit LDS build kernels");
   } else if (lds) {
-    e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, L.M, L.ncols,
+    e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, desc->N, L.M,
                                  reinterpret_cast<float*>(bdst), tau, path_tmp, s);
     if (e != hipSuccess) return bail(e, "LDS build kernels");
   } else {

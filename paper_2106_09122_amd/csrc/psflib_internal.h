@@ -153,7 +153,8 @@ hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo,
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K);
-size_t build_lds_scratch_bytes(int K, int64_t ncols);
+// scratch of launch_build_lds for an N x N scene
+size_t build_lds_scratch_bytes(int K, int N, int n);
 // Columns grouped by radial bracket on the device: order[] lists the columns
 // bucket by bucket (bucket k = bracket k, the last bucket = zero columns);
 // items[t] = (bucket, first position in order, length <= kLdsCols, 0) for
@@ -168,9 +169,18 @@ struct BucketPlan {
 size_t bucket_scratch_bytes(int K, int64_t ncols);
 hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* scratch,
                               BucketPlan* plan, hipStream_t s);
-// float32 columns (A32[j*M + i]) and their float64 sums
-hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int64_t M,
-                            int64_t ncols, float* A32, double* tau, void* scratch, hipStream_t s);
+// float32 columns (A32[j*M + i]) and their float64 sums: the rotation-orbit
+// build when the pair fits the LDS, else the banded build
+hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int N, int64_t M,
+                            float* A32, double* tau, void* scratch, hipStream_t s);
+// 16-bit storage built by rotation orbits (N % 8 == 0, pair and tile in LDS):
+// slot 32 (s/8) + 8 k + s%8 holds member k of the s-th base column in
+// bracket order (perm, slot_of, eslot written here); column sums in tau.
+bool build_orbit16_supported(int n, int K, int N);
+size_t build_orbit_scratch_bytes(int K, int N, int n);
+hipError_t launch_build_orbit16(int storage, const float* cube, int K, const ColGeom* geo, int n,
+                                int N, int64_t M, int32_t* perm, int32_t* eslot, int32_t* slot_of,
+                                void* lib, double* tau, void* scratch, hipStream_t s);
 // 16-bit storage built directly (bilinear rotation, no column rescale, the
 // pair and a 16-bit tile in LDS): columns ordered by radial bracket (perm,
 // slot_of, eslot written here, exps per column given), mantissas written as
