@@ -391,8 +391,9 @@ def main():
             rows[f"grouped_{fmt}"] = {"ms": t_g, "timing": "median of 10, MALL flushed before each",
                                       "scenes_per_s": len(scene_lib) / (t_g * 1e-3),
                                       "GB_per_s": nbytes / (t_g * 1e-3) / 1e9,
+                                      "frac_hbm": nbytes / (t_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                       "libraries": len(used), "scenes": len(scene_lib),
-                                      "chunk": gp.chunk()[0]}
+                                      "tile_shape": gp.shape()}
             gp.close()
             for Lb in Ls:
                 Lb.close()

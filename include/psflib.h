@@ -272,8 +272,9 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
  * complex scenes at once).  A plan lists work tiles over every (library,
  * group of up to 16 of its scenes, row block, column chunk); a persistent
  * kernel streams each library once per scene group from HBM and multiplies
- * it with the group's scenes on the matrix cores; a second kernel adds the
- * chunk partials in a fixed order (bitwise reproducible).  The scene groups
+ * it with the group's scenes on the matrix cores; when a library is cut into
+ * several chunks a second kernel adds the chunk partials in a fixed order
+ * (bitwise reproducible).  The scene groups
  * are packed into the matrix-core operand at the start of every run.  All
  * launches are captured in a HIP graph.
  *   h_libs          host array of nlibs built handles; all share one storage
@@ -283,10 +284,12 @@ psflib_status psflib_get_geometry(const psflib_handle* h, double* d_geom, int32_
  *                   of its library L; h_images: B device pointers, image b
  *                   float32 [n_L^2].  The pointers are fixed into the plan:
  *                   refill the buffers and run again; do not free them first.
- *   autotune        non-zero: time each candidate chunk length on this plan
- *                   (running the graph, which writes the images) and keep the
- *                   fastest; the choice is cached per plan shape for the
- *                   process.  Zero: use the cached or default choice.
+ *   autotune        non-zero: time each candidate tile shape on this plan
+ *                   (rows per item and chunk length, or whole columns per
+ *                   item; running the graph, which writes the images) and keep
+ *                   the fastest; the choice is cached per plan signature (the
+ *                   storage and every scene's library size) for the process.
+ *                   Zero: use the cached or default choice.
  * Synchronises `stream` (libraries built on it must be complete) and takes
  * the plan's device tables and partials from the library's device pool.  FP32 plans
  * take libraries with n*n <= 2^25 (n <= 5792; PSFLIB_ERR_UNSUPPORTED beyond). */
@@ -299,9 +302,25 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
 /* Run the plan: one hipGraphLaunch on `stream`. */
 psflib_status psflib_grouped_run(const psflib_grouped* g, void* stream);
 
-/* The plan's chunk length (columns for FP32, 8-column groups for 16-bit) and,
- * if it was autotuned, the measured time of one run in ms (else 0). */
+/* The plan's chunk length (columns for FP32, 8-column groups for 16-bit; 0:
+ * each item covers every column of its library) and, if it was autotuned, the
+ * measured time of one run in ms (else 0). */
 psflib_status psflib_grouped_chunk(const psflib_grouped* g, int64_t* chunk, float* tuned_ms);
+
+/* The plan's tile shape: chunk length as psflib_grouped_chunk, rows per work
+ * item (`rows` may be NULL; FP32 plans use 256, 16-bit plans 256, 128 or 64)
+ * and the autotuned time (`tuned_ms` may be NULL). */
+psflib_status psflib_grouped_shape(const psflib_grouped* g, int64_t* chunk, int32_t* rows,
+                                   float* tuned_ms);
+
+/* Rebuild the plan with a given tile shape instead of the tuned one: `chunk`
+ * 8-column groups (16-bit, a multiple of 8) or columns (FP32, a multiple of
+ * 16) per item, 0 for every column of the library in one item; `rows` per
+ * item, 64, 128 or 256 for 16-bit plans and 256 for FP32 (else
+ * PSFLIB_ERR_INVALID_ARG).  Waits for the plan's
+ * earlier runs; synchronises `stream`.  The images are unchanged until the
+ * next run. */
+psflib_status psflib_grouped_set_shape(psflib_grouped* g, int64_t chunk, int32_t rows, void* stream);
 
 /* Free the plan.  Waits on the host for the plan's own launches (events
  * recorded by psflib_grouped_run on each stream it ran on), not for other

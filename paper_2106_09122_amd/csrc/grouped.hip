@@ -10,11 +10,15 @@
 // Work items are (library, scene group of <= 16, row block, column chunk)
 // tiles, listed on the host when the plan is made.  A persistent grid
 // walks the list; each workgroup streams its tile of the library once and
-// multiplies it with every scene of the group, writing partial images; a
-// second kernel adds the partials of each (scene, row block) in chunk order
-// (bitwise reproducible).  The chunk length is chosen by timing the candidate
-// shapes on the plan itself (psflib_grouped_create with autotune), and the
-// choice is cached per plan signature for the process.
+// multiplies it with every scene of the group.  An item that covers every
+// column of its library writes the images directly; otherwise items write
+// partial images and a second kernel adds the partials of each (scene, row
+// block) in chunk order (bitwise reproducible).  The tile shape -- rows per
+// item (16-bit: 256, 128 or 64, the workgroup's four waves splitting the
+// columns of the smaller tiles and adding their sums through LDS) and chunk
+// length (or whole columns) -- is chosen by timing the candidate shapes on the
+// plan itself (psflib_grouped_create with autotune), and the choice is cached
+// per plan signature for the process.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -41,6 +45,8 @@ struct GItem {
   int32_t scene0, nscenes;  // scenes (index into the plan's scene table)
   int64_t part;           // float offset of this item's partials: [scenes per pass][rows]
   int64_t bpk;            // packed scene operand of the scene group (16-byte units)
+  int32_t direct;         // the item covers every column: images written directly, no partials
+  int32_t pad;
 };
 
 // A scene slot of the plan: its values and its library's column exponents.
@@ -85,7 +91,8 @@ constexpr int kGrpRing = 2;
 
 template <bool VEC>
 __device__ __forceinline__ void grouped_f32_item(const GItem& w, const f32x4* __restrict__ zpk,
-                                                 int lane, int wave, float* __restrict__ part) {
+                                                 int lane, int wave, float* __restrict__ part,
+                                                 float* const* __restrict__ images) {
   const int64_t m0 = w.row0 + 64 * wave;
   if (m0 >= w.M) return;  // no barriers: a wave past the image leaves at once
   const int n = lane & 15, q = lane >> 4;
@@ -148,26 +155,43 @@ __device__ __forceinline__ void grouped_f32_item(const GItem& w, const f32x4* __
   }
   // lane holds scene n and MFMA rows 4q + r, i.e. image rows m0 + 16q + 4r + t
   if (n < w.nscenes) {
-    float* dst = part + w.part + (int64_t)n * kGrpThreads + 64 * wave + 16 * q;
+    if (w.direct) {
+      float* img = images[w.scene0 + n];
+      const int64_t rr = m0 + 16 * q;
+      const bool whole = VEC && rr + 16 <= w.M;  // images are 16-byte aligned; M % 4 == 0
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const f32x4 v = {tot[0][r], tot[1][r], tot[2][r], tot[3][r]};
-      *reinterpret_cast<f32x4*>(dst + 4 * r) = v;
+      for (int r = 0; r < 4; ++r) {
+        const f32x4 v = {tot[0][r], tot[1][r], tot[2][r], tot[3][r]};
+        if (whole) {
+          *reinterpret_cast<f32x4*>(img + rr + 4 * r) = v;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (rr + 4 * r + t < w.M) img[rr + 4 * r + t] = v[t];
+        }
+      }
+    } else {
+      float* dst = part + w.part + (int64_t)n * kGrpThreads + 64 * wave + 16 * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const f32x4 v = {tot[0][r], tot[1][r], tot[2][r], tot[3][r]};
+        *reinterpret_cast<f32x4*>(dst + 4 * r) = v;
+      }
     }
   }
 }
 
 __global__ __launch_bounds__(kGrpThreads) void grouped_f32_kernel(
     const GItem* __restrict__ items, int64_t nitems, const f32x4* __restrict__ zpk,
-    float* __restrict__ part) {
+    float* __restrict__ part, float* const* __restrict__ images) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem w = items[it];
     if ((w.M & 3) == 0)
-      grouped_f32_item<true>(w, zpk, lane, wave, part);
+      grouped_f32_item<true>(w, zpk, lane, wave, part, images);
     else
-      grouped_f32_item<false>(w, zpk, lane, wave, part);
+      grouped_f32_item<false>(w, zpk, lane, wave, part, images);
   }
 }
 
@@ -271,39 +295,48 @@ __device__ __forceinline__ float g16_value(uint16_t h) {
     return (float)__builtin_bit_cast(_Float16, h);
 }
 
-// Packed operand: thread = (scene group, 8-column group g, scene slot r);
-// writes column r (hi parts) and 16 + r (lo parts) of group g, 16 bytes each
-// (zeros for slots past the group's scenes).  Grid: one row of workgroups per
-// scene group, (group, slot) pairs strided across the row.
+// Packed operand: thread = (scene group, 8-column group g, quarter r4 of the
+// scene slots); loads the group's 8 column indices and exponents once and
+// writes columns r (hi parts) and 16 + r (lo parts) of group g for its four
+// slots r = 4 r4 .. 4 r4 + 3, 16 bytes each (zeros for slots past the group's
+// scenes).  Grid: one row of workgroups per scene group, (group, quarter)
+// pairs strided across the row.
 template <bool BF16>
 __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restrict__ packs,
                                                            const float* const* __restrict__ scenes,
                                                            const int32_t* __restrict__ fexp,
                                                            u32x4* __restrict__ bpk) {
   const GPack pk = packs[blockIdx.x];
-  for (int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x; t < pk.ngroups * kGrpScenes;
+  for (int64_t t = (int64_t)blockIdx.y * 256 + threadIdx.x; t < pk.ngroups * 4;
        t += (int64_t)gridDim.y * 256) {
-    const int64_t g = t / kGrpScenes;
-    const int r = (int)(t - g * kGrpScenes);
+    const int64_t g = t >> 2;
+    const int r4 = (int)(t & 3);
     u32x4* dst = bpk + pk.bpk + g * 32;
-    uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
-    if (r < pk.nscenes) {
-      const float* z = scenes[pk.slot0 + r];
-      const int f = fexp[pk.slot0 + r];
+    int32_t jj[8], es[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t slot = g * 8 + u;
-        const int32_t j = pk.perm[slot];
-        float v = 0.0f;
-        if (j >= 0) v = ldexpf(z[j], pk.eslot[slot] + f);
-        const uint16_t h = g16_round<BF16>(v);
-        const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
-        hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
-        lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
-      }
+    for (int u = 0; u < 8; ++u) {
+      jj[u] = pk.perm[g * 8 + u];
+      es[u] = pk.eslot[g * 8 + u];
     }
-    dst[r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
-    dst[16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = 4 * r4 + rr;
+      uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
+      if (r < pk.nscenes) {
+        const float* z = scenes[pk.slot0 + r];
+        const int f = fexp[pk.slot0 + r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float v = (jj[u] >= 0) ? ldexpf(z[jj[u]], es[u] + f) : 0.0f;
+          const uint16_t h = g16_round<BF16>(v);
+          const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
+          hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
+          lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
+        }
+      }
+      dst[r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
+      dst[16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
+    }
   }
 }
 
@@ -319,19 +352,33 @@ __device__ __forceinline__ f32x16 g16_mfma(const u32x4 a, const u32x4 b, const f
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-template <bool BF16>
+// KS = waves splitting an item's columns: an item is 256 / KS rows, row wave
+// rw = wave % (4 / KS) takes 64 of them and split ks = wave / (4 / KS) a
+// contiguous run of the item's K steps (whole blocks of 4); the splits' sums
+// go through LDS and are added in split order by split 0, which writes the
+// item's rows.
+template <bool BF16, int KS>
 __global__ __launch_bounds__(kGrpThreads) void grouped_h16_kernel(
     const GItem* __restrict__ items, int64_t nitems, const u32x4* __restrict__ bpk,
-    const int32_t* __restrict__ fexp, float* __restrict__ part) {
+    const int32_t* __restrict__ fexp, float* __restrict__ part, float* const* __restrict__ images) {
+  constexpr int RW = 4 / KS;   // row waves
+  constexpr int R = 64 * RW;   // rows per item
+  __shared__ f32x16 red[(KS > 1) ? (KS - 1) * RW * 2 : 1][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rw = wave % RW, ks = wave / RW;
   const int half = lane >> 5;  // which group of a 16-wide K step this lane feeds
   const u32x4 z4 = {0u, 0u, 0u, 0u};
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GItem w = items[it];
     const u32x4* Mp = reinterpret_cast<const u32x4*>(w.A);
     const int ng = (int)(w.j1 - w.j0);  // even (chunks and libraries are whole 8-group blocks)
+    const int nsteps = ng / 2;
+    const int nq = (nsteps + 3) / 4;  // blocks of 4 K steps, shared out among the splits
+    const int sa = 4 * ((nq * ks) / KS);
+    const int sb = (4 * ((nq * (ks + 1)) / KS) < nsteps) ? 4 * ((nq * (ks + 1)) / KS) : nsteps;
+    const int gend = 2 * sb;
     // this lane's library rows; rows past M read row M-1 (never stored)
-    int64_t r0 = w.row0 + 64 * wave + (lane & 31), r1 = r0 + 32;
+    int64_t r0 = w.row0 + 64 * rw + (lane & 31), r1 = r0 + 32;
     if (r0 > w.M - 1) r0 = w.M - 1;
     if (r1 > w.M - 1) r1 = w.M - 1;
     const u32x4* A0 = Mp + w.j0 * w.M + r0;
@@ -342,45 +389,68 @@ __global__ __launch_bounds__(kGrpThreads) void grouped_h16_kernel(
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int g = 2 * (s0 + q) + half;
-        const bool ok = g < ng;
+        const bool ok = g < gend;
         a[q][0] = ok ? __builtin_nontemporal_load(A0 + (int64_t)g * w.M) : z4;
         a[q][1] = ok ? __builtin_nontemporal_load(A1 + (int64_t)g * w.M) : z4;
         a[q][2] = ok ? Bg[g * 32] : z4;
       }
     };
     u32x4 pa[4][3], pb[4][3];
-    load4(0, pa);
     const f32x16 zero16 = {};
     f32x16 acc[2] = {zero16, zero16};
-    const int nsteps = ng / 2;
     auto mult4 = [&](int s0, const u32x4 (&a)[4][3]) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (2 * (s0 + q) >= ng) break;  // uniform
+        if (s0 + q >= sb) break;  // uniform
         acc[0] = g16_mfma<BF16>(a[q][0], a[q][2], acc[0]);
         acc[1] = g16_mfma<BF16>(a[q][1], a[q][2], acc[1]);
       }
     };
-    for (int s0 = 0; s0 < nsteps; s0 += 8) {
-      load4(s0 + 4, pb);
-      mult4(s0, pa);
-      if (s0 + 4 >= nsteps) break;
-      load4(s0 + 8, pa);
-      mult4(s0 + 4, pb);
+    if (sa < sb) {
+      load4(sa, pa);
+      for (int s0 = sa; s0 < sb; s0 += 8) {
+        load4(s0 + 4, pb);
+        mult4(s0, pa);
+        if (s0 + 4 >= sb) break;
+        load4(s0 + 8, pa);
+        mult4(s0 + 4, pb);
+      }
     }
-    // column n = lane % 32 holds scene n's hi part (n < 16) or scene n-16's lo part
-    const int n = lane & 31;
+    if constexpr (KS > 1) {
+      if (ks > 0) {
+        red[((ks - 1) * RW + rw) * 2 + 0][lane] = acc[0];
+        red[((ks - 1) * RW + rw) * 2 + 1][lane] = acc[1];
+      }
+      __syncthreads();
+      if (ks == 0) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const float v = acc[t][q] + __shfl_xor(acc[t][q], 16, 64);
-        if (n < w.nscenes) {
-          const int rl = 64 * wave + 32 * t + 8 * (q >> 2) + 4 * half + (q & 3);
-          part[w.part + (int64_t)n * kGrpThreads + rl] = ldexpf(v, -fexp[w.scene0 + n]);
+        for (int k2 = 1; k2 < KS; ++k2) {
+          acc[0] += red[((k2 - 1) * RW + rw) * 2 + 0][lane];
+          acc[1] += red[((k2 - 1) * RW + rw) * 2 + 1][lane];
         }
       }
     }
+    if (ks == 0) {
+      // column n = lane % 32 holds scene n's hi part (n < 16) or scene n-16's lo part
+      const int n = lane & 31;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const float v = acc[t][q] + __shfl_xor(acc[t][q], 16, 64);
+          if (n < w.nscenes) {
+            const int rl = 64 * rw + 32 * t + 8 * (q >> 2) + 4 * half + (q & 3);
+            const float x = ldexpf(v, -fexp[w.scene0 + n]);
+            if (w.direct) {
+              if (w.row0 + rl < w.M) images[w.scene0 + n][w.row0 + rl] = x;
+            } else {
+              part[w.part + (int64_t)n * R + rl] = x;
+            }
+          }
+        }
+      }
+    }
+    if constexpr (KS > 1) __syncthreads();  // the LDS sums are read before the next item
   }
 }
 
@@ -417,7 +487,8 @@ struct psflib_grouped {
   hipGraph_t graph;
   hipGraphExec_t exec;
   void* dev;        // items | reductions | scene/image tables | slots | packed operands | partials
-  int64_t chunk;    // chosen chunk length (columns, or 8-column groups for 16-bit)
+  int64_t chunk;    // chosen chunk length (columns, or 8-column groups for 16-bit; 0: whole)
+  int32_t rows;     // chosen rows per item
   float ms_tuned;   // time of the chosen shape during autotuning (0 if not tuned)
   mutable psflib::StreamUses uses;  // streams the graph was launched on
 };
@@ -430,6 +501,16 @@ struct LibInfo {
   int64_t M, ncols, ncols_pad;
 };
 
+// What a plan is made of, kept for a later change of tile shape.
+struct PlanInputs {
+  std::vector<LibInfo> libs;
+  std::vector<int32_t> lib_of_scene;
+  std::vector<const float*> scenes;
+  std::vector<float*> images;
+};
+std::mutex g_inputs_mu;
+std::map<const psflib_grouped*, PlanInputs> g_inputs;
+
 struct Plan {
   std::vector<psflib::GItem> items;
   std::vector<psflib::GReduce> reds;
@@ -441,13 +522,20 @@ struct Plan {
   int64_t bpk_vecs = 0;               // 16-byte entries of the packed operands
 };
 
-// Items for a given chunk length.  Scenes are grouped by library (kept in the
+// Tile shape: rows per item and chunk length (0: every column of the library
+// in one item, whose rows are then written directly).
+struct Shape {
+  int64_t chunk;
+  int32_t rows;
+};
+
+// Items for a given shape.  Scenes are grouped by library (kept in the
 // caller's order inside a library) and cut into groups of kGrpScenes.
 Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib_of_scene,
-               const float* const* scenes, float* const* images, int B, int64_t chunk) {
+               const float* const* scenes, float* const* images, int B, Shape shape) {
   Plan p;
   const bool f32 = storage == PSFLIB_FP32;
-  const int64_t rows_per = psflib::kGrpThreads;
+  const int64_t rows_per = shape.rows;
   for (size_t L = 0; L < libs.size(); ++L) {
     std::vector<int> sc;
     for (int b = 0; b < B; ++b)
@@ -455,6 +543,7 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
     const LibInfo& li = libs[L];
     const int64_t units = f32 ? li.ncols : li.ncols_pad / 8;  // chunks count columns or 8-column groups
     const int64_t pk_units = f32 ? (li.ncols + 15) / 16 : units;  // packed operand blocks
+    const int64_t chunk = shape.chunk > 0 ? shape.chunk : std::max<int64_t>(units, 1);
     const int64_t nchunks = (units + chunk - 1) / chunk;
     const int64_t nrb = (li.M + rows_per - 1) / rows_per;
     const size_t spg = psflib::kGrpScenes;
@@ -480,7 +569,7 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
         rd.scene0 = scene0;
         rd.nscenes = ns;
         rd.pad = 0;
-        p.reds.push_back(rd);
+        if (nchunks > 1) p.reds.push_back(rd);
         for (int64_t c = 0; c < nchunks; ++c) {
           psflib::GItem it;
           it.A = li.A;
@@ -492,9 +581,11 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
           it.j1 = std::min(units, (c + 1) * chunk);
           it.scene0 = scene0;
           it.nscenes = ns;
-          it.part = p.part_floats;
           it.bpk = bpk;
-          p.part_floats += rd.stride;
+          it.direct = nchunks == 1;
+          it.pad = 0;
+          it.part = it.direct ? 0 : p.part_floats;
+          if (!it.direct) p.part_floats += rd.stride;
           p.items.push_back(it);
         }
       }
@@ -506,17 +597,17 @@ Plan make_plan(int storage, const std::vector<LibInfo>& libs, const int32_t* lib
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 std::mutex g_tune_mu;
-std::map<std::string, int64_t> g_tune_cache;  // plan signature -> chosen chunk
+std::map<std::string, Shape> g_tune_cache;  // plan signature -> chosen shape
 
 }  // namespace
 
 namespace psflib {
 
-// Build (or rebuild) the plan's device tables and graph for one chunk length.
+// Build (or rebuild) the plan's device tables and graph for one tile shape.
 static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& libs,
                               const int32_t* lib_of_scene, const float* const* scenes,
-                              float* const* images, int B, int64_t chunk, hipStream_t s) {
-  const Plan p = make_plan(g->storage, libs, lib_of_scene, scenes, images, B, chunk);
+                              float* const* images, int B, Shape shape, hipStream_t s) {
+  const Plan p = make_plan(g->storage, libs, lib_of_scene, scenes, images, B, shape);
   const size_t o_items = 0;
   const size_t o_reds = align256(o_items + p.items.size() * sizeof(GItem));
   const size_t o_sc = align256(o_reds + p.reds.size() * sizeof(GReduce));
@@ -580,26 +671,32 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
         const dim3 np((unsigned)p.packs.size(), 64);
         grouped_pack_f32_kernel<<<np, 256, 0, cap>>>(packs, sc, reinterpret_cast<f32x4*>(bpk));
         grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems,
-                                                          reinterpret_cast<const f32x4*>(bpk), part);
+                                                          reinterpret_cast<const f32x4*>(bpk), part, im);
       } else {
         grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 1024, 0, cap>>>(slots, fexp);
         const dim3 np((unsigned)p.packs.size(), 64);  // 64 workgroups per scene group
-        if (g->storage == PSFLIB_BF16_POW2) {
+        const bool bf = g->storage == PSFLIB_BF16_POW2;
+        if (bf)
           grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
-          grouped_h16_kernel<true><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
-        } else {
+        else
           grouped_pack_kernel<false><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
-          grouped_h16_kernel<false><<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part);
+        auto run = [&](auto kern) { kern<<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part, im); };
+        switch (shape.rows) {
+          case 64: bf ? run(grouped_h16_kernel<true, 4>) : run(grouped_h16_kernel<false, 4>); break;
+          case 128: bf ? run(grouped_h16_kernel<true, 2>) : run(grouped_h16_kernel<false, 2>); break;
+          default: bf ? run(grouped_h16_kernel<true, 1>) : run(grouped_h16_kernel<false, 1>); break;
         }
       }
-      grouped_reduce_kernel<<<(unsigned)p.reds.size(), 256, 0, cap>>>(reds, part, im);
+      if (!p.reds.empty())
+        grouped_reduce_kernel<<<(unsigned)p.reds.size(), 256, 0, cap>>>(reds, part, im);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
     e = (e2 != hipSuccess) ? e2 : hipGetLastError();
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cap);
-  g->chunk = chunk;
+  g->chunk = shape.chunk;
+  g->rows = shape.rows;
   return e;
 }
 
@@ -650,6 +747,8 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
   g->exec = nullptr;
   g->dev = nullptr;
   g->ms_tuned = 0.0f;
+  g->chunk = 0;
+  g->rows = 256;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // the libraries may still be building on `stream`
   hipError_t e = hipStreamSynchronize(s);
@@ -659,16 +758,23 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
   };
   if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
 
-  // Candidate chunk lengths: columns (FP32) or 8-column groups (16-bit).
+  // Candidate shapes.  Chunk lengths: columns (FP32) or 8-column groups
+  // (16-bit), 0 = every column in one item (images written directly, no
+  // partials); rows per item: 256 for FP32, 256, 128 or 64 for 16-bit.
   const bool f32 = storage == PSFLIB_FP32;
-  std::vector<int64_t> cands = f32 ? std::vector<int64_t>{256, 512, 1024, 2048}
-                                   : std::vector<int64_t>{128, 256, 512, 1024};
+  std::vector<Shape> cands;
+  if (f32) {
+    for (int64_t c : {0, 256, 512, 1024, 2048}) cands.push_back(Shape{c, 256});
+  } else {
+    for (int32_t r : {256, 128, 64})
+      for (int64_t c : {0, 128, 256, 512, 1024}) cands.push_back(Shape{c, r});
+  }
   std::string sig = std::to_string(storage) + ":";
   for (int b = 0; b < B; ++b) {
     const LibInfo& li = libs[h_lib_of_scene[b]];
     sig += std::to_string(li.M) + "x" + std::to_string(li.ncols) + ",";
   }
-  int64_t chosen = f32 ? 512 : 256;
+  Shape chosen = f32 ? Shape{512, 256} : Shape{256, 256};
   bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -680,7 +786,7 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
       return bail(hipErrorUnknown, "hipEventCreate");
-    for (int64_t c : cands) {
+    for (const Shape& c : cands) {
       e = psflib::instantiate(g, libs, h_lib_of_scene, h_scenes, h_images, B, c, s);
       if (e != hipSuccess) break;
       float t = 1e30f;
@@ -704,7 +810,44 @@ psflib_status psflib_grouped_create(const psflib_handle* const* h_libs, int32_t 
   }
   e = psflib::instantiate(g, libs, h_lib_of_scene, h_scenes, h_images, B, chosen, s);
   if (e != hipSuccess) return bail(e, "grouped plan");
+  {
+    PlanInputs in;
+    in.libs = libs;
+    in.lib_of_scene.assign(h_lib_of_scene, h_lib_of_scene + B);
+    in.scenes.assign(h_scenes, h_scenes + B);
+    in.images.assign(h_images, h_images + B);
+    std::lock_guard<std::mutex> lk(g_inputs_mu);
+    g_inputs[g] = std::move(in);
+  }
   *out = g;
+  return PSFLIB_OK;
+}
+
+psflib_status psflib_grouped_set_shape(psflib_grouped* g, int64_t chunk, int32_t rows, void* stream) {
+  if (!g) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped plan is NULL");
+  const bool f32 = g->storage == PSFLIB_FP32;
+  if (chunk < 0 || chunk % (f32 ? 16 : 8) != 0 ||
+      (f32 ? rows != 256 : (rows != 64 && rows != 128 && rows != 256)))
+    return psflib::fail_status(PSFLIB_ERR_INVALID_ARG,
+                               "grouped: chunk must be a non-negative multiple of 16 columns (FP32) or "
+                               "8 groups (16-bit); rows 256 (FP32) or 64, 128, 256 (16-bit)");
+  PlanInputs in;
+  {
+    std::lock_guard<std::mutex> lk(g_inputs_mu);
+    auto it = g_inputs.find(g);
+    if (it == g_inputs.end()) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "grouped: unknown plan");
+    in = it->second;
+  }
+  if (in.scenes.empty()) return PSFLIB_OK;
+  psflib_status pst = psflib::check_pending_error();
+  if (pst != PSFLIB_OK) return pst;
+  // the plan's earlier launches finish before its tables are replaced
+  g->uses.wait_all();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = psflib::instantiate(g, in.libs, in.lib_of_scene.data(), in.scenes.data(),
+                                     in.images.data(), (int)in.scenes.size(), Shape{chunk, rows}, s);
+  if (e != hipSuccess) return psflib::device_fail_status(e, "grouped plan");
+  g->ms_tuned = 0.0f;
   return PSFLIB_OK;
 }
 
@@ -722,14 +865,24 @@ psflib_status psflib_grouped_run(const psflib_grouped* g, void* stream) {
 }
 
 psflib_status psflib_grouped_chunk(const psflib_grouped* g, int64_t* chunk, float* tuned_ms) {
+  return psflib_grouped_shape(g, chunk, nullptr, tuned_ms);
+}
+
+psflib_status psflib_grouped_shape(const psflib_grouped* g, int64_t* chunk, int32_t* rows,
+                                   float* tuned_ms) {
   if (!g || !chunk) return psflib::fail_status(PSFLIB_ERR_INVALID_ARG, "NULL argument");
   *chunk = g->chunk;
+  if (rows) *rows = g->rows;
   if (tuned_ms) *tuned_ms = g->ms_tuned;
   return PSFLIB_OK;
 }
 
 void psflib_grouped_destroy(psflib_grouped* g) {
   if (!g) return;
+  {
+    std::lock_guard<std::mutex> lk(g_inputs_mu);
+    g_inputs.erase(g);
+  }
   // wait for the plan's own launches (not for the device)
   g->uses.wait_all();
   if (g->exec) (void)hipGraphExecDestroy(g->exec);

@@ -78,6 +78,9 @@ def _load():
         "psflib_grouped_create": (I32, [P, I32, P, P, P, I32, I32, P, ctypes.POINTER(P)]),
         "psflib_grouped_run": (I32, [P, P]),
         "psflib_grouped_chunk": (I32, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_float)]),
+        "psflib_grouped_shape": (I32, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_float)]),
+        "psflib_grouped_set_shape": (I32, [P, ctypes.c_int64, ctypes.c_int32, P]),
         "psflib_grouped_destroy": (None, [P]),
         "psflib_render_disk_grad": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P, P]),
         "psflib_destroy": (None, [P]),
@@ -99,7 +102,8 @@ SYMBOLS = (
     "psflib_apply", "psflib_apply_noalloc", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
     "psflib_render_disk", "psflib_render_disk_grad", "psflib_grouped_create",
-    "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_destroy",
+    "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_shape", "psflib_grouped_set_shape",
+    "psflib_grouped_destroy",
     "psflib_probe_hbm_read", "psflib_probe_mfma",
 )
 
@@ -245,6 +249,21 @@ def grouped_chunk(g: int):
     return int(c.value), float(t.value)
 
 
+def grouped_shape(g: int):
+    """(chunk, rows per item, autotuned ms) of a grouped plan."""
+    c = ctypes.c_int64(0)
+    r = ctypes.c_int32(0)
+    t = ctypes.c_float(0.0)
+    _check(_lib.psflib_grouped_shape(ctypes.c_void_p(g), ctypes.byref(c), ctypes.byref(r), ctypes.byref(t)),
+           "psflib_grouped_shape")
+    return int(c.value), int(r.value), float(t.value)
+
+
+def grouped_set_shape(g: int, chunk: int, rows: int, stream: int):
+    _check(_lib.psflib_grouped_set_shape(ctypes.c_void_p(g), ctypes.c_int64(chunk), ctypes.c_int32(rows),
+                                         ctypes.c_void_p(stream)), "psflib_grouped_set_shape")
+
+
 def grouped_destroy(g: int):
     _lib.psflib_grouped_destroy(ctypes.c_void_p(g))
 
@@ -282,6 +301,14 @@ class Grouped:
 
     def chunk(self):
         return grouped_chunk(self.g)
+
+    def shape(self):
+        """dict(chunk, rows, tuned_ms): the plan's tile shape (chunk 0 = whole columns)."""
+        c, r, t = grouped_shape(self.g)
+        return {"chunk": c, "rows": r, "tuned_ms": t}
+
+    def set_shape(self, chunk, rows, stream=None):
+        grouped_set_shape(self.g, chunk, rows, self._stream(stream))
 
     def close(self):
         if getattr(self, "g", None):

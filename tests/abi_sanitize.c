@@ -122,6 +122,9 @@ int main(void) {
   int64_t chunk = 0;
   float tuned = 0.0f;
   EXPECT(psflib_grouped_chunk(NULL, &chunk, &tuned) == PSFLIB_ERR_INVALID_ARG);
+  int32_t rows = 0;
+  EXPECT(psflib_grouped_shape(NULL, &chunk, &rows, &tuned) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_grouped_set_shape(NULL, 0, 256, NULL) == PSFLIB_ERR_INVALID_ARG);
   psflib_grouped_destroy(NULL);
 
   /* fitting model */

@@ -116,6 +116,8 @@ def test_grouped_and_model_validation_without_device():
         psflib.grouped_create([], [], [], [], False, 0)
     assert e.value.status == psflib.ERR_INVALID_ARG
     assert _err(psflib.grouped_run, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.grouped_shape, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.grouped_set_shape, 0, 0, 256, 0) == psflib.ERR_INVALID_ARG
     psflib.grouped_destroy(0)
     assert _err(psflib.render_disk, 0, 0.5, 8.0, FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.render_disk, 8, -0.5, 8.0, FAKE, FAKE, 0) == psflib.ERR_INVALID_ARG

@@ -52,7 +52,46 @@ def test_grouped_matches_oracle(torch, work, storage, autotune):
         single = L[scene_lib[b]].apply(Zs[b]).cpu().numpy().astype(np.float64)
         assert np.max(np.abs(single - got)) <= 2e-5 * np.max(np.abs(got)) + 1e-30
     chunk, ms = g.chunk()
-    assert chunk > 0 and (ms > 0) == (autotune and ms > 0)
+    sh = g.shape()
+    assert chunk >= 0 and sh["chunk"] == chunk and sh["rows"] in ((256,) if storage == "fp32" else (64, 128, 256))
+    assert (ms > 0) == (autotune and ms > 0)
+    g.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+def test_grouped_every_tile_shape(torch, work, storage):
+    """Every tile shape the autotuner can pick gives oracle-matching,
+    reproducible images: rows per item (16-bit: 256, 128 and 64, the last two
+    splitting columns among the workgroup's waves), chunked columns with the
+    partials added by the second kernel (chunks of 64 columns: many per
+    library, the last one short) and whole columns per item (images written
+    directly)."""
+    from paper_2106_09122_amd import psflib
+    libs, scene_lib, scenes, refs = work
+    L = [psflib.Library(torch.from_numpy(l["cube"]).cuda(), l["radii"], l["N"], l["S"], storage=storage)
+         for l in libs]
+    Zs = [torch.from_numpy(z).cuda() for z in scenes]
+    g = psflib.Grouped(L, scene_lib, Zs, autotune=False)
+    shapes = [(c, 256) for c in (0, 64, 2048)] if storage == "fp32" else \
+             [(c, r) for r in (256, 128, 64) for c in (0, 8, 256)]
+    with pytest.raises(RuntimeError):
+        g.set_shape(4, 256)  # not a whole number of blocks
+    with pytest.raises(RuntimeError):
+        g.set_shape(0, 32)
+    for chunk, rows in shapes:
+        g.set_shape(chunk, rows)
+        assert g.shape()["chunk"] == chunk and g.shape()["rows"] == rows
+        out = [im.cpu().numpy().astype(np.float64) for im in g.run()]
+        again = [im.cpu().numpy() for im in g.run()]
+        for b, (got, ref) in enumerate(zip(out, refs)):
+            assert np.array_equal(got.astype(np.float32), again[b]), (chunk, rows, b)
+            if storage == "fp32":
+                pos = ref > 0
+                assert np.all(got[~pos] == 0)
+                assert np.max(np.abs(got[pos] - ref[pos]) / ref[pos]) <= 1e-5, (chunk, rows, b)
+            else:
+                big = ref > 1e-6 * ref.max()
+                assert np.max(np.abs(got - ref)[big] / ref[big]) <= U16[storage] + 1e-5, (chunk, rows, b)
     g.close()
 
 
