@@ -396,6 +396,92 @@ __global__ __launch_bounds__(256) void pack_scenes_kernel(const float* __restric
   Zg[g * Bp + n] = pk;
 }
 
+// Scenes of at most kStageMaxCols columns take a two-kernel path that reads
+// every scene once, coalesced (the slot order gathers columns from all over
+// the scene: read straight from HBM, each 4-byte value would cost a sector):
+//  * stage_slots16_kernel, one 1024-thread workgroup per scene: the scene into
+//    LDS (16-byte loads), f_b from it (as scene_exponent_kernel), then the
+//    slots in order, gathered from LDS, scaled by 2^(eslot + f_b) and rounded:
+//    Zs[b][g] = 16 bytes per 8-slot group;
+//  * slots_to_operand_kernel: the [scene][group] -> [group][scene] transpose
+//    into the GEMM's operand Zg (zeros for the padding scenes).
+template <bool BF16, bool VEC>
+__global__ __launch_bounds__(1024) void stage_slots16_kernel(const float* __restrict__ Z,
+                                                             const int32_t* __restrict__ exps,
+                                                             const int32_t* __restrict__ perm,
+                                                             const int32_t* __restrict__ eslot,
+                                                             int64_t ncols, int64_t ngroups,
+                                                             int32_t* __restrict__ fexp,
+                                                             u32x4* __restrict__ Zs) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float zl[];  // the scene, ncols floats
+  __shared__ double red[16];
+  __shared__ int s_f;
+  const int64_t b = blockIdx.x;
+  const float* z = Z + b * ncols;
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  if constexpr (VEC) {
+    for (int64_t j = 4 * (int64_t)tid; j < ncols; j += 4 * 1024) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(z + j);
+      const i32x4 e = *reinterpret_cast<const i32x4*>(exps + j);
+      *reinterpret_cast<f32x4*>(zl + j) = v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m = fmax(m, ldexp((double)fabsf(v[q]), e[q]));
+    }
+  } else {
+    for (int64_t j = tid; j < ncols; j += 1024) {
+      const float v = z[j];
+      zl[j] = v;
+      m = fmax(m, ldexp((double)fabsf(v), exps[j]));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    m = red[0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+    int f = 0;
+    if (m > 0.0) {
+      int E;
+      (void)frexp(m, &E);
+      f = 15 - E;  // max |Z_bj| 2^(e_j + f) in [2^14, 2^15)
+    }
+    s_f = f;
+    fexp[b] = f;
+  }
+  __syncthreads();
+  const int f = s_f;
+  for (int64_t g = tid; g < ngroups; g += 1024) {
+    const i32x4 p0 = *reinterpret_cast<const i32x4*>(perm + 8 * g);
+    const i32x4 p1 = *reinterpret_cast<const i32x4*>(perm + 8 * g + 4);
+    const i32x4 e0 = *reinterpret_cast<const i32x4*>(eslot + 8 * g);
+    const i32x4 e1 = *reinterpret_cast<const i32x4*>(eslot + 8 * g + 4);
+    uint32_t h[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h[q] = to16(ldexpf(p0[q] >= 0 ? zl[p0[q]] : 0.0f, e0[q] + f), BF16);
+      h[4 + q] = to16(ldexpf(p1[q] >= 0 ? zl[p1[q]] : 0.0f, e1[q] + f), BF16);
+    }
+    Zs[b * ngroups + g] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                  h[6] | (h[7] << 16)};
+  }
+}
+
+// Thread = (group g, scene n), 8 lanes per 8 consecutive scenes: reads 16
+// bytes of Zs row n, writes 8 whole 128-byte lines of Zg per wave.
+__global__ __launch_bounds__(256) void slots_to_operand_kernel(const u32x4* __restrict__ Zs,
+                                                               int64_t bc, int64_t ngroups,
+                                                               int64_t Bp, u32x4* __restrict__ Zg) {
+  const int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (g >= ngroups) return;
+  const int64_t n = (int64_t)blockIdx.y * 8 + (threadIdx.x & 7);
+  Zg[g * Bp + n] = n < bc ? Zs[n * ngroups + g] : (u32x4){0u, 0u, 0u, 0u};
+}
+
 template <bool BF16>
 __device__ __forceinline__ f32x16 mfma16(const u32x4 a, const u32x4 b, const f32x16 c) {
   if constexpr (BF16)
@@ -830,6 +916,8 @@ size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncol
   if (storage != PSFLIB_FP32) {
     bytes += ((size_t)padded_batch(bc) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;  // Zg
     bytes += ((size_t)bc * 4 + 255) & ~(size_t)255;                                    // fexp
+    if (ncols <= kStageMaxCols)
+      bytes += ((size_t)bc * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;             // Zs
   } else {
     bytes += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bc) * 1024;          // Zp
   }
@@ -852,11 +940,16 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
   const int64_t bcmax = chunk_of(B);
   size_t off = 0;
   f32x4* Zp = nullptr;
+  u32x4* Zs = nullptr;
   if (storage != PSFLIB_FP32) {
     Zg = reinterpret_cast<u32x4*>(sp);
     off += ((size_t)padded_batch(bcmax) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
     fexp = reinterpret_cast<int32_t*>(sp + off);
     off += ((size_t)bcmax * 4 + 255) & ~(size_t)255;
+    if (ncols <= kStageMaxCols) {
+      Zs = reinterpret_cast<u32x4*>(sp + off);
+      off += ((size_t)bcmax * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
+    }
   } else {
     Zp = reinterpret_cast<f32x4*>(sp);
     off += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bcmax) * 1024;
@@ -890,17 +983,32 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
       const bool bf = storage == PSFLIB_BF16_POW2;
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
       const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
-      if (vec)
-        scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
-      else
-        scene_exponent_kernel<false><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
       const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
-      if (bf)
-        pack_scenes_kernel<true><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
-      else
-        pack_scenes_kernel<false><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
+      if (Zs) {
+        const size_t lds = (size_t)ncols * 4;
+        auto stage = [&](auto kern) -> hipError_t {
+          hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          if (err != hipSuccess) return err;
+          kern<<<(unsigned)bc, 1024, lds, s>>>(Zc, cx.exps, cx.perm, cx.eslot, ncols, ngroups, fexp, Zs);
+          return hipGetLastError();
+        };
+        e = bf ? (vec ? stage(stage_slots16_kernel<true, true>) : stage(stage_slots16_kernel<true, false>))
+               : (vec ? stage(stage_slots16_kernel<false, true>) : stage(stage_slots16_kernel<false, false>));
+        if (e != hipSuccess) return e;
+        slots_to_operand_kernel<<<pgrid, 256, 0, s>>>(Zs, bc, ngroups, Bp, Zg);
+      } else {
+        if (vec)
+          scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
+        else
+          scene_exponent_kernel<false><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (bf)
+          pack_scenes_kernel<true><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
+        else
+          pack_scenes_kernel<false><<<pgrid, 256, 0, s>>>(Zc, cx.perm, cx.eslot, fexp, ncols, ngroups, bc, Bp, Zg);
+      }
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
