@@ -1154,15 +1154,18 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
 // 16-bit orbit build (N a multiple of 8: no centre, whole blocks of 8 bases).
 // A window of 16 bases is two blocks; block h's member k is group
 // 4 (w0/8 + h) + k, whose unit at an image pixel holds the 8 bases' member
-// values there.  Per step every wave forms a 16 x 32 pixel tile of its base
-// column (lane (i, k): rows 2i, 2i+1, columns 4k..4k+3), rounds the values
-// into an LDS tile [2][16][33][8] (unit-major: the 8 bases of a block and
-// pixel are one 16-byte LDS word; one unit of padding per row keeps the
-// column-wise reads conflict-free); then each unit is read once per store
-// pattern and written to two groups: along rows for members 0 and 2 (runs of
-// 32 units in rows a and n-1-a), along columns for members 1 and 3 (runs of
-// 16 units in rows b and n-1-b).  Slots of a block outside the item (the
-// block straddles two brackets) are left to the other item: 2-byte stores.
+// values there.  The item's rows are walked in tiles of 8 x 32 pixels: every
+// wave forms its base column's tile (lane (i, k): row i, columns 4k..4k+3),
+// rounds the values into an LDS tile [2][8][33][8] (unit-major: the 8 bases of
+// a block and pixel are one 16-byte LDS word; one unit of padding per row
+// keeps the column-wise reads conflict-free), and after one barrier half the
+// threads copy the tile's units along rows to members 0 and 2 (runs of 32
+// units in rows a and n-1-a) and half along columns to members 1 and 3 (runs
+// of 8 units, one 128-byte line, in rows b and n-1-b).  The LDS tile is
+// double-buffered, so that one barrier per tile suffices: a tile's buffer is
+// written again two tiles later, after every thread has passed the barrier
+// behind the copy that read it.  Slots of a block outside the item (the block
+// straddles two brackets) are left to the other item: 2-byte stores.
 template <bool BF16>
 __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __restrict__ cube, int K,
                                                              const ColGeom* __restrict__ geo,
@@ -1173,15 +1176,16 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
                                                              int rpr, int64_t nreps,
                                                              uint16_t* __restrict__ Mh,
                                                              double* __restrict__ part) {
-  constexpr int TA = 16, TB = 32, TP = TB + 1;
-  extern __shared__ float2 P2[];  // bordered pair, then the tile
+  constexpr int TA = 8, TB = 32, TP = TB + 1;
+  constexpr int TILE = 2 * TA * TP * 8;  // uint16 per buffer
+  extern __shared__ float2 P2[];  // bordered pair, then the two tile buffers
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
   const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
   const bool zero_bucket = bkt == nb - 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
-  uint16_t* tile = reinterpret_cast<uint16_t*>(P2 + ((((size_t)(n + 2) * ls) + 1) & ~(size_t)1));
+  uint16_t* tiles = reinterpret_cast<uint16_t*>(P2 + ((((size_t)(n + 2) * ls) + 1) & ~(size_t)1));
   if (!zero_bucket) stage_pair(P2, cube, bkt, K, n, ls, M, tid);
   const int sp = w0 + wave;
   const bool live = sp >= first && sp < first + len;  // uniform per wave
@@ -1200,24 +1204,18 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
     hi[q] = (first + len < s0 + 8) ? first + len - s0 : 8;
   }
   const int li = lane >> 3, lk = lane & 7;
+  // copy roles: threads 0..511 along rows, 512..1023 along columns
+  const bool along_cols = tid >= 512;
+  const int cq = (tid & 511) >> 8, crem = tid & 255;
   double tsum = 0.0;
+  __syncthreads();  // the pair is staged
+  int buf = 0;
   for (int a0 = ra; a0 < rb; a0 += TA) {
-    for (int b0 = 0; b0 < n; b0 += TB) {
-      __syncthreads();  // the pair is staged; the previous tile has been stored
+    for (int b0 = 0; b0 < n; b0 += TB, buf ^= 1) {
+      uint16_t* tile = tiles + buf * TILE;
       if (live) {
-        const int ta = 2 * li, tb = 4 * lk;  // the lane's block inside the tile
-        double ctux[4], mstux[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma clang fp contract(off)
-          const double ux = (double)(b0 + tb + q) - c;
-          ctux[q] = g.ct * ux;
-          mstux[q] = (-g.st) * ux;
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const int a = a0 + ta + r;
-          if (a >= rb) continue;
+        const int a = a0 + li, bb = b0 + 4 * lk;
+        if (a < rb) {
           double stuy, ctuy;
           {
 #pragma clang fp contract(off)
@@ -1227,10 +1225,16 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            if (b0 + tb + q >= n) continue;
-            const float val = zero_bucket
-                                  ? 0.0f
-                                  : orbit_value(P2, ctux[q], mstux[q], stuy, ctuy, c, n, ls, wk0, wk1);
+            if (bb + q >= n) continue;
+            double ctux, mstux;
+            {
+#pragma clang fp contract(off)
+              const double ux = (double)(bb + q) - c;
+              ctux = g.ct * ux;
+              mstux = (-g.st) * ux;
+            }
+            const float val = zero_bucket ? 0.0f
+                                          : orbit_value(P2, ctux, mstux, stuy, ctuy, c, n, ls, wk0, wk1);
             tsum += (double)val;
             const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
             uint32_t hv;
@@ -1241,50 +1245,41 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
             } else {
               hv = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)xs);
             }
-            tile[((h * TA + ta + r) * TP + tb + q) * 8 + u] = (uint16_t)hv;
+            tile[((h * TA + li) * TP + 4 * lk + q) * 8 + u] = (uint16_t)hv;
           }
         }
       }
       __syncthreads();
-      // one unit per thread and pattern: 2 blocks x 16 rows x 32 columns
-      {
-        const int q = tid >> 9, rem = tid & 511;
-        const bool any = lo[q] < hi[q];
-        // members 0 and 2: columns fastest
-        {
-          const int r = rem >> 5, cb = rem & 31, a = a0 + r, b = b0 + cb;
-          if (any && a < rb && b < n) {
-            const uint16_t* src = tile + ((q * TA + r) * TP + cb) * 8;
-            uint16_t* d0 = Mh + ((G0 + 4 * q + 0) * M + (int64_t)a * n + b) * 8;
-            uint16_t* d2 = Mh + ((G0 + 4 * q + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
-            if (lo[q] == 0 && hi[q] == 8) {
-              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d0));
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d2));
-            } else {
-              for (int s = lo[q]; s < hi[q]; ++s) {
-                d0[s] = src[s];
-                d2[s] = src[s];
-              }
-            }
-          }
+      // one unit per thread: block cq, 8 rows x 32 columns
+      if (lo[cq] < hi[cq]) {
+        int r, cb;
+        if (along_cols) {
+          cb = crem >> 3;
+          r = crem & 7;
+        } else {
+          r = crem >> 5;
+          cb = crem & 31;
         }
-        // members 1 and 3: rows fastest
-        {
-          const int cb = rem >> 4, r = rem & 15, a = a0 + r, b = b0 + cb;
-          if (any && a < rb && b < n) {
-            const uint16_t* src = tile + ((q * TA + r) * TP + cb) * 8;
-            uint16_t* d1 = Mh + ((G0 + 4 * q + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
-            uint16_t* d3 = Mh + ((G0 + 4 * q + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
-            if (lo[q] == 0 && hi[q] == 8) {
-              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d1));
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(d3));
-            } else {
-              for (int s = lo[q]; s < hi[q]; ++s) {
-                d1[s] = src[s];
-                d3[s] = src[s];
-              }
+        const int a = a0 + r, b = b0 + cb;
+        if (a < rb && b < n) {
+          const uint16_t* src = tile + ((cq * TA + r) * TP + cb) * 8;
+          uint16_t* dA;
+          uint16_t* dB;
+          if (along_cols) {
+            dA = Mh + ((G0 + 4 * cq + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
+            dB = Mh + ((G0 + 4 * cq + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
+          } else {
+            dA = Mh + ((G0 + 4 * cq + 0) * M + (int64_t)a * n + b) * 8;
+            dB = Mh + ((G0 + 4 * cq + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
+          }
+          if (lo[cq] == 0 && hi[cq] == 8) {
+            const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dA));
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dB));
+          } else {
+            for (int s = lo[cq]; s < hi[cq]; ++s) {
+              dA[s] = src[s];
+              dB[s] = src[s];
             }
           }
         }
@@ -1602,11 +1597,11 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
   return orbit_finish(pl, tau, s);
 }
 
-// 16-bit orbit build: the pair (ending 16-byte aligned), then the 2 x 16 x 33 unit tile
+// 16-bit orbit build: the pair (ending 16-byte aligned), then two 2 x 8 x 33 unit tiles
 static size_t orbit16_pair_bytes(int n) {
   return (((size_t)(n + 2) * lds_stride(n) * sizeof(float2)) + 15) & ~(size_t)15;
 }
-static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)2 * 16 * 33 * 16; }
+static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)2 * (2 * 8 * 33 * 16); }
 
 bool build_orbit16_supported(int n, int K, int N) {
   return N % 8 == 0 && pair_fits_lds(n) && orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes &&

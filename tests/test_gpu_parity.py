@@ -162,6 +162,8 @@ SHAPES = [
     # centre of an odd grid, and the 16-bit orbit build with one tile row
     (136, 8, 0.5, 4, "linear", "linear", "clamp"),
     (133, 9, 0.45, 3, "nonuniform", "linear", "zero"),
+    # 22500 scene pixels: the 16-bit batched product stages each scene in 88 KiB of LDS
+    (8, 150, 0.1, 3, "linear", "linear", "clamp"),
     # bordered PSF pairs larger than the LDS: staged in row bands (2, 3 and 4
     # bands; 199 also takes the scalar staging loads and partial lanes)
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
@@ -206,7 +208,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:8] + [SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:9] + [SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
