@@ -396,30 +396,41 @@ __global__ __launch_bounds__(256) void pack_scenes_kernel(const float* __restric
   Zg[g * Bp + n] = pk;
 }
 
-// Scenes of at most kStageMaxCols columns take a two-kernel path that reads
-// every scene once, coalesced (the slot order gathers columns from all over
-// the scene: read straight from HBM, each 4-byte value would cost a sector):
-//  * stage_slots16_kernel, one 1024-thread workgroup per scene: the scene into
-//    LDS (16-byte loads), f_b from it (as scene_exponent_kernel), then the
-//    slots in order, gathered from LDS, scaled by 2^(eslot + f_b) and rounded:
-//    Zs[b][g] = 16 bytes per 8-slot group;
-//  * slots_to_operand_kernel: the [scene][group] -> [group][scene] transpose
-//    into the GEMM's operand Zg (zeros for the padding scenes).
+// Scenes of at most kStageMaxCols columns are packed by one workgroup of 1024
+// threads per scene that reads the scene once, coalesced (the slot order
+// gathers columns from all over the scene: read straight from HBM, each
+// 4-byte value would cost a sector): the scene into LDS (16-byte loads), f_b
+// from it (as scene_exponent_kernel), then the slots in order, gathered from
+// LDS, scaled by 2^(eslot + f_b) and rounded, each group's 16 bytes written to
+// its place Zg[g][b] of the operand.  A workgroup writes one 16-byte piece of
+// every 128-byte line of the operand; the 8 scenes of a line are numbered to
+// land on one XCD back to back (dispatch is round-robin over the 8 XCDs), so
+// each line fills in that XCD's L2.  Workgroups of the padding scenes (b >= bc)
+// write zeros.  (A [scene][group] copy followed by a transpose kernel took
+// 27 + 12 us at B = 1024 against 34 us.)
 template <bool BF16, bool VEC>
 __global__ __launch_bounds__(1024) void stage_slots16_kernel(const float* __restrict__ Z,
                                                              const int32_t* __restrict__ exps,
                                                              const int32_t* __restrict__ perm,
                                                              const int32_t* __restrict__ eslot,
                                                              int64_t ncols, int64_t ngroups,
+                                                             int64_t bc, int64_t Bp,
                                                              int32_t* __restrict__ fexp,
-                                                             u32x4* __restrict__ Zs) {
+                                                             u32x4* __restrict__ Zg) {
   typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   extern __shared__ float zl[];  // the scene, ncols floats
   __shared__ double red[16];
   __shared__ int s_f;
-  const int64_t b = blockIdx.x;
-  const float* z = Z + b * ncols;
+  // Bp is a multiple of 64: workgroups x, x + 8, ..., x + 56 (one XCD) take
+  // scenes 8x .. 8x + 7, and so on per 64 scenes
+  const int64_t wg = blockIdx.x, xcd = wg % 8, rnd = wg / 8;
+  const int64_t b = 8 * (xcd + 8 * (rnd / 8)) + rnd % 8;
   const int tid = threadIdx.x;
+  if (b >= bc) {
+    for (int64_t g = tid; g < ngroups; g += 1024) Zg[g * Bp + b] = (u32x4){0u, 0u, 0u, 0u};
+    return;
+  }
+  const float* z = Z + b * ncols;
   double m = 0.0;
   if constexpr (VEC) {
     for (int64_t j = 4 * (int64_t)tid; j < ncols; j += 4 * 1024) {
@@ -466,20 +477,9 @@ __global__ __launch_bounds__(1024) void stage_slots16_kernel(const float* __rest
       h[q] = to16(ldexpf(p0[q] >= 0 ? zl[p0[q]] : 0.0f, e0[q] + f), BF16);
       h[4 + q] = to16(ldexpf(p1[q] >= 0 ? zl[p1[q]] : 0.0f, e1[q] + f), BF16);
     }
-    Zs[b * ngroups + g] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                                  h[6] | (h[7] << 16)};
+    Zg[g * Bp + b] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                             h[6] | (h[7] << 16)};
   }
-}
-
-// Thread = (group g, scene n), 8 lanes per 8 consecutive scenes: reads 16
-// bytes of Zs row n, writes 8 whole 128-byte lines of Zg per wave.
-__global__ __launch_bounds__(256) void slots_to_operand_kernel(const u32x4* __restrict__ Zs,
-                                                               int64_t bc, int64_t ngroups,
-                                                               int64_t Bp, u32x4* __restrict__ Zg) {
-  const int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
-  if (g >= ngroups) return;
-  const int64_t n = (int64_t)blockIdx.y * 8 + (threadIdx.x & 7);
-  Zg[g * Bp + n] = n < bc ? Zs[n * ngroups + g] : (u32x4){0u, 0u, 0u, 0u};
 }
 
 template <bool BF16>
@@ -916,8 +916,6 @@ size_t batched_scratch_bytes(int storage, int64_t M, int64_t ncols, int64_t ncol
   if (storage != PSFLIB_FP32) {
     bytes += ((size_t)padded_batch(bc) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;  // Zg
     bytes += ((size_t)bc * 4 + 255) & ~(size_t)255;                                    // fexp
-    if (ncols <= kStageMaxCols)
-      bytes += ((size_t)bc * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;             // Zs
   } else {
     bytes += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bc) * 1024;          // Zp
   }
@@ -940,16 +938,11 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
   const int64_t bcmax = chunk_of(B);
   size_t off = 0;
   f32x4* Zp = nullptr;
-  u32x4* Zs = nullptr;
   if (storage != PSFLIB_FP32) {
     Zg = reinterpret_cast<u32x4*>(sp);
     off += ((size_t)padded_batch(bcmax) * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
     fexp = reinterpret_cast<int32_t*>(sp + off);
     off += ((size_t)bcmax * 4 + 255) & ~(size_t)255;
-    if (ncols <= kStageMaxCols) {
-      Zs = reinterpret_cast<u32x4*>(sp + off);
-      off += ((size_t)bcmax * (size_t)ncols_pad * 2 + 255) & ~(size_t)255;
-    }
   } else {
     Zp = reinterpret_cast<f32x4*>(sp);
     off += (size_t)((ncols + 7) / 8) * (size_t)f32_scene_blocks(bcmax) * 1024;
@@ -984,19 +977,19 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
       const bool vec = (ncols % 8) == 0 && (reinterpret_cast<uintptr_t>(Zc) % 16) == 0;
       const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
       const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
-      if (Zs) {
+      if (ncols <= kStageMaxCols) {
         const size_t lds = (size_t)ncols * 4;
         auto stage = [&](auto kern) -> hipError_t {
           hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
           if (err != hipSuccess) return err;
-          kern<<<(unsigned)bc, 1024, lds, s>>>(Zc, cx.exps, cx.perm, cx.eslot, ncols, ngroups, fexp, Zs);
+          kern<<<(unsigned)Bp, 1024, lds, s>>>(Zc, cx.exps, cx.perm, cx.eslot, ncols, ngroups, bc, Bp,
+                                               fexp, Zg);
           return hipGetLastError();
         };
         e = bf ? (vec ? stage(stage_slots16_kernel<true, true>) : stage(stage_slots16_kernel<true, false>))
                : (vec ? stage(stage_slots16_kernel<false, true>) : stage(stage_slots16_kernel<false, false>));
         if (e != hipSuccess) return e;
-        slots_to_operand_kernel<<<pgrid, 256, 0, s>>>(Zs, bc, ngroups, Bp, Zg);
       } else {
         if (vec)
           scene_exponent_kernel<true><<<(unsigned)bc, 1024, 0, s>>>(Zc, cx.exps, ncols, ngroups, fexp);
