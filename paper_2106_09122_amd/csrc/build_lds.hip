@@ -291,8 +291,10 @@ __global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict
 // block's end pixels, with a margin); over those rows every lane forms its
 // pixel's row coordinate (the oracle's float64 operations) to test membership
 // exactly, and does the rest of the element's work only for pixels of the
-// band.  Stores go to the same columns as in the unbanded kernel, each
-// element written once.
+// band.  A wave builds a column j of the first half of the scene grid (or the
+// centre of an odd grid) and, in the same step, its half turn about the star,
+// column N^2-1-j, whose entry (n-1-a, n-1-b) is entry (a, b) of column j (the
+// same float64 products, negated twice); every element is written once.
 template <int E, bool FULL>
 __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restrict__ cube, int K,
                                                           const ColGeom* __restrict__ geo,
@@ -300,7 +302,8 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
                                                           const int4* __restrict__ items,
                                                           const int32_t* __restrict__ nitems,
                                                           int nb, int n, int ls, int H, int nbands,
-                                                          int64_t M, float* __restrict__ A,
+                                                          int64_t M, int64_t ncols,
+                                                          float* __restrict__ A,
                                                           double* __restrict__ tau) {
   extern __shared__ float2 P2[];  // H rows of the bordered pair array, row stride ls
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
@@ -310,15 +313,19 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   const int np = n + 2;
   if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
     if (wave >= len) return;
-    const int64_t j = order[start + wave];
+    const int64_t j = order[start + wave], j2 = ncols - 1 - j;
     float* col = A + j * M;
+    float* col2 = A + j2 * M;
     for (int a = 0; a < n; ++a)
 #pragma unroll
       for (int v = 0; v < E; ++v) {
         const int b = lane + 64 * v;
-        if (FULL || b < n) __builtin_nontemporal_store(0.0f, col + a * n + b);
+        if (FULL || b < n) {
+          __builtin_nontemporal_store(0.0f, col + a * n + b);
+          __builtin_nontemporal_store(0.0f, col2 + a * n + b);
+        }
       }
-    if (lane == 0) tau[j] = 0.0;
+    if (lane == 0) tau[j] = tau[j2] = 0.0;
     return;
   }
   const float* Pk = cube + (int64_t)bkt * M;
@@ -331,7 +338,11 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
     j = order[start + wave];
     g = geo[j];
   }
+  // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
+  const int64_t j2 = ncols - 1 - j;
+  const bool pair = j2 != j;
   float* col = A + j * M;
+  float* col2 = A + j2 * M;
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   double ctux[E], mstux[E];
@@ -463,6 +474,7 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
         val = fmaf(tfy * tfx, q11, val);
         val = ok ? val : 0.0f;
         __builtin_nontemporal_store(val, col + a * n + b);
+        if (pair) __builtin_nontemporal_store(val, col2 + (n - 1 - a) * n + (n - 1 - b));
         rowsum += val;
       }
       tsum += (double)rowsum;
@@ -470,7 +482,10 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   }
   if (!live) return;
   tsum = wave_sum_f64(tsum);
-  if (lane == 0) tau[j] = tsum;
+  if (lane == 0) {
+    tau[j] = tsum;
+    if (pair) tau[j2] = tsum;
+  }
 }
 
 // ------------------------------------------- 16-bit build, slot order -----
@@ -1465,8 +1480,11 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
                             float* A32, double* tau, void* scratch, hipStream_t s) {
   if (build_orbit_supported(n, K, N)) return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, s);
   const int64_t ncols = (int64_t)N * N;
+  // banded pairs: the first half of the columns (and the centre of an odd
+  // grid), each written with its half turn; otherwise every column
+  const int64_t nsort = pair_fits_lds(n) ? ncols : (ncols + 1) / 2;
   BucketPlan bp;
-  hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
+  hipError_t e = launch_bucket_sort(geo, nsort, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
   const int32_t* order = bp.order;
   const int4* items = bp.items;
@@ -1484,8 +1502,8 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
       const void* fn = reinterpret_cast<const void*>(kern);
       hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return err;
-      kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, ls, H, nbands, M, A32,
-                                   tau);
+      kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, ls, H, nbands, M,
+                                   ncols, A32, tau);
       return hipGetLastError();
     };
     switch (lds_e(n)) {  // n > 141 here
