@@ -340,6 +340,99 @@ __global__ __launch_bounds__(256) void grouped_pack_kernel(const GPack* __restri
   }
 }
 
+// Scene exponents and packing in one kernel when every library of the plan
+// has at most kStageMaxCols columns: one 1024-thread workgroup per (scene
+// group, slot r < 16) stages its scene in LDS (coalesced loads), takes f_s
+// from the LDS copy (as grouped_scene_exp_kernel) and writes columns r and
+// 16 + r of every 8-slot group of the group's operand, gathering the slots
+// from LDS (gathered straight from HBM, every 4-byte value costs a sector).
+// The 16 slots of a scene group write the 512-byte blocks of its operand
+// together; they are numbered to land on one XCD back to back (dispatch is
+// round-robin over the 8 XCDs), so the blocks fill in that XCD's L2.  Slots
+// past the group's scenes write zeros.
+template <bool BF16>
+__global__ __launch_bounds__(1024) void grouped_stage_pack_kernel(const GPack* __restrict__ packs,
+                                                                  int64_t npacks,
+                                                                  const GScene* __restrict__ slots,
+                                                                  int32_t* __restrict__ fexp,
+                                                                  u32x4* __restrict__ bpk) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float zl[];  // the scene
+  __shared__ double red[16];
+  __shared__ int s_f;
+  const int64_t wg = blockIdx.x, xcd = wg % 8, rnd = wg / 8;
+  const int64_t gi = xcd + 8 * (rnd / kGrpScenes);
+  const int r = (int)(rnd % kGrpScenes);
+  if (gi >= npacks) return;  // uniform: padding workgroups of the grid
+  const GPack pk = packs[gi];
+  const int tid = threadIdx.x;
+  u32x4* dst = bpk + pk.bpk;
+  if (r >= pk.nscenes) {
+    for (int64_t g = tid; g < pk.ngroups; g += 1024) {
+      dst[g * 32 + r] = (u32x4){0u, 0u, 0u, 0u};
+      dst[g * 32 + 16 + r] = (u32x4){0u, 0u, 0u, 0u};
+    }
+    return;
+  }
+  const GScene sc = slots[pk.slot0 + r];
+  double m = 0.0;
+  const bool vec = (sc.ncols % 4) == 0 && (reinterpret_cast<uintptr_t>(sc.z) % 16) == 0 &&
+                   (reinterpret_cast<uintptr_t>(sc.exps) % 16) == 0;
+  if (vec) {
+    for (int64_t j = 4 * (int64_t)tid; j < sc.ncols; j += 4 * 1024) {
+      const f32x4 z = *reinterpret_cast<const f32x4*>(sc.z + j);
+      const i32x4 e = *reinterpret_cast<const i32x4*>(sc.exps + j);
+      *reinterpret_cast<f32x4*>(zl + j) = z;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m = fmax(m, ldexp((double)fabsf(z[q]), e[q]));
+    }
+  } else {
+    for (int64_t j = tid; j < sc.ncols; j += 1024) {
+      const float z = sc.z[j];
+      zl[j] = z;
+      m = fmax(m, ldexp((double)fabsf(z), sc.exps[j]));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double mm = red[0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) mm = fmax(mm, red[w]);
+    int f = 0;
+    if (mm > 0.0) {
+      int E;
+      (void)frexp(mm, &E);
+      f = 15 - E;
+    }
+    s_f = f;
+    fexp[pk.slot0 + r] = f;
+  }
+  __syncthreads();
+  const int f = s_f;
+  for (int64_t g = tid; g < pk.ngroups; g += 1024) {
+    const i32x4 p0 = *reinterpret_cast<const i32x4*>(pk.perm + 8 * g);
+    const i32x4 p1 = *reinterpret_cast<const i32x4*>(pk.perm + 8 * g + 4);
+    const i32x4 e0 = *reinterpret_cast<const i32x4*>(pk.eslot + 8 * g);
+    const i32x4 e1 = *reinterpret_cast<const i32x4*>(pk.eslot + 8 * g + 4);
+    uint32_t hi[4] = {0u, 0u, 0u, 0u}, lo[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int32_t j = u < 4 ? p0[u] : p1[u - 4];
+      const int32_t e = u < 4 ? e0[u] : e1[u - 4];
+      const float v = (j >= 0) ? ldexpf(zl[j], e + f) : 0.0f;
+      const uint16_t h = g16_round<BF16>(v);
+      const uint16_t l = g16_round<BF16>(v - g16_value<BF16>(h));
+      hi[u >> 1] |= (uint32_t)h << (16 * (u & 1));
+      lo[u >> 1] |= (uint32_t)l << (16 * (u & 1));
+    }
+    dst[g * 32 + r] = (u32x4){hi[0], hi[1], hi[2], hi[3]};
+    dst[g * 32 + 16 + r] = (u32x4){lo[0], lo[1], lo[2], lo[3]};
+  }
+}
+
 template <bool BF16>
 __device__ __forceinline__ f32x16 g16_mfma(const u32x4 a, const u32x4 b, const f32x16 c) {
   typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -661,6 +754,18 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
   const int64_t per_cu = 4;  // resident workgroups per CU the persistent grid aims at
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cus * per_cu));
 
+  // 16-bit scenes staged whole in LDS for packing when every library allows
+  int64_t maxcols = 0;
+  for (const GPack& pk : p.packs) maxcols = std::max<int64_t>(maxcols, pk.ncols);
+  const bool staged = g->storage != PSFLIB_FP32 && maxcols <= kStageMaxCols;
+  const size_t stage_lds = (size_t)maxcols * 4;
+  if (staged) {
+    e = hipFuncSetAttribute(g->storage == PSFLIB_BF16_POW2
+                                ? reinterpret_cast<const void*>(grouped_stage_pack_kernel<true>)
+                                : reinterpret_cast<const void*>(grouped_stage_pack_kernel<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_lds);
+    if (e != hipSuccess) return e;
+  }
   hipStream_t cap;
   e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
@@ -673,13 +778,23 @@ static hipError_t instantiate(psflib_grouped* g, const std::vector<LibInfo>& lib
         grouped_f32_kernel<<<grid, kGrpThreads, 0, cap>>>(items, nitems,
                                                           reinterpret_cast<const f32x4*>(bpk), part, im);
       } else {
-        grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 1024, 0, cap>>>(slots, fexp);
-        const dim3 np((unsigned)p.packs.size(), 64);  // 64 workgroups per scene group
         const bool bf = g->storage == PSFLIB_BF16_POW2;
-        if (bf)
-          grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
-        else
-          grouped_pack_kernel<false><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
+        if (staged) {
+          // whole rounds of 8 XCDs x 16 slots
+          const int64_t npk = (int64_t)p.packs.size();
+          const unsigned sgrid = (unsigned)((npk + 7) / 8 * 8 * kGrpScenes);
+          if (bf)
+            grouped_stage_pack_kernel<true><<<sgrid, 1024, stage_lds, cap>>>(packs, npk, slots, fexp, bpk);
+          else
+            grouped_stage_pack_kernel<false><<<sgrid, 1024, stage_lds, cap>>>(packs, npk, slots, fexp, bpk);
+        } else {
+          grouped_scene_exp_kernel<<<(unsigned)p.slots.size(), 1024, 0, cap>>>(slots, fexp);
+          const dim3 np((unsigned)p.packs.size(), 64);  // 64 workgroups per scene group
+          if (bf)
+            grouped_pack_kernel<true><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
+          else
+            grouped_pack_kernel<false><<<np, 256, 0, cap>>>(packs, sc, fexp, bpk);
+        }
         auto run = [&](auto kern) { kern<<<grid, kGrpThreads, 0, cap>>>(items, nitems, bpk, fexp, part, im); };
         switch (shape.rows) {
           case 64: bf ? run(grouped_h16_kernel<true, 4>) : run(grouped_h16_kernel<false, 4>); break;
