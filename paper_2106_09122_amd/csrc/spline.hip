@@ -218,8 +218,12 @@ __host__ __device__ inline int cubic_band_rows(int Np) {
 // rows that overlap by 3, band b holding extended rows [b (H-3), b (H-3) + H);
 // the 4 tap rows of a pixel, from its (clamped) origin row R - 1 on, all lie
 // in band min((R - 1) / (H-3), last), so each pixel is produced in exactly
-// one band.  A work item is up to kLdsCols columns of one bracket (columns
-// grouped on the device), one wave per column.  A wave walks its column in
+// one band.  A work item is up to kLdsCols columns of one bracket (columns of
+// the first half of the scene grid, and the centre of an odd grid, grouped on
+// the device), one wave per column, which writes every element also to the
+// half-turned column N^2-1-j at the mirrored pixel (n-1-a, n-1-b): that
+// column's tap coordinates there are the same float64 values, so its entry is
+// the same.  A wave walks its column in
 // tiles of 8 x 8 image pixels (lane l: row 8 a' + l / 8, column 8 b' + l % 8),
 // so the 64 stencils of one LDS read cover a compact rotated patch of the
 // array rather than a 64-pixel line: with the row stride at 5 mod 8 pairs
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
     const float2* __restrict__ pairs, int Np, int ls, int H, int nbands,
     const ColGeom* __restrict__ geo, const int32_t* __restrict__ order,
     const int4* __restrict__ items, const int32_t* __restrict__ nitems, int nb, int n, int64_t M,
-    float* __restrict__ A, double* __restrict__ tau) {
+    int64_t ncols, float* __restrict__ A, double* __restrict__ tau) {
 #pragma clang fp contract(off)
   extern __shared__ float2 band[];  // H rows of the extended array, stride ls
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
@@ -246,11 +250,15 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
   const int nt = (n + 7) / 8;               // tiles per side
   if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
     if (wave >= len) return;
-    const int64_t j = order[start + wave];
+    const int64_t j = order[start + wave], j2 = ncols - 1 - j;
     float* col = A + j * M;
+    float* col2 = A + j2 * M;
     for (int a = 0; a < n; ++a)
-      for (int b = lane; b < n; b += 64) __builtin_nontemporal_store(0.0f, col + a * n + b);
-    if (lane == 0) tau[j] = 0.0;
+      for (int b = lane; b < n; b += 64) {
+        __builtin_nontemporal_store(0.0f, col + a * n + b);
+        __builtin_nontemporal_store(0.0f, col2 + a * n + b);
+      }
+    if (lane == 0) tau[j] = tau[j2] = 0.0;
     return;
   }
   const float2* src = pairs + (int64_t)bkt * Np * Np;
@@ -263,7 +271,12 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
     j = order[start + wave];
     g = geo[j];
   }
+  // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
+  // (its tap coordinates are the same float64 values, the products negated twice)
+  const int64_t j2 = ncols - 1 - j;
+  const bool pair = j2 != j;
   float* col = A + j * M;
+  float* col2 = A + j2 * M;
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   const double pad = (double)kSplinePad;
@@ -325,13 +338,17 @@ __global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
         }
         const float val = fmaf(wk1, Y, wk0 * X);
         col[a * n + b] = val;
+        if (pair) col2[(n - 1 - a) * n + (n - 1 - b)] = val;
         tsum += (double)val;
       }
     }
   }
   if (!live) return;
   tsum = wave_sum(tsum);
-  if (lane == 0) tau[j] = tsum;
+  if (lane == 0) {
+    tau[j] = tsum;
+    if (pair) tau[j2] = tsum;
+  }
 }
 
 }  // namespace
@@ -400,8 +417,10 @@ size_t build_cubic_lds_scratch_bytes(int K, int64_t ncols) { return bucket_scrat
 hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo, int n, int64_t M,
                                   int64_t ncols, float* A32, double* tau, void* scratch,
                                   hipStream_t s) {
+  // the first half of the columns (and the centre of an odd grid), each
+  // written with its half turn
   BucketPlan bp;
-  hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
+  hipError_t e = launch_bucket_sort(geo, (ncols + 1) / 2, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
   const int Np = n + 2 * kSplinePad, Ne = cubic_ext(Np), ls = cubic_stride(Np);
   const int H = cubic_band_rows(Np);
@@ -413,7 +432,7 @@ hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(P, Np, ls, H, nbands, geo, bp.order, bp.items,
-                                                   bp.nitems, bp.nb, n, M, A32, tau);
+                                                   bp.nitems, bp.nb, n, M, ncols, A32, tau);
     return hipGetLastError();
   };
   return launch(build_cubic_lds_kernel);
