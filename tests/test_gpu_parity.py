@@ -164,6 +164,10 @@ SHAPES = [
     (133, 9, 0.45, 3, "nonuniform", "linear", "zero"),
     # 22500 scene pixels: the 16-bit batched product stages each scene in 88 KiB of LDS
     (8, 150, 0.1, 3, "linear", "linear", "clamp"),
+    # scene sides that are multiples of 8 (the 16-bit orbit build): partial 8 x 32
+    # tiles, zero columns past the last offset, odd PSF sides, nearest samples
+    (20, 16, 0.6, 5, "linear", "linear", "zero"),
+    (33, 24, 0.3, 4, "nonuniform", "nearest", "zero"),
     # bordered PSF pairs larger than the LDS: staged in row bands (2, 3 and 4
     # bands; 199 also takes the scalar staging loads and partial lanes)
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
@@ -208,7 +212,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:9] + [SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + [SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
