@@ -302,9 +302,12 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
                                                           const int4* __restrict__ items,
                                                           const int32_t* __restrict__ nitems,
                                                           int nb, int n, int ls, int H, int nbands,
-                                                          int64_t M, int64_t ncols,
-                                                          float* __restrict__ A,
+                                                          int64_t M, int64_t ncols, int64_t jbase,
+                                                          float* __restrict__ A_lo,
+                                                          float* __restrict__ A_hi, int64_t p0,
                                                           double* __restrict__ tau) {
+  // order[] holds columns relative to jbase (absolute column jbase + j, at
+  // A_lo + j M); the half turn j2 = ncols-1-(jbase+j) goes to A_hi + (j2 - p0) M
   extern __shared__ float2 P2[];  // H rows of the bordered pair array, row stride ls
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
@@ -313,16 +316,16 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   const int np = n + 2;
   if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
     if (wave >= len) return;
-    const int64_t j = order[start + wave], j2 = ncols - 1 - j;
-    float* col = A + j * M;
-    float* col2 = A + j2 * M;
+    const int64_t jr = order[start + wave], j = jbase + jr, j2 = ncols - 1 - j;
+    float* col = A_lo + jr * M;
+    float* col2 = A_hi + (j2 - p0) * M;
     for (int a = 0; a < n; ++a)
 #pragma unroll
       for (int v = 0; v < E; ++v) {
         const int b = lane + 64 * v;
         if (FULL || b < n) {
           __builtin_nontemporal_store(0.0f, col + a * n + b);
-          __builtin_nontemporal_store(0.0f, col2 + a * n + b);
+          if (j2 != j) __builtin_nontemporal_store(0.0f, col2 + a * n + b);
         }
       }
     if (lane == 0) tau[j] = tau[j2] = 0.0;
@@ -331,18 +334,18 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   const float* Pk = cube + (int64_t)bkt * M;
   const float* Pk1 = (K > 1) ? Pk + M : nullptr;
   const bool live = wave < len;
-  int64_t j = 0;
+  int64_t jr = 0;
   ColGeom g;
   g.ct = 1.0; g.st = 0.0; g.w = 0.0;
   if (live) {
-    j = order[start + wave];
-    g = geo[j];
+    jr = order[start + wave];
+    g = geo[jbase + jr];
   }
   // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
-  const int64_t j2 = ncols - 1 - j;
+  const int64_t j = jbase + jr, j2 = ncols - 1 - j;
   const bool pair = j2 != j;
-  float* col = A + j * M;
-  float* col2 = A + j2 * M;
+  float* col = A_lo + jr * M;
+  float* col2 = A_hi + (j2 - p0) * M;
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   double ctux[E], mstux[E];
@@ -777,9 +780,11 @@ template <bool BF16>
 __global__ __launch_bounds__(256) void pack16_kernel(const float* __restrict__ A32,
                                                      const ColGeom* __restrict__ geo,
                                                      int64_t M, int64_t ncols,
-                                                     u32x4* __restrict__ Mp) {
+                                                     u32x4* __restrict__ Mp, int64_t g0,
+                                                     int64_t col0) {
+  // groups g0 + blockIdx.y; column j of the float32 source at A32 + (j - col0) M
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
-  const int64_t grp = blockIdx.y;
+  const int64_t grp = g0 + blockIdx.y;
   if (i0 >= M) return;
   const bool pair = (M % 2) == 0;  // then i0 + 1 < M and the 8-byte loads are aligned
   float v[8][2];
@@ -791,7 +796,7 @@ __global__ __launch_bounds__(256) void pack16_kernel(const float* __restrict__ A
     ex[u] = 0;
     if (j < ncols) {
       ex[u] = geo[j].e;
-      const float* src = A32 + j * M + i0;
+      const float* src = A32 + (j - col0) * M + i0;
       if (pair) {
         typedef float f32x2 __attribute__((ext_vector_type(2)));
         const f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src));
@@ -1385,12 +1390,19 @@ hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* sc
 
 hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int64_t M,
                          int64_t ncols, int64_t ncols_pad, void* lib, hipStream_t s) {
-  const dim3 pgrid((unsigned)((M + 511) / 512), (unsigned)(ncols_pad / 8));
+  return launch_pack16_range(storage, A32, 0, 0, ncols_pad / 8, geo, M, ncols, lib, s);
+}
+
+hipError_t launch_pack16_range(int storage, const float* A32, int64_t col0, int64_t g0, int64_t g1,
+                               const ColGeom* geo, int64_t M, int64_t ncols, void* lib,
+                               hipStream_t s) {
+  if (g1 <= g0) return hipSuccess;
+  const dim3 pgrid((unsigned)((M + 511) / 512), (unsigned)(g1 - g0));
   u32x4* Mp = reinterpret_cast<u32x4*>(lib);
   if (storage == PSFLIB_BF16_POW2)
-    pack16_kernel<true><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+    pack16_kernel<true><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp, g0, col0);
   else
-    pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp);
+    pack16_kernel<false><<<pgrid, 256, 0, s>>>(A32, geo, M, ncols, Mp, g0, col0);
   return hipGetLastError();
 }
 
@@ -1472,6 +1484,30 @@ hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGe
   return e;
 }
 
+// the banded build over the sorted columns of `bp` (relative to jbase, see
+// build_band_kernel)
+static hipError_t launch_band(const float* cube, int K, const ColGeom* geo, const BucketPlan& bp,
+                              int n, int64_t M, int64_t ncols, int64_t jbase, float* A_lo,
+                              float* A_hi, int64_t p0, double* tau, hipStream_t s) {
+  const int ls = band_stride(n), H = band_rows(n), np = n + 2;
+  const int nbands = (np - 1 + (H - 1) - 1) / (H - 1);
+  const size_t lds = (size_t)H * ls * sizeof(float2);
+  const bool full = (n % 64) == 0;
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(cube, K, geo, bp.order, bp.items, bp.nitems, bp.nb,
+                                                   n, ls, H, nbands, M, ncols, jbase, A_lo, A_hi, p0,
+                                                   tau);
+    return hipGetLastError();
+  };
+  switch (lds_e(n)) {  // n > 141 here
+    case 3: return full ? launch(build_band_kernel<3, true>) : launch(build_band_kernel<3, false>);
+    default: return full ? launch(build_band_kernel<4, true>) : launch(build_band_kernel<4, false>);
+  }
+}
+
 static bool build_orbit_supported(int n, int K, int N);
 static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
                                      int64_t M, float* A32, double* tau, void* scratch, hipStream_t s);
@@ -1494,23 +1530,7 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
 
   const unsigned grid = (unsigned)items_max;
   const bool full = (n % 64) == 0;
-  if (!pair_fits_lds(n)) {
-    const int ls = band_stride(n), H = band_rows(n), np = n + 2;
-    const int nbands = (np - 1 + (H - 1) - 1) / (H - 1);
-    const size_t lds = (size_t)H * ls * sizeof(float2);
-    auto launch = [&](auto kern) -> hipError_t {
-      const void* fn = reinterpret_cast<const void*>(kern);
-      hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (err != hipSuccess) return err;
-      kern<<<grid, 1024, lds, s>>>(cube, K, geo, order, items, nitems, nb, n, ls, H, nbands, M,
-                                   ncols, A32, tau);
-      return hipGetLastError();
-    };
-    switch (lds_e(n)) {  // n > 141 here
-      case 3: return full ? launch(build_band_kernel<3, true>) : launch(build_band_kernel<3, false>);
-      default: return full ? launch(build_band_kernel<4, true>) : launch(build_band_kernel<4, false>);
-    }
-  }
+  if (!pair_fits_lds(n)) return launch_band(cube, K, geo, bp, n, M, ncols, 0, A32, A32, 0, tau, s);
   const int ls = lds_stride(n);
   const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
   const void* fn;
@@ -1656,4 +1676,42 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
   return orbit_finish(pl, tau, s);
 }
 
+
+// 16-bit libraries of banded PSF pairs, staged through float32 a chunk of
+// columns at a time: chunk [c0, c1) of the first half of the scene grid and
+// its half turns [N^2-c1, N^2-c0) are built into the staging buffer (2 CH
+// columns) and packed before the next chunk, so the staging needs 2 CH n^2
+// floats instead of the whole float32 library.  N % 16 == 0 (whole 8-column
+// groups on both sides, no centre column).
+static int64_t band16_chunk(int N) {
+  const int64_t nhalf = (int64_t)N * N / 2;
+  return nhalf < kBand16ChunkCols ? nhalf : kBand16ChunkCols;
+}
+
+bool build_band16_chunked_supported(int n, int K, int N) {
+  return !pair_fits_lds(n) && build_lds_supported(n, K) && N % 16 == 0;
+}
+
+size_t band16_stage_bytes(int N, int64_t M) { return (size_t)2 * band16_chunk(N) * (size_t)M * 4; }
+
+hipError_t launch_build_band16_chunked(int storage, const float* cube, int K, const ColGeom* geo,
+                                       int n, int N, int64_t M, void* lib, double* tau,
+                                       void* scratch, float* stage, hipStream_t s) {
+  const int64_t ncols = (int64_t)N * N, nhalf = ncols / 2, CH = band16_chunk(N);
+  float* A_hi = stage + CH * M;
+  for (int64_t c0 = 0; c0 < nhalf; c0 += CH) {
+    const int64_t c1 = (c0 + CH < nhalf) ? c0 + CH : nhalf;
+    BucketPlan bp;
+    hipError_t e = launch_bucket_sort(geo + c0, c1 - c0, K, scratch, &bp, s);
+    if (e != hipSuccess) return e;
+    e = launch_band(cube, K, geo, bp, n, M, ncols, c0, stage, A_hi, ncols - c1, tau, s);
+    if (e != hipSuccess) return e;
+    e = launch_pack16_range(storage, stage, c0, c0 / 8, c1 / 8, geo, M, ncols, lib, s);
+    if (e != hipSuccess) return e;
+    e = launch_pack16_range(storage, A_hi, ncols - c1, (ncols - c1) / 8, (ncols - c0) / 8, geo, M,
+                            ncols, lib, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 }  // namespace psflib

@@ -336,6 +336,10 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                         psflib::build_lds16_supported(desc->n, K, L.ncols);
   const bool orbit16 = direct16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
+  // banded 16-bit builds without the rescale stage through float32 a chunk of
+  // columns at a time (each chunk packed before the next)
+  const bool band16 = stage32 && !cubic && !flux &&
+                      psflib::build_band16_chunked_supported(desc->n, K, desc->N);
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
       spline_bytes + align256(orbit16    ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
@@ -344,7 +348,9 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               : lds    ? psflib::build_lds_scratch_bytes(K, desc->N, desc->n)
                               : cubic  ? 0
                                        : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
-  const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
+  const size_t stage_bytes = align256(band16    ? psflib::band16_stage_bytes(desc->N, L.M)
+                                      : stage32 ? (size_t)L.ncols * (size_t)L.M * 4
+                                                : 0);
   const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
   void* tmp = nullptr;
@@ -405,6 +411,10 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                    reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
                                    path_tmp, s);
     if (e != hipSuccess) return bail(e, "16-bit LDS build kernels");
+  } else if (band16) {
+    e = psflib::launch_build_band16_chunked(storage, d_cube, K, h->geo, desc->n, desc->N, L.M, d_lib,
+                                            tau, path_tmp, A32, s);
+    if (e != hipSuccess) return bail(e, "16-bit banded build kernels");
   } else if (lds) {
     e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, desc->N, L.M,
                                  reinterpret_cast<float*>(bdst), tau, path_tmp, s);
@@ -423,7 +433,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                     L.ncols, tau, exps, storage != PSFLIB_FP32, s);
     if (e != hipSuccess) return bail(e, "flux rescale kernel");
   }
-  if (stage32) {
+  if (stage32 && !band16) {
     e = psflib::launch_pack16(storage, A32, h->geo, L.M, L.ncols, L.ncols_pad, d_lib, s);
     if (e != hipSuccess) return bail(e, "16-bit packing kernel");
   }
