@@ -319,7 +319,8 @@ psflib_status psflib_grouped_shape(const psflib_grouped* g, int64_t* chunk, int3
  * item, 64, 128 or 256 for 16-bit plans and 256 for FP32 (else
  * PSFLIB_ERR_INVALID_ARG).  Waits for the plan's
  * earlier runs; synchronises `stream`.  The images are unchanged until the
- * next run. */
+ * next run.  Not to be called while another thread runs or destroys the
+ * same plan. */
 psflib_status psflib_grouped_set_shape(psflib_grouped* g, int64_t chunk, int32_t rows, void* stream);
 
 /* Free the plan.  Waits on the host for the plan's own launches (events

@@ -380,22 +380,39 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_h16_kernel(const u32x4* _
     const int64_t i = row0 + tid + (int64_t)kAdjThreads * u;
     gr[u] = (i < M) ? g[i] : 0.0f;
   }
-  const int64_t gb = (int64_t)blockIdx.x * kAdjColsPerBlock;
-  for (int t = 0; t < kAdjColsPerBlock; ++t) {
+  const int64_t gb = (int64_t)blockIdx.x * kAdj16GroupsPerBlock;
+  for (int t = 0; t < kAdj16GroupsPerBlock; ++t) {
     const int64_t grp = gb + t;
     if (grp >= ngroups) break;
     float acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0f;
-#pragma unroll 8
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = row0 + tid + (int64_t)kAdjThreads * u;
-      if (i < M) {
-        const u32x4 p = __builtin_nontemporal_load(Mp + grp * M + i);
-        float f[8];
-        unpack8<BF16>(p, f);
+    const u32x4* src = Mp + grp * M + row0 + tid;
+    if (row0 + kAdj16Rows <= M) {  // uniform: every row of the block is in the image
+      // blocks of 16 loads issued together, then consumed in order
+      for (int u0 = 0; u0 < U; u0 += 16) {
+        u32x4 p[16];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = fmaf(f[q], gr[u], acc[q]);
+        for (int u = 0; u < 16; ++u) p[u] = __builtin_nontemporal_load(src + (int64_t)kAdjThreads * (u0 + u));
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          float f[8];
+          unpack8<BF16>(p[u], f);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[q] = fmaf(f[q], gr[u0 + u], acc[q]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = row0 + tid + (int64_t)kAdjThreads * u;
+        if (i < M) {
+          const u32x4 p = __builtin_nontemporal_load(src + (int64_t)kAdjThreads * u);
+          float f[8];
+          unpack8<BF16>(p, f);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[q] = fmaf(f[q], gr[u], acc[q]);
+        }
       }
     }
 #pragma unroll
@@ -451,7 +468,7 @@ hipError_t launch_adjoint(int storage, const void* lib, const Cols16& cx, const 
       adjoint_f32_kernel<false><<<grid, kAdjThreads, 0, s>>>(A, g, dst, M, ncols, stride);
   } else {
     const int64_t ngroups = ncols_pad / 8;
-    const dim3 grid((unsigned)((ngroups + kAdjColsPerBlock - 1) / kAdjColsPerBlock), (unsigned)nb);
+    const dim3 grid((unsigned)((ngroups + kAdj16GroupsPerBlock - 1) / kAdj16GroupsPerBlock), (unsigned)nb);
     const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
     const int apply_exp = (nb > 1) ? 0 : 1;
     if (storage == PSFLIB_BF16_POW2)

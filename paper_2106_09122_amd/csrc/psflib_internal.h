@@ -36,7 +36,8 @@ constexpr int64_t kStageMaxCols = 32768;  // batched 16-bit: scenes staged whole
 constexpr int kAdjThreads = 256;     // adjoint threads per workgroup
 constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 float4 per thread)
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
-constexpr int kAdjColsPerBlock = 16; // columns (FP32) or 8-column groups (16-bit) per workgroup
+constexpr int kAdjColsPerBlock = 16; // FP32 adjoint: columns per workgroup
+constexpr int kAdj16GroupsPerBlock = 2;  // 16-bit adjoint: 8-column groups per workgroup
 constexpr int kColPad = 64;          // 16-bit column count padded to a multiple of this
 constexpr int32_t kZeroColumnExp = PSFLIB_ZERO_COLUMN_EXPONENT;  // exponent of an identically zero column
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
