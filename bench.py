@@ -416,6 +416,9 @@ def main():
                    "GB_per_s": (M * ((ncols + 63) // 64 * 64) * 2 + 4 * (M + 2 * ncols)) / (ms16 * 1e-3) / 1e9,
                    "speedup_vs_fp32": ms / ms16,
                    "peak_normalised_error_vs_fp32": err}
+            t_adj16 = _timed(torch, lambda: lh.apply_adjoint(g, out=grad), args.steps // 2, 10)
+            ent["adjoint_us"] = t_adj16 * 1e3
+            ent["adjoint_GB_per_s"] = M * ((ncols + 63) // 64 * 64) * 2 / (t_adj16 * 1e-3) / 1e9
             for bi, (B, Zb_h) in enumerate(batches.items()):
                 Zb = torch.from_numpy(Zb_h).to(dev)
                 out = torch.empty((B, M), device=dev, dtype=torch.float32)

@@ -399,7 +399,8 @@ __global__ __launch_bounds__(256) void pack_scenes_kernel(const float* __restric
 // Scenes of at most kStageMaxCols columns are packed by one workgroup of 1024
 // threads per scene that reads the scene once, coalesced (the slot order
 // gathers columns from all over the scene: read straight from HBM, each
-// 4-byte value would cost a sector): the scene into LDS (16-byte loads), f_b
+// 4-byte value would cost a sector): the scene into LDS (16-byte loads, all
+// of a thread's issued before their use), f_b
 // from it (as scene_exponent_kernel), then the slots in order, gathered from
 // LDS, scaled by 2^(eslot + f_b) and rounded, each group's 16 bytes written to
 // its place Zg[g][b] of the operand.  A workgroup writes one 16-byte piece of
@@ -433,12 +434,28 @@ __global__ __launch_bounds__(1024) void stage_slots16_kernel(const float* __rest
   const float* z = Z + b * ncols;
   double m = 0.0;
   if constexpr (VEC) {
-    for (int64_t j = 4 * (int64_t)tid; j < ncols; j += 4 * 1024) {
-      const f32x4 v = *reinterpret_cast<const f32x4*>(z + j);
-      const i32x4 e = *reinterpret_cast<const i32x4*>(exps + j);
-      *reinterpret_cast<f32x4*>(zl + j) = v;
+    // batches of 4 independent 16-byte loads per thread (all of a 16384-column
+    // scene in one batch), then their use
+    for (int64_t j0 = 4 * (int64_t)tid; j0 < ncols; j0 += 4 * 4 * 1024) {
+      f32x4 v[4];
+      i32x4 e[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) m = fmax(m, ldexp((double)fabsf(v[q]), e[q]));
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + 4 * 1024 * u;
+        if (j < ncols) {
+          v[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(z + j));
+          e[u] = *reinterpret_cast<const i32x4*>(exps + j);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + 4 * 1024 * u;
+        if (j < ncols) {
+          *reinterpret_cast<f32x4*>(zl + j) = v[u];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) m = fmax(m, ldexp((double)fabsf(v[u][q]), e[u][q]));
+        }
+      }
     }
   } else {
     for (int64_t j = tid; j < ncols; j += 1024) {
@@ -466,19 +483,158 @@ __global__ __launch_bounds__(1024) void stage_slots16_kernel(const float* __rest
   }
   __syncthreads();
   const int f = s_f;
-  for (int64_t g = tid; g < ngroups; g += 1024) {
-    const i32x4 p0 = *reinterpret_cast<const i32x4*>(perm + 8 * g);
-    const i32x4 p1 = *reinterpret_cast<const i32x4*>(perm + 8 * g + 4);
-    const i32x4 e0 = *reinterpret_cast<const i32x4*>(eslot + 8 * g);
-    const i32x4 e1 = *reinterpret_cast<const i32x4*>(eslot + 8 * g + 4);
-    uint32_t h[8];
+  // two groups per thread per batch: the slot maps of both loaded first
+  for (int64_t g0 = tid; g0 < ngroups; g0 += 2 * 1024) {
+    i32x4 p0[2], p1[2], e0[2], e1[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      h[q] = to16(ldexpf(p0[q] >= 0 ? zl[p0[q]] : 0.0f, e0[q] + f), BF16);
-      h[4 + q] = to16(ldexpf(p1[q] >= 0 ? zl[p1[q]] : 0.0f, e1[q] + f), BF16);
+    for (int u = 0; u < 2; ++u) {
+      const int64_t g = g0 + 1024 * u;
+      if (g < ngroups) {
+        p0[u] = *reinterpret_cast<const i32x4*>(perm + 8 * g);
+        p1[u] = *reinterpret_cast<const i32x4*>(perm + 8 * g + 4);
+        e0[u] = *reinterpret_cast<const i32x4*>(eslot + 8 * g);
+        e1[u] = *reinterpret_cast<const i32x4*>(eslot + 8 * g + 4);
+      }
     }
-    Zg[g * Bp + b] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                             h[6] | (h[7] << 16)};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t g = g0 + 1024 * u;
+      if (g < ngroups) {
+        uint32_t h[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          h[q] = to16(ldexpf(p0[u][q] >= 0 ? zl[p0[u][q]] : 0.0f, e0[u][q] + f), BF16);
+          h[4 + q] = to16(ldexpf(p1[u][q] >= 0 ? zl[p1[u][q]] : 0.0f, e1[u][q] + f), BF16);
+        }
+        Zg[g * Bp + b] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                 h[6] | (h[7] << 16)};
+      }
+    }
+  }
+}
+
+// Two scenes per workgroup, for scenes of at most kStagePairCols columns (both
+// in LDS): the same steps as stage_slots16_kernel, with lanes 2i and 2i+1
+// packing one group of the two scenes, so each pair of lanes writes 32
+// contiguous bytes of the operand line (half as many L2 write requests).
+// Scenes 2q, 2q+1 of the 4 pairs of an 8-scene line are numbered to run on
+// one XCD back to back.
+template <bool BF16, bool VEC>
+__global__ __launch_bounds__(1024) void stage_pairs16_kernel(const float* __restrict__ Z,
+                                                             const int32_t* __restrict__ exps,
+                                                             const int32_t* __restrict__ perm,
+                                                             const int32_t* __restrict__ eslot,
+                                                             int64_t ncols, int64_t ngroups,
+                                                             int64_t bc, int64_t Bp,
+                                                             int32_t* __restrict__ fexp,
+                                                             u32x4* __restrict__ Zg) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float zl[];  // the two scenes, ncols floats each
+  __shared__ double red[2][16];
+  __shared__ int s_f[2];
+  const int64_t wg = blockIdx.x, xcd = wg % 8, rnd = wg / 8;
+  const int64_t b0 = 2 * (4 * (xcd + 8 * (rnd / 4)) + rnd % 4);
+  const int tid = threadIdx.x;
+  if (b0 >= bc) {
+    for (int64_t t = tid; t < 2 * ngroups; t += 1024) Zg[(t >> 1) * Bp + b0 + (t & 1)] = (u32x4){0u, 0u, 0u, 0u};
+    return;
+  }
+  const bool live1 = b0 + 1 < bc;
+  const float* z0 = Z + b0 * ncols;
+  const float* z1 = live1 ? z0 + ncols : z0;
+  float* zl1 = zl + ncols;
+  double m0 = 0.0, m1 = 0.0;
+  if constexpr (VEC) {
+    for (int64_t j0 = 4 * (int64_t)tid; j0 < ncols; j0 += 4 * 4 * 1024) {
+      f32x4 v0[4], v1[4];
+      i32x4 e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + 4 * 1024 * u;
+        if (j < ncols) {
+          v0[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(z0 + j));
+          v1[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(z1 + j));
+          e[u] = *reinterpret_cast<const i32x4*>(exps + j);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + 4 * 1024 * u;
+        if (j < ncols) {
+          if (!live1) v1[u] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+          *reinterpret_cast<f32x4*>(zl + j) = v0[u];
+          *reinterpret_cast<f32x4*>(zl1 + j) = v1[u];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            m0 = fmax(m0, ldexp((double)fabsf(v0[u][q]), e[u][q]));
+            m1 = fmax(m1, ldexp((double)fabsf(v1[u][q]), e[u][q]));
+          }
+        }
+      }
+    }
+  } else {
+    for (int64_t j = tid; j < ncols; j += 1024) {
+      const float v0 = z0[j], v1 = live1 ? z1[j] : 0.0f;
+      zl[j] = v0;
+      zl1[j] = v1;
+      m0 = fmax(m0, ldexp((double)fabsf(v0), exps[j]));
+      m1 = fmax(m1, ldexp((double)fabsf(v1), exps[j]));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    m0 = fmax(m0, __shfl_xor(m0, off, 64));
+    m1 = fmax(m1, __shfl_xor(m1, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = m0;
+    red[1][tid >> 6] = m1;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    double m = red[tid][0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[tid][w]);
+    int f = 0;
+    if (m > 0.0) {
+      int E;
+      (void)frexp(m, &E);
+      f = 15 - E;  // max |Z_bj| 2^(e_j + f) in [2^14, 2^15)
+    }
+    s_f[tid] = f;
+    if (b0 + tid < bc) fexp[b0 + tid] = f;
+  }
+  __syncthreads();
+  const int sc = tid & 1;
+  const int f = s_f[sc];
+  const float* zs = sc ? zl1 : zl;
+  // item t = 2 g + sc; two items per thread per batch, slot maps loaded first
+  for (int64_t g0 = tid >> 1; g0 < ngroups; g0 += 2 * 512) {
+    i32x4 p0[2], p1[2], e0[2], e1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t g = g0 + 512 * u;
+      if (g < ngroups) {
+        p0[u] = *reinterpret_cast<const i32x4*>(perm + 8 * g);
+        p1[u] = *reinterpret_cast<const i32x4*>(perm + 8 * g + 4);
+        e0[u] = *reinterpret_cast<const i32x4*>(eslot + 8 * g);
+        e1[u] = *reinterpret_cast<const i32x4*>(eslot + 8 * g + 4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t g = g0 + 512 * u;
+      if (g < ngroups) {
+        uint32_t h[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          h[q] = to16(ldexpf(p0[u][q] >= 0 ? zs[p0[u][q]] : 0.0f, e0[u][q] + f), BF16);
+          h[4 + q] = to16(ldexpf(p1[u][q] >= 0 ? zs[p1[u][q]] : 0.0f, e1[u][q] + f), BF16);
+        }
+        Zg[g * Bp + b0 + sc] = (u32x4){h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                      h[6] | (h[7] << 16)};
+      }
+    }
   }
 }
 
@@ -978,17 +1134,23 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
       const int64_t ngroups = ncols_pad / 8, Bp = padded_batch(bc);
       const dim3 pgrid((unsigned)((ngroups + 31) / 32), (unsigned)(Bp / 8));
       if (ncols <= kStageMaxCols) {
-        const size_t lds = (size_t)ncols * 4;
+        const bool pairs = ncols <= kStagePairCols;
+        const size_t lds = (size_t)ncols * 4 * (pairs ? 2 : 1);
+        const unsigned sgrid = (unsigned)(pairs ? Bp / 2 : Bp);
         auto stage = [&](auto kern) -> hipError_t {
           hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
           if (err != hipSuccess) return err;
-          kern<<<(unsigned)Bp, 1024, lds, s>>>(Zc, cx.exps, cx.perm, cx.eslot, ncols, ngroups, bc, Bp,
-                                               fexp, Zg);
+          kern<<<sgrid, 1024, lds, s>>>(Zc, cx.exps, cx.perm, cx.eslot, ncols, ngroups, bc, Bp,
+                                        fexp, Zg);
           return hipGetLastError();
         };
-        e = bf ? (vec ? stage(stage_slots16_kernel<true, true>) : stage(stage_slots16_kernel<true, false>))
-               : (vec ? stage(stage_slots16_kernel<false, true>) : stage(stage_slots16_kernel<false, false>));
+        if (pairs)
+          e = bf ? (vec ? stage(stage_pairs16_kernel<true, true>) : stage(stage_pairs16_kernel<true, false>))
+                 : (vec ? stage(stage_pairs16_kernel<false, true>) : stage(stage_pairs16_kernel<false, false>));
+        else
+          e = bf ? (vec ? stage(stage_slots16_kernel<true, true>) : stage(stage_slots16_kernel<true, false>))
+                 : (vec ? stage(stage_slots16_kernel<false, true>) : stage(stage_slots16_kernel<false, false>));
         if (e != hipSuccess) return e;
       } else {
         if (vec)

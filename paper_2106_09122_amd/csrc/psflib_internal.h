@@ -33,6 +33,7 @@ constexpr int kMvTargetWorkgroups16 = 768;  // split-K 16-bit matvec: workgroups
 constexpr int kMv16Threads = 256;    // 16-bit matvec threads per workgroup (1 row each)
 constexpr int kMv16MaxChunkGroups = 512;  // 16-bit matvec: 8-column groups per chunk, at most
 constexpr int64_t kStageMaxCols = 32768;  // batched 16-bit: scenes staged whole in LDS up to this many columns
+constexpr int64_t kStagePairCols = 16384;  // batched 16-bit: two scenes per staging workgroup up to this many columns
 constexpr int kAdjThreads = 256;     // adjoint threads per workgroup
 constexpr int kAdjF32Rows = 16384;   // rows per FP32 adjoint row block (16 float4 per thread)
 constexpr int kAdj16Rows = 16384;    // rows per 16-bit adjoint row block (64 rows per thread)
