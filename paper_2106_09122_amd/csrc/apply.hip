@@ -142,6 +142,9 @@ __device__ __forceinline__ void unpack8(const u32x4 p, float* f) {
   }
 }
 
+// Each thread owns kMv16RowsPerThread rows, kMv16Threads apart, so a
+// workgroup reads kMv16RowsPerThread * 4 KiB of every group in one piece, and
+// each broadcast of the group's 8 scene values serves that many loads.
 template <bool BF16>
 __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* __restrict__ Mp,
                                                                   const int32_t* __restrict__ perm,
@@ -151,9 +154,11 @@ __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* _
                                                                   float* __restrict__ out,
                                                                   int64_t M, int64_t ngroups,
                                                                   int64_t chunk_g) {
+  constexpr int R = kMv16RowsPerThread;
+  constexpr int GB = 16 / R;  // groups per block of 16 loads
   __shared__ f32x4 zs[kMv16MaxChunkGroups * 2];
   const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kMv16Threads + tid;
+  const int64_t i0 = (int64_t)blockIdx.x * kMv16Threads * R + tid;
   const int64_t c = blockIdx.y;
   const int64_t nchunks = gridDim.y;
   const int64_t g0 = c * chunk_g;
@@ -166,55 +171,89 @@ __global__ __launch_bounds__(kMv16Threads) void matvec_h16_kernel(const u32x4* _
     zsf[t] = (j >= 0) ? ldexpf(Z[j], eslot[slot]) : 0.0f;
   }
   __syncthreads();
-  const bool active = i < M;
-  float outer = 0.0f, mid = 0.0f;
-  if (active) {
-    int nblk = 0;
-    int64_t g = g0;
-    for (; g + 16 <= g1; g += 16) {
-      u32x4 p[16];
+  // rows past the image read row M-1 (in bounds) and are not written
+  const u32x4* src[R];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) p[u] = __builtin_nontemporal_load(Mp + (g + u) * M + i);
-      float inner = 0.0f;
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + (int64_t)kMv16Threads * r;
+    src[r] = Mp + (i < M ? i : M - 1);
+  }
+  float outer[R], mid[R];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+  for (int r = 0; r < R; ++r) outer[r] = mid[r] = 0.0f;
+  // blocks of 16 groups per inner sum, 8 blocks per middle sum, per row
+  float inner[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) inner[r] = 0.0f;
+  int ing = 0, nblk = 0;
+  int64_t g = g0;
+  for (; g + GB <= g1; g += GB) {
+    u32x4 p[GB][R];
+#pragma unroll
+    for (int u = 0; u < GB; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[u][r] = __builtin_nontemporal_load(src[r] + (g + u) * M);
+#pragma unroll
+    for (int u = 0; u < GB; ++u) {
+      const f32x4 za = zs[2 * (g - g0 + u)], zb = zs[2 * (g - g0 + u) + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
         float f[8];
-        unpack8<BF16>(p[u], f);
-        const f32x4 za = zs[2 * (g - g0 + u)], zb = zs[2 * (g - g0 + u) + 1];
-        inner = fmaf(f[0], za.x, inner);
-        inner = fmaf(f[1], za.y, inner);
-        inner = fmaf(f[2], za.z, inner);
-        inner = fmaf(f[3], za.w, inner);
-        inner = fmaf(f[4], zb.x, inner);
-        inner = fmaf(f[5], zb.y, inner);
-        inner = fmaf(f[6], zb.z, inner);
-        inner = fmaf(f[7], zb.w, inner);
+        unpack8<BF16>(p[u][r], f);
+        float acc = inner[r];
+        acc = fmaf(f[0], za.x, acc);
+        acc = fmaf(f[1], za.y, acc);
+        acc = fmaf(f[2], za.z, acc);
+        acc = fmaf(f[3], za.w, acc);
+        acc = fmaf(f[4], zb.x, acc);
+        acc = fmaf(f[5], zb.y, acc);
+        acc = fmaf(f[6], zb.z, acc);
+        acc = fmaf(f[7], zb.w, acc);
+        inner[r] = acc;
       }
-      mid += inner;
+    }
+    ing += GB;
+    if (ing == 16) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mid[r] += inner[r];
+        inner[r] = 0.0f;
+      }
+      ing = 0;
       if (++nblk == 8) {
-        outer += mid;
-        mid = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          outer[r] += mid[r];
+          mid[r] = 0.0f;
+        }
         nblk = 0;
       }
     }
-    float inner = 0.0f;
-    for (; g < g1; ++g) {
-      float f[8];
-      unpack8<BF16>(__builtin_nontemporal_load(Mp + g * M + i), f);
-      const f32x4 za = zs[2 * (g - g0)], zb = zs[2 * (g - g0) + 1];
-      inner = fmaf(f[0], za.x, inner);
-      inner = fmaf(f[1], za.y, inner);
-      inner = fmaf(f[2], za.z, inner);
-      inner = fmaf(f[3], za.w, inner);
-      inner = fmaf(f[4], zb.x, inner);
-      inner = fmaf(f[5], zb.y, inner);
-      inner = fmaf(f[6], zb.z, inner);
-      inner = fmaf(f[7], zb.w, inner);
-    }
-    mid += inner;
-    outer += mid;
   }
-  if (active) ((nchunks == 1) ? out : part + c * M)[i] = outer;
+  for (; g < g1; ++g) {
+    const f32x4 za = zs[2 * (g - g0)], zb = zs[2 * (g - g0) + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float f[8];
+      unpack8<BF16>(__builtin_nontemporal_load(src[r] + g * M), f);
+      float acc = inner[r];
+      acc = fmaf(f[0], za.x, acc);
+      acc = fmaf(f[1], za.y, acc);
+      acc = fmaf(f[2], za.z, acc);
+      acc = fmaf(f[3], za.w, acc);
+      acc = fmaf(f[4], zb.x, acc);
+      acc = fmaf(f[5], zb.y, acc);
+      acc = fmaf(f[6], zb.z, acc);
+      acc = fmaf(f[7], zb.w, acc);
+      inner[r] = acc;
+    }
+  }
+  float* dst = (nchunks == 1) ? out : part + c * M;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + (int64_t)kMv16Threads * r;
+    if (i < M) dst[i] = outer[r] + (mid[r] + inner[r]);
+  }
 }
 
 // out[i] = sum over chunks of part[chunk][i]: blocks of 16 partials loaded
@@ -238,9 +277,11 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restric
   out[i] = total;
 }
 
-// Split-K shape: about kMvTargetWorkgroups{32,16} workgroups in all (two to
-// three per CU: enough loads in flight to saturate HBM, few partials).  The
-// value can be overridden with PSFLIB_MV_WORKGROUPS for tuning sweeps.
+// Split-K shape: about kMvTargetWorkgroups{32,16} workgroups in all (FP32:
+// two per CU; 16-bit: one per CU of 8 rows x 16 B per thread and load step,
+// measured at 128^2 against 192 or 384 workgroups: 80 us against 88-94 us,
+// and against one row per thread at 768 workgroups: 85 us).  The value can be
+// overridden with PSFLIB_MV_WORKGROUPS for tuning sweeps.
 static int64_t mv_target_workgroups(int storage) {
   static const long env = [] {
     const char* e = getenv("PSFLIB_MV_WORKGROUPS");
@@ -256,7 +297,7 @@ struct MvShape {
 
 static MvShape mv_shape(int storage, int64_t M, int64_t ncols, int64_t ncols_pad) {
   MvShape sh;
-  const int64_t rows = (storage == PSFLIB_FP32) ? 4 * kMvThreads : kMv16Threads;
+  const int64_t rows = (storage == PSFLIB_FP32) ? 4 * kMvThreads : kMv16Threads * kMv16RowsPerThread;
   const int64_t units = (storage == PSFLIB_FP32) ? ncols : ncols_pad / 8;
   sh.rowblocks = (M + rows - 1) / rows;
   int64_t want = (mv_target_workgroups(storage) + sh.rowblocks - 1) / sh.rowblocks;

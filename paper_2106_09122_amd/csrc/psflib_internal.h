@@ -29,8 +29,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBuildThreads = 256;   // build kernel: one workgroup per group of 8 columns
 constexpr int kMvThreads = 256;      // FP32 matvec threads per workgroup (4 rows each)
 constexpr int kMvTargetWorkgroups32 = 512;  // split-K FP32 matvec: workgroups per launch (about)
-constexpr int kMvTargetWorkgroups16 = 768;  // split-K 16-bit matvec: workgroups per launch (about)
-constexpr int kMv16Threads = 256;    // 16-bit matvec threads per workgroup (1 row each)
+constexpr int kMvTargetWorkgroups16 = 256;  // split-K 16-bit matvec: workgroups per launch (about)
+constexpr int kMv16Threads = 256;    // 16-bit matvec threads per workgroup
+constexpr int kMv16RowsPerThread = 8;  // 16-bit matvec rows per thread (kMv16Threads apart)
 constexpr int kMv16MaxChunkGroups = 512;  // 16-bit matvec: 8-column groups per chunk, at most
 constexpr int64_t kStageMaxCols = 32768;  // batched 16-bit: scenes staged whole in LDS up to this many columns
 constexpr int64_t kStagePairCols = 16384;  // batched 16-bit: two scenes per staging workgroup up to this many columns
