@@ -55,10 +55,33 @@ __global__ __launch_bounds__(256) void flux_rescale_kernel(
   const float sf = (float)scale;
   float* col = A32 + j * M;
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < M; i += 256) {
-    const float v = col[i] * sf;
-    col[i] = v;
-    acc += (double)v;
+  if ((M & 3) == 0 && (reinterpret_cast<uintptr_t>(col) & 15) == 0) {
+    // 16-byte pieces, 8 loads of a thread in flight before their use
+    f32x4* c4 = reinterpret_cast<f32x4*>(col);
+    const int64_t nq = M >> 2;
+    for (int64_t q0 = threadIdx.x; q0 < nq; q0 += 256 * 8) {
+      f32x4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t q = q0 + 256 * u;
+        if (q < nq) v[u] = __builtin_nontemporal_load(c4 + q);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t q = q0 + 256 * u;
+        if (q < nq) {
+          const f32x4 x = v[u] * sf;
+          __builtin_nontemporal_store(x, c4 + q);
+          acc += ((double)x[0] + (double)x[1]) + ((double)x[2] + (double)x[3]);
+        }
+      }
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < M; i += 256) {
+      const float v = col[i] * sf;
+      col[i] = v;
+      acc += (double)v;
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
