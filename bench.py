@@ -220,7 +220,16 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="time only the headline matvec")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates profiler byte counters)")
+    ap.add_argument("--storage", choices=("fp32", "bf16", "fp16"), default="fp32",
+                    help="storage form of the headline library (profiling runs of the 16-bit "
+                         "matvec and adjoint; the reported metric is defined for fp32)")
+    ap.add_argument("--with-adjoint", action="store_true",
+                    help="also run --steps adjoint products after the headline (profiling runs)")
     args = ap.parse_args()
+    if args.storage != "fp32" and not (args.no_rows and args.no_cpu_baseline):
+        print("--storage bf16/fp16 is a profiling mode: give it with --no-rows --no-cpu-baseline",
+              file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the operator "
               "has no multi-GPU path (sharding is described, not implemented).", file=sys.stderr)
@@ -240,20 +249,26 @@ def main():
     cube = torch.from_numpy(d["cube"]).to(dev)
     scene = torch.from_numpy(d["scene"]).to(dev)
     image = torch.empty(M, dtype=torch.float32, device=dev)
-    print(f"[bench] workload n={n} N={N} K={K}: building FP32 library", file=sys.stderr, flush=True)
+    print(f"[bench] workload n={n} N={N} K={K}: building {args.storage} library", file=sys.stderr, flush=True)
 
     rows = {}
     ref_scenes = [d["scene"]]   # scenes whose FP64 oracle images the CPU leg computes
     gpu_images = {}             # name -> (index into ref_scenes, float32 image on the host)
-    lib = psflib.Library(cube, d["radii"], N, S, storage="fp32")
+    lib = psflib.Library(cube, d["radii"], N, S, storage=args.storage)
     torch.cuda.synchronize()
 
     # headline: FP32 single-scene simulation, library resident
     ms = _timed(torch, lambda: lib.apply(scene, out=image), args.steps, args.warmup)
-    lib_bytes = M * ncols * 4
+    lib_bytes = M * ncols * 4 if args.storage == "fp32" else M * ((ncols + 63) // 64 * 64) * 2
     alg_bytes = lib_bytes + 4 * (M + ncols)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    print(f"[bench] fp32 apply {ms * 1e3:.1f} us/scene, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    print(f"[bench] {args.storage} apply {ms * 1e3:.1f} us/scene, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    if args.with_adjoint:
+        gq = torch.randn(M, device=dev, dtype=torch.float32)
+        gout = torch.empty(ncols, device=dev, dtype=torch.float32)
+        t_adj = _timed(torch, lambda: lib.apply_adjoint(gq, out=gout), args.steps, args.warmup)
+        print(f"[bench] {args.storage} adjoint {t_adj * 1e3:.1f} us, {lib_bytes / (t_adj * 1e-3) / 1e9:.0f} GB/s",
+              file=sys.stderr, flush=True)
     gpu_images["fp32"] = (0, lib.apply(scene).cpu().numpy())
     ceil = None if args.no_probes else probes(torch, psflib, dev)
     if args.copy_probe:
@@ -472,16 +487,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage == "fp32" else args.storage,
         "data": "synthetic (seeded Fraunhofer PSF cube with Zernike aberrations and a coronagraph "
                 "throughput ramp; inclined power-law ring + 5 planets)",
         "config": {"workload": "single-scene matvec, 128x128 image and scene, 64 PSFs of 128x128, "
                                "16384x16384 float32 library (1 GiB) resident in HBM",
                    "n": n, "N": N, "n_psf": K, "pixscale_lod": S, "library_bytes": lib_bytes,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": _profiled_traffic(),
-                     "kernel": "matvec_f32_kernel", "algorithmic_bytes_per_launch": alg_bytes,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _profiled_traffic() if args.storage == "fp32" else None,
+                     "kernel": "matvec_f32_kernel" if args.storage == "fp32" else "matvec_h16_kernel",
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "measured_peak": ceil["hbm_read_GB_per_s"] if ceil else None,
                      "frac_of_measured": achieved / ceil["hbm_read_GB_per_s"] if ceil else None},
         "measured_ceilings": ceil,
