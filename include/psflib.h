@@ -208,7 +208,7 @@ psflib_status psflib_apply(const psflib_handle* h, const float* d_scene, float* 
  * and give wrong images: order them (one stream, or events).
  *   Fails with PSFLIB_ERR_SIZE, before enqueuing anything, if the library needs
  * more partial sums than the array holds.  FP32 libraries need at most 4 MiB;
- * 16-bit ones at most max(1.5 MiB, ceil(N*N / 4096) * n*n * 4 bytes), which
+ * 16-bit ones at most max(4 MiB, ceil(N*N / 4096) * n*n * 4 bytes), which
  * can pass 8 MiB only when n*n*N*N > 2^32 (16-bit libraries of more than
  * 8 GiB, e.g. n = 128 with N >= 1024). */
 #define PSFLIB_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
