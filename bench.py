@@ -434,6 +434,8 @@ def main():
             t_adj16 = _timed(torch, lambda: lh.apply_adjoint(g, out=grad), args.steps // 2, 10)
             ent["adjoint_us"] = t_adj16 * 1e3
             ent["adjoint_GB_per_s"] = M * ((ncols + 63) // 64 * 64) * 2 / (t_adj16 * 1e-3) / 1e9
+            ent["frac_hbm"] = ent["GB_per_s"] / HBM_PEAK_GBS
+            ent["adjoint_frac_hbm"] = ent["adjoint_GB_per_s"] / HBM_PEAK_GBS
             for bi, (B, Zb_h) in enumerate(batches.items()):
                 Zb = torch.from_numpy(Zb_h).to(dev)
                 out = torch.empty((B, M), device=dev, dtype=torch.float32)
