@@ -204,9 +204,10 @@ def test_c2_batched_dense(torch, c2, dense, storage):
     Zb, ref = dense
     lib = _build(torch, c2, storage)
     # a few scenes (mostly-padding tiles, the most K slices), then every K-split
-    # shape of the GEMMs down to no split (the longest chains), and a full pass
-    # of 1024 scenes (the 16-bit forms' 256-scene tiles)
-    for B in (2, 3, 5, 8, 20, 64, 256, 512, 1024):
+    # shape of the GEMMs down to no split (the longest chains), an odd batch that
+    # leaves the 8-wave 16-bit kernel a part-filled scene tile and a half-padding
+    # staging pair, and a full pass of 1024 scenes (the 16-bit forms' 256-scene tiles)
+    for B in (2, 3, 5, 8, 20, 64, 256, 301, 512, 1024):
         out = lib.apply_batched(torch.from_numpy(Zb[:B]).cuda()).cpu().numpy().astype(np.float64)
         r = ref[:B]
         if storage == "fp32":
