@@ -33,6 +33,8 @@
 // nearest even, 8 columns per 16 B).
 #include <math.h>
 
+#include <type_traits>
+
 #include "psflib_internal.h"
 
 namespace psflib {
@@ -295,7 +297,22 @@ __global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict
 // centre of an odd grid) and, in the same step, its half turn about the star,
 // column N^2-1-j, whose entry (n-1-a, n-1-b) is entry (a, b) of column j (the
 // same float64 products, negated twice); every element is written once.
-template <int E, bool FULL>
+// OUT: 0 = float32 columns; 1, 2 = the columns rounded to BF16 / FP16 after
+// scaling by 2^-e_j (the column's exponent, known from the geometry), the
+// values packing would give, as 2-byte column-major staging.
+template <int OUT>
+__device__ __forceinline__ uint16_t band_round16(float v, int32_t e) {
+  const float x = ldexpf(v, -e);
+  if constexpr (OUT == 1) {
+    uint32_t w = __float_as_uint(x);
+    w += 0x7FFFu + ((w >> 16) & 1u);
+    return (uint16_t)(w >> 16);
+  } else {
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
+  }
+}
+
+template <int E, bool FULL, int OUT>
 __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restrict__ cube, int K,
                                                           const ColGeom* __restrict__ geo,
                                                           const int32_t* __restrict__ order,
@@ -303,9 +320,10 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
                                                           const int32_t* __restrict__ nitems,
                                                           int nb, int n, int ls, int H, int nbands,
                                                           int64_t M, int64_t ncols, int64_t jbase,
-                                                          float* __restrict__ A_lo,
-                                                          float* __restrict__ A_hi, int64_t p0,
+                                                          void* __restrict__ A_lo,
+                                                          void* __restrict__ A_hi, int64_t p0,
                                                           double* __restrict__ tau) {
+  using T = typename std::conditional<OUT == 0, float, uint16_t>::type;
   // order[] holds columns relative to jbase (absolute column jbase + j, at
   // A_lo + j M); the half turn j2 = ncols-1-(jbase+j) goes to A_hi + (j2 - p0) M
   extern __shared__ float2 P2[];  // H rows of the bordered pair array, row stride ls
@@ -317,15 +335,15 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
     if (wave >= len) return;
     const int64_t jr = order[start + wave], j = jbase + jr, j2 = ncols - 1 - j;
-    float* col = A_lo + jr * M;
-    float* col2 = A_hi + (j2 - p0) * M;
+    T* col = reinterpret_cast<T*>(A_lo) + jr * M;
+    T* col2 = reinterpret_cast<T*>(A_hi) + (j2 - p0) * M;
     for (int a = 0; a < n; ++a)
 #pragma unroll
       for (int v = 0; v < E; ++v) {
         const int b = lane + 64 * v;
         if (FULL || b < n) {
-          __builtin_nontemporal_store(0.0f, col + a * n + b);
-          if (j2 != j) __builtin_nontemporal_store(0.0f, col2 + a * n + b);
+          __builtin_nontemporal_store((T)0, col + a * n + b);
+          if (j2 != j) __builtin_nontemporal_store((T)0, col2 + a * n + b);
         }
       }
     if (lane == 0) tau[j] = tau[j2] = 0.0;
@@ -344,8 +362,10 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
   // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
   const int64_t j = jbase + jr, j2 = ncols - 1 - j;
   const bool pair = j2 != j;
-  float* col = A_lo + jr * M;
-  float* col2 = A_hi + (j2 - p0) * M;
+  T* col = reinterpret_cast<T*>(A_lo) + jr * M;
+  T* col2 = reinterpret_cast<T*>(A_hi) + (j2 - p0) * M;
+  // 16-bit staging: the half turn has the same radius, so the same exponent
+  const int32_t ecol = (OUT != 0 && live) ? g.e : 0;
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   double ctux[E], mstux[E];
@@ -476,8 +496,14 @@ __global__ __launch_bounds__(1024) void build_band_kernel(const float* __restric
         val = fmaf(tfy * tgx, q10, val);
         val = fmaf(tfy * tfx, q11, val);
         val = ok ? val : 0.0f;
-        __builtin_nontemporal_store(val, col + a * n + b);
-        if (pair) __builtin_nontemporal_store(val, col2 + (n - 1 - a) * n + (n - 1 - b));
+        if constexpr (OUT == 0) {
+          __builtin_nontemporal_store(val, col + a * n + b);
+          if (pair) __builtin_nontemporal_store(val, col2 + (n - 1 - a) * n + (n - 1 - b));
+        } else {
+          const uint16_t h = band_round16<OUT>(val, ecol);
+          __builtin_nontemporal_store(h, col + a * n + b);
+          if (pair) __builtin_nontemporal_store(h, col2 + (n - 1 - a) * n + (n - 1 - b));
+        }
         rowsum += val;
       }
       tsum += (double)rowsum;
@@ -1486,9 +1512,10 @@ hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGe
 
 // the banded build over the sorted columns of `bp` (relative to jbase, see
 // build_band_kernel)
+template <int OUT>
 static hipError_t launch_band(const float* cube, int K, const ColGeom* geo, const BucketPlan& bp,
-                              int n, int64_t M, int64_t ncols, int64_t jbase, float* A_lo,
-                              float* A_hi, int64_t p0, double* tau, hipStream_t s) {
+                              int n, int64_t M, int64_t ncols, int64_t jbase, void* A_lo,
+                              void* A_hi, int64_t p0, double* tau, hipStream_t s) {
   const int ls = band_stride(n), H = band_rows(n), np = n + 2;
   const int nbands = (np - 1 + (H - 1) - 1) / (H - 1);
   const size_t lds = (size_t)H * ls * sizeof(float2);
@@ -1503,8 +1530,8 @@ static hipError_t launch_band(const float* cube, int K, const ColGeom* geo, cons
     return hipGetLastError();
   };
   switch (lds_e(n)) {  // n > 141 here
-    case 3: return full ? launch(build_band_kernel<3, true>) : launch(build_band_kernel<3, false>);
-    default: return full ? launch(build_band_kernel<4, true>) : launch(build_band_kernel<4, false>);
+    case 3: return full ? launch(build_band_kernel<3, true, OUT>) : launch(build_band_kernel<3, false, OUT>);
+    default: return full ? launch(build_band_kernel<4, true, OUT>) : launch(build_band_kernel<4, false, OUT>);
   }
 }
 
@@ -1530,7 +1557,7 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
 
   const unsigned grid = (unsigned)items_max;
   const bool full = (n % 64) == 0;
-  if (!pair_fits_lds(n)) return launch_band(cube, K, geo, bp, n, M, ncols, 0, A32, A32, 0, tau, s);
+  if (!pair_fits_lds(n)) return launch_band<0>(cube, K, geo, bp, n, M, ncols, 0, A32, A32, 0, tau, s);
   const int ls = lds_stride(n);
   const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
   const void* fn;
@@ -1677,12 +1704,71 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
 }
 
 
-// 16-bit libraries of banded PSF pairs, staged through float32 a chunk of
-// columns at a time: chunk [c0, c1) of the first half of the scene grid and
-// its half turns [N^2-c1, N^2-c0) are built into the staging buffer (2 CH
-// columns) and packed before the next chunk, so the staging needs 2 CH n^2
-// floats instead of the whole float32 library.  N % 16 == 0 (whole 8-column
-// groups on both sides, no centre column).
+// Interleave 16-bit column-major staging into the 8-slot groups:
+// M16[g][i][u] = S[8g+u][i] (column j of the staging at S + (j - col0) M),
+// zeros past ncols.  VEC (M % 8 == 0): a thread takes 8 rows, one 16-byte
+// load per column (1 KiB per wave and column), transposes the 8 x 8 values in
+// registers and writes its 128 contiguous bytes.
+template <bool VEC>
+__global__ __launch_bounds__(256) void pack16_staged_kernel(const uint16_t* __restrict__ S,
+                                                            int64_t M, int64_t ncols,
+                                                            u32x4* __restrict__ Mp, int64_t g0,
+                                                            int64_t col0) {
+  const int64_t grp = g0 + blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  if (i0 >= M) return;
+  uint32_t w[8][4];  // column u, rows 2k, 2k+1 in word k
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t j = grp * 8 + u;
+    if constexpr (VEC) {
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (j < ncols) t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(S + (j - col0) * M + i0));
+      w[u][0] = t.x; w[u][1] = t.y; w[u][2] = t.z; w[u][3] = t.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t lo = 0u, hi = 0u;
+        if (j < ncols) {
+          if (i0 + 2 * k < M) lo = S[(j - col0) * M + i0 + 2 * k];
+          if (i0 + 2 * k + 1 < M) hi = S[(j - col0) * M + i0 + 2 * k + 1];
+        }
+        w[u][k] = lo | (hi << 16);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (!VEC && i0 + r >= M) break;
+    const int k = r >> 1, sh = 16 * (r & 1);
+    u32x4 pk;
+    pk.x = ((w[0][k] >> sh) & 0xFFFFu) | (((w[1][k] >> sh) & 0xFFFFu) << 16);
+    pk.y = ((w[2][k] >> sh) & 0xFFFFu) | (((w[3][k] >> sh) & 0xFFFFu) << 16);
+    pk.z = ((w[4][k] >> sh) & 0xFFFFu) | (((w[5][k] >> sh) & 0xFFFFu) << 16);
+    pk.w = ((w[6][k] >> sh) & 0xFFFFu) | (((w[7][k] >> sh) & 0xFFFFu) << 16);
+    Mp[grp * M + i0 + r] = pk;
+  }
+}
+
+static hipError_t launch_pack16_staged(const uint16_t* S, int64_t col0, int64_t g0, int64_t g1,
+                                       int64_t M, int64_t ncols, void* lib, hipStream_t s) {
+  if (g1 <= g0) return hipSuccess;
+  const dim3 pgrid((unsigned)((M + 2047) / 2048), (unsigned)(g1 - g0));
+  u32x4* Mp = reinterpret_cast<u32x4*>(lib);
+  if (M % 8 == 0 && (reinterpret_cast<uintptr_t>(S) & 15) == 0)
+    pack16_staged_kernel<true><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
+  else
+    pack16_staged_kernel<false><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
+  return hipGetLastError();
+}
+
+// 16-bit libraries of banded PSF pairs, a chunk of columns at a time: chunk
+// [c0, c1) of the first half of the scene grid and its half turns
+// [N^2-c1, N^2-c0) are built, already rounded to the format, into a 16-bit
+// column-major staging buffer (2 CH columns) and interleaved into the groups
+// before the next chunk, so the staging needs 2 CH n^2 2-byte values instead
+// of a float32 copy of the library.  N % 16 == 0 (whole 8-column groups on
+// both sides, no centre column).
 static int64_t band16_chunk(int N) {
   const int64_t nhalf = (int64_t)N * N / 2;
   return nhalf < kBand16ChunkCols ? nhalf : kBand16ChunkCols;
@@ -1692,24 +1778,26 @@ bool build_band16_chunked_supported(int n, int K, int N) {
   return !pair_fits_lds(n) && build_lds_supported(n, K) && N % 16 == 0;
 }
 
-size_t band16_stage_bytes(int N, int64_t M) { return (size_t)2 * band16_chunk(N) * (size_t)M * 4; }
+size_t band16_stage_bytes(int N, int64_t M) { return (size_t)2 * band16_chunk(N) * (size_t)M * 2; }
 
 hipError_t launch_build_band16_chunked(int storage, const float* cube, int K, const ColGeom* geo,
                                        int n, int N, int64_t M, void* lib, double* tau,
-                                       void* scratch, float* stage, hipStream_t s) {
+                                       void* scratch, void* stage, hipStream_t s) {
   const int64_t ncols = (int64_t)N * N, nhalf = ncols / 2, CH = band16_chunk(N);
-  float* A_hi = stage + CH * M;
+  uint16_t* A_lo = reinterpret_cast<uint16_t*>(stage);
+  uint16_t* A_hi = A_lo + CH * M;
+  const bool bf = storage == PSFLIB_BF16_POW2;
   for (int64_t c0 = 0; c0 < nhalf; c0 += CH) {
     const int64_t c1 = (c0 + CH < nhalf) ? c0 + CH : nhalf;
     BucketPlan bp;
     hipError_t e = launch_bucket_sort(geo + c0, c1 - c0, K, scratch, &bp, s);
     if (e != hipSuccess) return e;
-    e = launch_band(cube, K, geo, bp, n, M, ncols, c0, stage, A_hi, ncols - c1, tau, s);
+    e = bf ? launch_band<1>(cube, K, geo, bp, n, M, ncols, c0, A_lo, A_hi, ncols - c1, tau, s)
+           : launch_band<2>(cube, K, geo, bp, n, M, ncols, c0, A_lo, A_hi, ncols - c1, tau, s);
     if (e != hipSuccess) return e;
-    e = launch_pack16_range(storage, stage, c0, c0 / 8, c1 / 8, geo, M, ncols, lib, s);
+    e = launch_pack16_staged(A_lo, c0, c0 / 8, c1 / 8, M, ncols, lib, s);
     if (e != hipSuccess) return e;
-    e = launch_pack16_range(storage, A_hi, ncols - c1, (ncols - c1) / 8, (ncols - c0) / 8, geo, M,
-                            ncols, lib, s);
+    e = launch_pack16_staged(A_hi, ncols - c1, (ncols - c1) / 8, (ncols - c0) / 8, M, ncols, lib, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

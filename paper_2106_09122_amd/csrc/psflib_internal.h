@@ -45,7 +45,7 @@ constexpr int32_t kZeroColumnExp = PSFLIB_ZERO_COLUMN_EXPONENT;  // exponent of 
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter
-constexpr int64_t kBand16ChunkCols = 8192;  // banded 16-bit builds: base columns per float32 staging chunk
+constexpr int64_t kBand16ChunkCols = 16384;  // banded 16-bit builds: base columns per staging chunk
 constexpr int kLdsMaxBuckets = 8193; // LDS builds: radial brackets + the zero-column bucket, at most
 
 struct Layout {
@@ -203,13 +203,14 @@ hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int6
 hipError_t launch_pack16_range(int storage, const float* A32, int64_t col0, int64_t g0, int64_t g1,
                                const ColGeom* geo, int64_t M, int64_t ncols, void* lib,
                                hipStream_t s);
-// 16-bit storage of a banded build (pairs beyond the LDS; N % 16 == 0), staged
-// through float32 a chunk of columns at a time (band16_stage_bytes of staging)
+// 16-bit storage of a banded build (pairs beyond the LDS; N % 16 == 0): a chunk
+// of columns at a time, rounded to the format in the build and staged as 2-byte
+// columns (band16_stage_bytes of staging), then interleaved into the groups
 bool build_band16_chunked_supported(int n, int K, int N);
 size_t band16_stage_bytes(int N, int64_t M);
 hipError_t launch_build_band16_chunked(int storage, const float* cube, int K, const ColGeom* geo,
                                        int n, int N, int64_t M, void* lib, double* tau,
-                                       void* scratch, float* stage, hipStream_t s);
+                                       void* scratch, void* stage, hipStream_t s);
 // Flux-preserving rescale of float32 columns: sums[k] = sum(P_k) (float64),
 // column j scaled by t_j / tau_j, tau_j recomputed; with want_exp the 16-bit
 // exponents (geo[j].e and exps[j]) follow the rescaled bound.
