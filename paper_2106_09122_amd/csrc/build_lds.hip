@@ -1706,9 +1706,10 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
 
 // Interleave 16-bit column-major staging into the 8-slot groups:
 // M16[g][i][u] = S[8g+u][i] (column j of the staging at S + (j - col0) M),
-// zeros past ncols.  VEC (M % 8 == 0): a thread takes 8 rows, one 16-byte
-// load per column (1 KiB per wave and column), transposes the 8 x 8 values in
-// registers and writes its 128 contiguous bytes.
+// zeros past ncols.  A thread takes 8 rows, one 16-byte load per column
+// (VEC, M % 2048 == 0: 1 KiB per wave and column), transposes the 8 x 8 values
+// in registers and, through LDS, the workgroup writes its 2048 rows 1 KiB per
+// store instruction.
 template <bool VEC>
 __global__ __launch_bounds__(256) void pack16_staged_kernel(const uint16_t* __restrict__ S,
                                                             int64_t M, int64_t ncols,
@@ -1716,7 +1717,7 @@ __global__ __launch_bounds__(256) void pack16_staged_kernel(const uint16_t* __re
                                                             int64_t col0) {
   const int64_t grp = g0 + blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
-  if (i0 >= M) return;
+  if (!VEC && i0 >= M) return;  // VEC: every row of the workgroup is in the image
   uint32_t w[8][4];  // column u, rows 2k, 2k+1 in word k
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -1737,16 +1738,29 @@ __global__ __launch_bounds__(256) void pack16_staged_kernel(const uint16_t* __re
       }
     }
   }
+  u32x4 pk[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    if (!VEC && i0 + r >= M) break;
     const int k = r >> 1, sh = 16 * (r & 1);
-    u32x4 pk;
-    pk.x = ((w[0][k] >> sh) & 0xFFFFu) | (((w[1][k] >> sh) & 0xFFFFu) << 16);
-    pk.y = ((w[2][k] >> sh) & 0xFFFFu) | (((w[3][k] >> sh) & 0xFFFFu) << 16);
-    pk.z = ((w[4][k] >> sh) & 0xFFFFu) | (((w[5][k] >> sh) & 0xFFFFu) << 16);
-    pk.w = ((w[6][k] >> sh) & 0xFFFFu) | (((w[7][k] >> sh) & 0xFFFFu) << 16);
-    Mp[grp * M + i0 + r] = pk;
+    pk[r].x = ((w[0][k] >> sh) & 0xFFFFu) | (((w[1][k] >> sh) & 0xFFFFu) << 16);
+    pk[r].y = ((w[2][k] >> sh) & 0xFFFFu) | (((w[3][k] >> sh) & 0xFFFFu) << 16);
+    pk[r].z = ((w[4][k] >> sh) & 0xFFFFu) | (((w[5][k] >> sh) & 0xFFFFu) << 16);
+    pk[r].w = ((w[6][k] >> sh) & 0xFFFFu) | (((w[7][k] >> sh) & 0xFFFFu) << 16);
+  }
+  if constexpr (VEC) {
+    // through LDS, so each store instruction writes 1 KiB of consecutive rows
+    // (the workgroup's 2048 rows are whole: M % 2048 == 0)
+    __shared__ u32x4 rows[2048];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rows[8 * threadIdx.x + r] = pk[r];
+    __syncthreads();
+    u32x4* dst = Mp + grp * M + (int64_t)blockIdx.x * 2048;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) dst[threadIdx.x + 256 * r] = rows[threadIdx.x + 256 * r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if (i0 + r < M) Mp[grp * M + i0 + r] = pk[r];
   }
 }
 
@@ -1755,7 +1769,7 @@ static hipError_t launch_pack16_staged(const uint16_t* S, int64_t col0, int64_t 
   if (g1 <= g0) return hipSuccess;
   const dim3 pgrid((unsigned)((M + 2047) / 2048), (unsigned)(g1 - g0));
   u32x4* Mp = reinterpret_cast<u32x4*>(lib);
-  if (M % 8 == 0 && (reinterpret_cast<uintptr_t>(S) & 15) == 0)
+  if (M % 2048 == 0 && (reinterpret_cast<uintptr_t>(S) & 15) == 0)
     pack16_staged_kernel<true><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
   else
     pack16_staged_kernel<false><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
