@@ -26,7 +26,10 @@
 //    of 8): one wave per column, 16 columns per workgroup, units assembled
 //    from an LDS tile;
 //  * row bands (pairs larger than the LDS, up to 256 x 256): one wave per
-//    column, the pair staged a band of rows at a time.
+//    column, the pair staged a band of rows at a time; the 16-bit forms (scene
+//    sides a multiple of 16) round each value in the build and stage 2-byte
+//    columns, a chunk at a time, which a second kernel interleaves into the
+//    8-slot groups.
 // The 16-bit forms of the other builds (and of columns that need float32
 // post-processing, the flux-preserving rescale) are built as float32 columns
 // into scratch and packed by a second kernel (scale by 2^-e_j, round to
