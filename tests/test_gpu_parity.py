@@ -174,6 +174,7 @@ SHAPES = [
     (150, 33, 0.3, 6, "linear", "linear", "zero"),   # 1089 position angles
     (150, 16, 0.4, 4, "linear", "linear", "zero"),   # 16-bit: 2-byte staging, scalar interleave
     (192, 16, 0.35, 4, "nonuniform", "linear", "zero"),  # 16-bit: 2-byte staging, 1 KiB interleave stores
+    (151, 16, 0.45, 3, "linear", "nearest", "clamp"),  # 16-bit: odd image size in the 2-byte staging
     (199, 4, 0.5, 3, "nonuniform", "linear", "zero"),
     (256, 3, 0.9, 3, "linear", "linear", "clamp"),
     # PSFs larger than 256 x 256 take the gather path
@@ -214,7 +215,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + [SHAPES[13], SHAPES[14], SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + [SHAPES[13], SHAPES[14], SHAPES[15], SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
