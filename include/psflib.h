@@ -349,6 +349,21 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
                                       const double* d_theta, const float* d_dscene,
                                       double* d_dtheta, void* stream);
 
+/* The misfit the retrieval of Sec. 5 minimises, for Gaussian errors with a
+ * per-pixel variance (e.g. photon noise of the simulated counts):
+ *   L = sum_i (K S_i - D_i)^2 / var_i   and   dL/dS_i = 2 K (K S_i - D_i) / var_i,
+ * K the exposure scale from image units to counts.  d_image float32 [M] (a
+ * simulated image), d_data and d_var float64 [M] (var_i > 0), all in device
+ * memory; M in [1, 2^36], K finite.  d_loss float64 [1] receives L, summed in
+ * float64 in a fixed order (per-workgroup trees, then their sums in block
+ * order: repeated calls give identical results); d_grad float32 [M] receives
+ * dL/dS (the input of psflib_apply_adjoint), or NULL to skip it.  Uses M/256
+ * * 8 bytes of temporaries in the buffer of `stream`.  With psflib_render_disk,
+ * psflib_apply, psflib_apply_adjoint and psflib_render_disk_grad this gives
+ * the loss of a disk model and its gradient without host arithmetic. */
+psflib_status psflib_chi2(int64_t M, double K, const float* d_image, const double* d_data,
+                          const double* d_var, double* d_loss, float* d_grad, void* stream);
+
 /* ---- Measurement probes ---------------------------------------------------
  * Not part of the method: they measure, on the part itself, the ceilings the
  * products are compared against (the paper times its simulation against CPU

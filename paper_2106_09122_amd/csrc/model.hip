@@ -114,6 +114,64 @@ __global__ __launch_bounds__(kGradThreads) void grad_sum_kernel(const double* __
   if (tid < 5) dtheta[tid] = red[tid][0];
 }
 
+// Chi-square misfit of a simulated image and its gradient in the image:
+// t_i = (K S_i - D_i)^2 / var_i, grad_i = 2 K (K S_i - D_i) / var_i (float64,
+// rounded once to float32).  Per-workgroup trees of t_i, then their sums in
+// block order (chi2_sum_kernel), so the loss does not depend on scheduling.
+__global__ __launch_bounds__(kGradThreads) void chi2_kernel(int64_t M, double K,
+                                                            const float* __restrict__ S,
+                                                            const double* __restrict__ D,
+                                                            const double* __restrict__ var,
+                                                            float* __restrict__ grad,
+                                                            double* __restrict__ partial) {
+  __shared__ double red[kGradThreads];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kGradThreads + tid;
+  double t = 0.0;
+  if (i < M) {
+    const double r = K * (double)S[i] - D[i];
+    const double v = var[i];
+    t = r * r / v;
+    if (grad) grad[i] = (float)((2.0 * K) * r / v);
+  }
+  red[tid] = t;
+  for (int s2 = kGradThreads / 2; s2 > 0; s2 >>= 1) {
+    __syncthreads();
+    if (tid < s2) red[tid] += red[tid + s2];
+  }
+  if (tid == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kGradThreads) void chi2_sum_kernel(const double* __restrict__ partial,
+                                                                int64_t nblocks,
+                                                                double* __restrict__ loss) {
+  __shared__ double red[kGradThreads];
+  const int tid = threadIdx.x;
+  double a = 0.0;
+  for (int64_t b = tid; b < nblocks; b += kGradThreads) a += partial[b];
+  red[tid] = a;
+  for (int s2 = kGradThreads / 2; s2 > 0; s2 >>= 1) {
+    __syncthreads();
+    if (tid < s2) red[tid] += red[tid + s2];
+  }
+  if (tid == 0) *loss = red[0];
+}
+
+size_t chi2_scratch_bytes(int64_t M) {
+  return (size_t)((M + kGradThreads - 1) / kGradThreads) * sizeof(double);
+}
+
+hipError_t launch_chi2(int64_t M, double K, const float* S, const double* D, const double* var,
+                       double* loss, float* grad, void* scratch, hipStream_t s) {
+  const int64_t nblocks = (M + kGradThreads - 1) / kGradThreads;
+  double* partial = reinterpret_cast<double*>(scratch);
+  chi2_kernel<<<(unsigned)nblocks, kGradThreads, 0, s>>>(M, K, S, D, var, grad, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  chi2_sum_kernel<<<1, kGradThreads, 0, s>>>(partial, nblocks, loss);
+  return hipGetLastError();
+}
+
 size_t render_disk_grad_scratch_bytes(int N) {
   const int64_t nblocks = ((int64_t)N * N + kGradThreads - 1) / kGradThreads;
   return (size_t)nblocks * 5 * sizeof(double);

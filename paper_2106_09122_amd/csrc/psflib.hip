@@ -744,6 +744,31 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   return PSFLIB_OK;
 }
 
+psflib_status psflib_chi2(int64_t M, double K, const float* d_image, const double* d_data,
+                          const double* d_var, double* d_loss, float* d_grad, void* stream) {
+  if (M < 1 || M > ((int64_t)1 << 36)) return fail(PSFLIB_ERR_INVALID_ARG, "M must be in [1, 2^36]");
+  if (!isfinite(K)) return fail(PSFLIB_ERR_INVALID_ARG, "K must be finite");
+  if (!d_image || !d_data || !d_var || !d_loss)
+    return fail(PSFLIB_ERR_INVALID_ARG, "d_image, d_data, d_var and d_loss must be non-NULL");
+  if (!aligned16(d_image) || !aligned16(d_data) || !aligned16(d_var) || !aligned16(d_loss) ||
+      (d_grad && !aligned16(d_grad)))
+    return fail(PSFLIB_ERR_INVALID_ARG, "device arrays must be 16-byte aligned");
+  psflib_status st = psflib::check_pending_error();
+  if (st != PSFLIB_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  CallScratch cs;
+  e = cs.acquire(dev, s, psflib::chi2_scratch_bytes(M));
+  if (e != hipSuccess) return device_fail(e, "scratch buffer (chi-square)");
+  e = psflib::launch_chi2(M, K, d_image, d_data, d_var, d_loss, d_grad, cs.ptr(), s);
+  const hipError_t e2 = cs.release();
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return device_fail(e, "chi-square kernels");
+  return PSFLIB_OK;
+}
+
 psflib_status psflib_probe_hbm_read(const void* d_buf, size_t bytes, int32_t workgroups,
                                     int32_t unroll, int32_t slice, float* d_sink, void* stream) {
   if (!d_buf || !d_sink) return fail(PSFLIB_ERR_INVALID_ARG, "d_buf and d_sink must be non-NULL");

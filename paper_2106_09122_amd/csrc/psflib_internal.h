@@ -236,6 +236,9 @@ hipError_t launch_get_columns(int storage, const void* lib, const Cols16& cx,
 hipError_t launch_render_disk(int N, double S, double rmax, const double* theta, float* Z,
                               hipStream_t s);
 size_t render_disk_grad_scratch_bytes(int N);
+size_t chi2_scratch_bytes(int64_t M);
+hipError_t launch_chi2(int64_t M, double K, const float* S, const double* D, const double* var,
+                       double* loss, float* grad, void* scratch, hipStream_t s);
 hipError_t launch_render_disk_grad(int N, double S, double rmax, const double* theta,
                                    const float* dZ, double* dtheta, void* scratch, hipStream_t s);
 // Measurement probes (probe.hip): a 16-byte-load read stream over `bytes`

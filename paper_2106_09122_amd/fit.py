@@ -3,9 +3,9 @@
 ``simulate`` is S = A Z as a ``torch.autograd.Function`` whose backward is the
 adjoint A^T g (``psflib_apply_adjoint``); ``render_disk`` renders the
 parametric disk with its parameter gradient (``psflib_render_disk`` and
-``psflib_render_disk_grad``).  Chaining them gives d(loss)/d(theta) for any
-loss written in torch on the simulated image, e.g. the chi-square of
-``chi2``.  Both run the HIP kernels of libpsflib; torch only holds tensors and
+``psflib_render_disk_grad``); ``chi2`` is the chi-square misfit with its
+gradient in the image (``psflib_chi2``).  Chaining them gives d(loss)/d(theta);
+``loss_and_grad`` runs the chain directly, without the autograd tape.  Both run the HIP kernels of libpsflib; torch only holds tensors and
 the autograd tape.  This is the gradient analogue of the parameter retrieval
 the paper's conclusions plan (Sec. 5).
 """
@@ -64,18 +64,63 @@ def render_disk(theta: torch.Tensor, N: int, S: float, rmax: float) -> torch.Ten
     return _RenderDisk.apply(theta, N, S, rmax)
 
 
+def _float64_vec(x, name, M, dev):
+    if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.device == dev
+            and x.numel() == M):
+        raise ValueError(f"{name} must be a float64 tensor of {M} elements on {dev}")
+    return x.contiguous()
+
+
+class _Chi2(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, model, counts, var, K):
+        S = model.detach().contiguous()
+        if S.dtype != torch.float32:
+            raise ValueError("model must be a float32 image")
+        M = S.numel()
+        D = _float64_vec(counts, "counts", M, S.device)
+        V = _float64_vec(var, "var", M, S.device)
+        loss = torch.empty((), dtype=torch.float64, device=S.device)
+        grad = torch.empty_like(S)
+        psflib.chi2(M, float(K), S.data_ptr(), D.data_ptr(), V.data_ptr(), loss.data_ptr(),
+                    grad.data_ptr(), _stream(S.device))
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gL):
+        (grad,) = ctx.saved_tensors
+        return grad * gL.to(grad.dtype), None, None, None
+
+
 def chi2(model: torch.Tensor, counts: torch.Tensor, var: torch.Tensor, K: float) -> torch.Tensor:
-    """sum_i (K S_i - D_i)^2 / var_i, accumulated in float64."""
-    r = K * model.to(torch.float64) - counts
-    return (r * r / var).sum()
+    """sum_i (K S_i - D_i)^2 / var_i (``psflib_chi2``: float64, fixed-order sum),
+    differentiable in the float32 image S (backward: 2 K (K S_i - D_i) / var_i
+    from the same kernel)."""
+    return _Chi2.apply(model, counts, var, K)
 
 
 def loss_and_grad(lib, theta, counts, var, K, rmax):
-    """Chi-square of the simulated disk image and its gradient in theta."""
-    th = theta.detach().clone().requires_grad_(True)
-    L = chi2(simulate(lib, render_disk(th, lib.N, lib.S, rmax)), counts, var, K)
-    L.backward()
-    return L.detach(), th.grad.detach()
+    """Chi-square of the simulated disk image and its gradient in theta, every
+    step in the library's kernels: render Z(theta), S = A Z, the chi-square and
+    dL/dS, A^T (dL/dS), and dL/dtheta through the renderer's gradient."""
+    dev = counts.device
+    th = theta.detach().to(device=dev, dtype=torch.float64).contiguous()
+    st = _stream(dev)
+    N = lib.N
+    Z = torch.empty(N * N, dtype=torch.float32, device=dev)
+    psflib.render_disk(N, lib.S, rmax, th.data_ptr(), Z.data_ptr(), st)
+    S = lib.apply(Z)
+    M = S.numel()
+    D = _float64_vec(counts, "counts", M, dev)
+    V = _float64_vec(var, "var", M, dev)
+    L = torch.empty((), dtype=torch.float64, device=dev)
+    gS = torch.empty_like(S)
+    psflib.chi2(M, float(K), S.data_ptr(), D.data_ptr(), V.data_ptr(), L.data_ptr(), gS.data_ptr(), st)
+    gZ = lib.apply_adjoint(gS)
+    dth = torch.empty(5, dtype=torch.float64, device=dev)
+    psflib.render_disk_grad(N, lib.S, rmax, th.data_ptr(), gZ.data_ptr(), dth.data_ptr(), st)
+    return L, dth
 
 
 def fit_disk(lib, counts, var, K, theta0, rmax, steps: int = 64, lr: float = 0.05):

@@ -83,6 +83,7 @@ def _load():
         "psflib_grouped_set_shape": (I32, [P, ctypes.c_int64, ctypes.c_int32, P]),
         "psflib_grouped_destroy": (None, [P]),
         "psflib_render_disk_grad": (I32, [I32, ctypes.c_double, ctypes.c_double, P, P, P, P]),
+        "psflib_chi2": (I32, [ctypes.c_int64, ctypes.c_double, P, P, P, P, P, P]),
         "psflib_destroy": (None, [P]),
         "psflib_probe_hbm_read": (I32, [P, SZ, I32, I32, I32, P, P]),
         "psflib_probe_mfma": (I32, [I32, I32, I32, P, P]),
@@ -101,7 +102,7 @@ SYMBOLS = (
     "psflib_status_string", "psflib_last_error", "psflib_library_bytes", "psflib_build",
     "psflib_apply", "psflib_apply_noalloc", "psflib_apply_adjoint", "psflib_apply_batched", "psflib_column_sums",
     "psflib_get_columns", "psflib_get_exponents", "psflib_get_geometry", "psflib_destroy",
-    "psflib_render_disk", "psflib_render_disk_grad", "psflib_grouped_create",
+    "psflib_render_disk", "psflib_render_disk_grad", "psflib_chi2", "psflib_grouped_create",
     "psflib_grouped_run", "psflib_grouped_chunk", "psflib_grouped_shape", "psflib_grouped_set_shape",
     "psflib_grouped_destroy",
     "psflib_probe_hbm_read", "psflib_probe_mfma",
@@ -194,6 +195,13 @@ def render_disk(N: int, S: float, rmax: float, d_theta: int, d_scene: int, strea
     _check(_lib.psflib_render_disk(ctypes.c_int32(N), ctypes.c_double(S), ctypes.c_double(rmax),
                                    ctypes.c_void_p(d_theta), ctypes.c_void_p(d_scene),
                                    ctypes.c_void_p(stream)), "psflib_render_disk")
+
+
+def chi2(M: int, K: float, d_image: int, d_data: int, d_var: int, d_loss: int, d_grad: int,
+         stream: int):
+    _check(_lib.psflib_chi2(ctypes.c_int64(M), ctypes.c_double(K), ctypes.c_void_p(d_image),
+                            ctypes.c_void_p(d_data), ctypes.c_void_p(d_var), ctypes.c_void_p(d_loss),
+                            ctypes.c_void_p(d_grad), ctypes.c_void_p(stream)), "psflib_chi2")
 
 
 def render_disk_grad(N: int, S: float, rmax: float, d_theta: int, d_dscene: int, d_dtheta: int,

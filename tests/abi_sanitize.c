@@ -136,6 +136,11 @@ int main(void) {
   EXPECT(psflib_render_disk(8, 0.5, 8.0, fake_odd, fake, NULL) == PSFLIB_ERR_INVALID_ARG);
   EXPECT(psflib_render_disk_grad(8, 0.5, 8.0, fake, fake, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
   EXPECT(psflib_render_disk_grad(8, 0.5, 8.0, fake, fake, fake_odd, NULL) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_chi2(0, 1.0, (const float*)fake, fake, fake, (double*)fake, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_chi2(16, NAN, (const float*)fake, fake, fake, (double*)fake, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_chi2(16, 1.0, NULL, fake, fake, (double*)fake, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_chi2(16, 1.0, (const float*)fake, fake, fake, NULL, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
+  EXPECT(psflib_chi2(16, 1.0, (const float*)fake, fake_odd, fake, (double*)fake, NULL, NULL) == PSFLIB_ERR_INVALID_ARG);
 
   /* probes */
   EXPECT(psflib_probe_hbm_read(NULL, 1 << 20, 64, 8, 0, (float*)fake, NULL) == PSFLIB_ERR_INVALID_ARG);

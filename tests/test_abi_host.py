@@ -18,7 +18,7 @@ def header_symbols():
     with open(os.path.join(ROOT, "include", "psflib.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(psflib_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(psflib_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -127,6 +127,13 @@ def test_grouped_and_model_validation_without_device():
     assert _err(psflib.render_disk, 8, 0.5, 8.0, FAKE + 8, FAKE, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.render_disk, 8, 0.5, 8.0, FAKE, FAKE + 4, 0) == psflib.ERR_INVALID_ARG
     assert _err(psflib.render_disk_grad, 8, 0.5, 8.0, FAKE, FAKE, FAKE + 8, 0) == psflib.ERR_INVALID_ARG
+    # chi-square: size, scale, NULL and misaligned arrays (d_grad may be NULL)
+    assert _err(psflib.chi2, 0, 1.0, FAKE, FAKE, FAKE, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.chi2, 16, float("inf"), FAKE, FAKE, FAKE, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.chi2, 16, 1.0, FAKE, FAKE, 0, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.chi2, 16, 1.0, FAKE, FAKE, FAKE, 0, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.chi2, 16, 1.0, FAKE, FAKE + 8, FAKE, FAKE, 0, 0) == psflib.ERR_INVALID_ARG
+    assert _err(psflib.chi2, 16, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE + 4, 0) == psflib.ERR_INVALID_ARG
 
 
 def test_largest_library_size_is_representable():

@@ -37,6 +37,38 @@ def setup(torch):
     return d, lib, A, counts, K, var
 
 
+def test_chi2_kernel(torch):
+    """psflib_chi2 against the definition written out in float64 numpy: the
+    loss (an exactly rounded sum, math.fsum) within 1e-13 relative, the
+    gradient 2 K (K S - D) / var rounded once to float32 within one float32
+    unit; sizes from one pixel to several workgroups with a ragged tail; the
+    loss alone (no gradient array); repeated calls bitwise equal."""
+    from paper_2106_09122_amd import psflib
+    rng = np.random.default_rng(77)
+    st = torch.cuda.current_stream().cuda_stream
+    for M in (1, 255, 256, 1000, 65539):
+        S = (rng.random(M) * 1e-7).astype(np.float32)
+        K = 3.7e9
+        D = rng.poisson(K * S.astype(np.float64) + 5.0).astype(np.float64)
+        V = np.maximum(D, 1.0) + rng.random(M)
+        r = K * S.astype(np.float64) - D
+        Lref = math.fsum(r * r / V)
+        gref = ((2.0 * K) * r / V).astype(np.float32)
+        St, Dt, Vt = (torch.from_numpy(x).cuda() for x in (S, D, V))
+        L = torch.empty((), dtype=torch.float64, device="cuda")
+        g = torch.empty(M, dtype=torch.float32, device="cuda")
+        psflib.chi2(M, K, St.data_ptr(), Dt.data_ptr(), Vt.data_ptr(), L.data_ptr(), g.data_ptr(), st)
+        torch.cuda.synchronize()
+        assert abs(float(L) - Lref) <= 1e-13 * Lref, M
+        gg = g.cpu().numpy()
+        ulp = np.spacing(np.abs(gref).astype(np.float32))
+        assert np.all(np.abs(gg.astype(np.float64) - gref.astype(np.float64)) <= ulp), M
+        L2 = torch.empty((), dtype=torch.float64, device="cuda")
+        psflib.chi2(M, K, St.data_ptr(), Dt.data_ptr(), Vt.data_ptr(), L2.data_ptr(), 0, st)
+        torch.cuda.synchronize()
+        assert float(L2) == float(L), M
+
+
 def test_render_matches_oracle(torch, setup):
     from paper_2106_09122_amd import fit
     d = setup[0]
