@@ -58,6 +58,7 @@ __all__ = [
     "library_column", "build_library", "column_sums", "apply", "apply_adjoint",
     "apply_batched", "pow2_exponents", "column_max_bound", "round_to_format",
     "quantize_library", "scale_exponent", "ZERO_COLUMN_EXPONENT", "render_disk", "render_disk_grad",
+    "chi2",
 ]
 
 
@@ -463,3 +464,14 @@ def render_disk_grad(N: int, S: float, rmax: float, theta, dZ) -> np.ndarray:
     out[3] = np.sum(d * Z * np.log(rho / r0))
     out[4] = np.sum(d * Z / F)
     return out
+
+
+def chi2(S, D, var, K: float):
+    """Misfit of a simulated image for Gaussian errors, the quantity the
+    retrieval the paper's conclusions plan would minimise:
+    L = sum_i (K S_i - D_i)^2 / var_i, with its gradient in the image
+    dL/dS_i = 2 K (K S_i - D_i) / var_i.  float64; the sum is exactly rounded
+    (math.fsum).  Returns (L, gradient)."""
+    r = float(K) * np.asarray(S, dtype=np.float64) - np.asarray(D, dtype=np.float64)
+    v = np.asarray(var, dtype=np.float64)
+    return math.fsum((r * r / v).tolist()), (2.0 * float(K)) * r / v

@@ -38,11 +38,11 @@ def setup(torch):
 
 
 def test_chi2_kernel(torch):
-    """psflib_chi2 against the definition written out in float64 numpy: the
-    loss (an exactly rounded sum, math.fsum) within 1e-13 relative, the
-    gradient 2 K (K S - D) / var rounded once to float32 within one float32
-    unit; sizes from one pixel to several workgroups with a ragged tail; the
-    loss alone (no gradient array); repeated calls bitwise equal."""
+    """psflib_chi2 against the oracle's chi2 (float64, exactly rounded sum):
+    the loss within 1e-13 relative, the gradient 2 K (K S - D) / var rounded
+    once to float32 within one float32 unit; sizes from one pixel to several
+    workgroups with a ragged tail; the loss alone (no gradient array);
+    repeated calls bitwise equal."""
     from paper_2106_09122_amd import psflib
     rng = np.random.default_rng(77)
     st = torch.cuda.current_stream().cuda_stream
@@ -51,9 +51,8 @@ def test_chi2_kernel(torch):
         K = 3.7e9
         D = rng.poisson(K * S.astype(np.float64) + 5.0).astype(np.float64)
         V = np.maximum(D, 1.0) + rng.random(M)
-        r = K * S.astype(np.float64) - D
-        Lref = math.fsum(r * r / V)
-        gref = ((2.0 * K) * r / V).astype(np.float32)
+        Lref, g64 = O.chi2(S, D, V, K)
+        gref = g64.astype(np.float32)
         St, Dt, Vt = (torch.from_numpy(x).cuda() for x in (S, D, V))
         L = torch.empty((), dtype=torch.float64, device="cuda")
         g = torch.empty(M, dtype=torch.float32, device="cuda")

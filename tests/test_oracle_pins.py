@@ -564,3 +564,31 @@ def test_disk_face_on_is_radial_and_peaks_near_r0():
     # maximum of u^g exp(-(rho-r0)^2/2w^2): g/rho = (rho - r0)/w^2
     rho_star = (5.0 + math.sqrt(25.0 + 4 * 0.36 * -1.0)) / 2
     assert abs(peak - rho_star) <= S
+
+
+def test_chi2_pins():
+    """The misfit's definition pinned by what it must satisfy: zero at
+    D = K S (with a zero gradient), a one-pixel value worked by hand, the
+    gradient against FP64 central differences of the loss, and 1/var
+    scaling."""
+    S = np.array([2.0, 0.5, 1.25])
+    K = 4.0
+    L, g = O.chi2(S, K * S, np.ones(3), K)
+    assert L == 0.0 and np.all(g == 0.0)
+    # one pixel: (4*3 - 10)^2 / 2 = 2, gradient 2*4*(12 - 10)/2 = 8
+    L1, g1 = O.chi2([3.0], [10.0], [2.0], 4.0)
+    assert L1 == 2.0 and g1[0] == 8.0
+    rng = np.random.default_rng(5)
+    S = rng.random(7)
+    D = rng.random(7) * 4.0
+    V = 0.5 + rng.random(7)
+    L, g = O.chi2(S, D, V, 3.0)
+    for i in range(7):
+        h = 1e-6
+        Sp, Sm = S.copy(), S.copy()
+        Sp[i] += h
+        Sm[i] -= h
+        fd = (O.chi2(Sp, D, V, 3.0)[0] - O.chi2(Sm, D, V, 3.0)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
+    L2, g2 = O.chi2(S, D, 2.0 * V, 3.0)
+    assert abs(L2 - 0.5 * L) <= 1e-15 * L and np.allclose(g2, 0.5 * g, rtol=1e-15, atol=0)
