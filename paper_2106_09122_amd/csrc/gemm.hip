@@ -672,11 +672,11 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 a, const u32x4 b, const f32
 constexpr int kHRing = 4;    // ring slots
 constexpr int kHUnroll = 16; // stages per main-loop iteration (a multiple of kHRing)
 
-// NT: library loads with the non-temporal hint, for grids with one 128-scene
+// NT: library loads with the non-temporal hint, for grids with one scene
 // tile (no other workgroup re-reads a library block; B <= 128: 130 -> 120 us
-// at 128^2).  With several scene tiles the hint costs the L2 reuse (B = 1024:
-// +12%); the 256-scene tile (128 < B <= 256) measured the same either way and
-// keeps plain loads.
+// at 128^2; the 256-scene tile, 128 < B <= 256: ~2.4% at B = 160 and 256,
+// re-measured with the current staging).  With several scene tiles the hint
+// costs the L2 reuse (B = 1024: +12%).
 template <bool BF16, int TN, bool NT>
 __global__ __launch_bounds__(kGemmThreads, TN == 128 ? 2 : 1) void gemm_h16_kernel(
     const u32x4* Mp, const u32x4* Zg, const int32_t* __restrict__ fexp,
@@ -1168,7 +1168,7 @@ hipError_t launch_batched(int storage, const void* lib, const Cols16& cx, const 
       if (e != hipSuccess) return e;
       const u32x4* Mp = reinterpret_cast<const u32x4*>(lib);
       const H16Kind kind = h16_kind(bc);
-      e = launch_gemm_h16(bf, kind, kind == kH128 && p.nblocks == 1, grid, Mp, Zg, fexp, dst, M,
+      e = launch_gemm_h16(bf, kind, (kind == kH128 || kind == kH256) && p.nblocks == 1, grid, Mp, Zg, fexp, dst, M,
                           ngroups, bc, Bp, p, s);
     }
     if (e != hipSuccess) return e;
