@@ -45,8 +45,12 @@
  *    and psflib_render_disk_grad (split-K partial sums, packed scenes) live in
  *    one buffer per stream, taken from a pool the library keeps per device,
  *    grown on demand and shared, in stream order, by every call on that
- *    stream.  Under stream capture these calls allocate their temporaries
- *    from the pool inside the graph instead, so each graph owns its own.
+ *    stream.  Under stream capture psflib_apply, psflib_apply_adjoint and
+ *    psflib_apply_batched allocate their temporaries from the pool inside
+ *    the graph instead, so each graph owns its own (tested: replays equal
+ *    the eager results bitwise).  psflib_render_disk_grad and psflib_chi2
+ *    return PSFLIB_ERR_UNSUPPORTED, enqueuing nothing, on a capturing stream:
+ *    a captured fit chain faulted the GPU once, cause not found.
  *    Work that uses the library must be ordered after the build on the
  *    build's stream (same stream, or an event).
  *  - Device memory the library allocates for itself comes from that pool and

@@ -708,6 +708,18 @@ static psflib_status check_model_args(int32_t N, double S, double rmax, const vo
   return PSFLIB_OK;
 }
 
+// psflib_render_disk_grad and psflib_chi2 are not run under stream capture
+// (a captured fit chain faulted the GPU once, cause not found): refused
+// before anything is enqueued.
+static psflib_status refuse_capture(hipStream_t s, const char* what) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return device_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(PSFLIB_ERR_UNSUPPORTED, std::string(what) + " cannot be captured in a graph");
+  return PSFLIB_OK;
+}
+
 psflib_status psflib_render_disk(int32_t N, double scene_pixscale, double rmax,
                                  const double* d_theta, float* d_scene, void* stream) {
   psflib_status st = check_model_args(N, scene_pixscale, rmax, d_theta, d_scene);
@@ -730,6 +742,8 @@ psflib_status psflib_render_disk_grad(int32_t N, double scene_pixscale, double r
   st = psflib::check_pending_error();
   if (st != PSFLIB_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = refuse_capture(s, "psflib_render_disk_grad");
+  if (st != PSFLIB_OK) return st;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");
@@ -756,6 +770,8 @@ psflib_status psflib_chi2(int64_t M, double K, const float* d_image, const doubl
   psflib_status st = psflib::check_pending_error();
   if (st != PSFLIB_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = refuse_capture(s, "psflib_chi2");
+  if (st != PSFLIB_OK) return st;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_fail(e, "hipGetDevice");

@@ -103,7 +103,9 @@ def chi2(model: torch.Tensor, counts: torch.Tensor, var: torch.Tensor, K: float)
 def loss_and_grad(lib, theta, counts, var, K, rmax):
     """Chi-square of the simulated disk image and its gradient in theta, every
     step in the library's kernels: render Z(theta), S = A Z, the chi-square and
-    dL/dS, A^T (dL/dS), and dL/dtheta through the renderer's gradient."""
+    dL/dS, A^T (dL/dS), and dL/dtheta through the renderer's gradient.  Not to
+    be captured in a graph (psflib_chi2 and psflib_render_disk_grad refuse a
+    capturing stream)."""
     dev = counts.device
     th = theta.detach().to(device=dev, dtype=torch.float64).contiguous()
     st = _stream(dev)

@@ -68,6 +68,75 @@ def test_chi2_kernel(torch):
         assert float(L2) == float(L), M
 
 
+def test_fit_calls_refuse_capture(torch, setup):
+    """psflib_chi2 and psflib_render_disk_grad return PSFLIB_ERR_UNSUPPORTED on a
+    capturing stream, before enqueuing anything (their capture is not
+    supported); no kernel runs in this test."""
+    from paper_2106_09122_amd import psflib
+    d, lib, A, counts, K, var = setup
+    M, N = lib.M, lib.N
+    S = torch.zeros(M, device="cuda")
+    D = torch.zeros(M, dtype=torch.float64, device="cuda")
+    V = torch.ones(M, dtype=torch.float64, device="cuda")
+    L = torch.empty((), dtype=torch.float64, device="cuda")
+    g = torch.empty(M, device="cuda")
+    th = torch.tensor(synth.DISK_START, dtype=torch.float64, device="cuda")
+    dZ = torch.zeros(N * N, device="cuda")
+    dth = torch.empty(5, dtype=torch.float64, device="cuda")
+    calls = (
+        lambda st: psflib.chi2(M, 1.0, S.data_ptr(), D.data_ptr(), V.data_ptr(), L.data_ptr(),
+                               g.data_ptr(), st),
+        lambda st: psflib.render_disk_grad(N, lib.S, RMAX, th.data_ptr(), dZ.data_ptr(),
+                                           dth.data_ptr(), st),
+    )
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for call in calls:
+        graph = torch.cuda.CUDAGraph()
+        with pytest.raises(psflib.PsflibError) as e:
+            with torch.cuda.graph(graph, stream=side):
+                call(side.cuda_stream)
+        assert e.value.status == psflib.ERR_UNSUPPORTED
+        del graph
+    torch.cuda.synchronize()
+
+
+@pytest.mark.skip(reason="faulted the GPU once (illegal address) on its first run; cause not "
+                         "found by reading the library or the test, so graph capture of "
+                         "psflib_render_disk_grad / psflib_chi2 is not claimed")
+def test_fit_chain_in_a_graph(torch, setup):
+    """The loss-and-gradient chain (render, S = A Z, chi-square, A^T, render
+    gradient; the chi-square and render gradient take their temporaries from
+    the stream's pool) captured in a HIP graph: every replay, with eager work
+    and synchronisations between replays, equals the eager result bitwise."""
+    from paper_2106_09122_amd import fit
+    d, lib, A, counts, K, var = setup
+    ct = torch.from_numpy(counts).cuda()
+    vt = torch.from_numpy(var).cuda()
+    th = torch.tensor(synth.DISK_START, dtype=torch.float64, device="cuda")
+    L0, g0 = fit.loss_and_grad(lib, th, ct, vt, K, RMAX)
+    L0, g0 = L0.clone(), g0.clone()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        fit.loss_and_grad(lib, th, ct, vt, K, RMAX)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        L, g = fit.loss_and_grad(lib, th, ct, vt, K, RMAX)
+    for rep in range(3):
+        L.zero_()
+        g.zero_()
+        fit.loss_and_grad(lib, 1.01 * th, ct, vt, K, RMAX)  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L, L0) and torch.equal(g, g0), rep
+    del graph
+
+
 def test_render_matches_oracle(torch, setup):
     from paper_2106_09122_amd import fit
     d = setup[0]
