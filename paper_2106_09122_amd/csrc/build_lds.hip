@@ -17,19 +17,16 @@
 // combinations).
 //
 // Paths, by what fits:
-//  * rotation orbits (the pair fits the LDS): the four quarter turns of a
-//    scene pixel about the star have bitwise-rotated columns, so one wave
-//    forms a base column and writes all four (float32: 16-byte runs straight
-//    from registers; 16-bit: rounded into an LDS tile of 8-slot units, slots
-//    ordered so that a group holds one quarter turn of 8 base columns);
+//  * rotation orbits: the four quarter turns of a scene pixel about the star
+//    have bitwise-rotated columns, so one wave forms a base column and writes
+//    all four (float32: 16-byte runs straight from registers; 16-bit: rounded
+//    into an LDS tile of 8-slot units, slots ordered so that a group holds one
+//    quarter turn of 8 base columns).  The pair is staged whole when it fits
+//    the LDS; larger pairs (up to 256 x 256) are read through a small box per
+//    32 x 32 pixel tile, staged by each wave in its own LDS region;
 //  * columns in bracket order (16-bit forms whose scene size is not a multiple
-//    of 8): one wave per column, 16 columns per workgroup, units assembled
-//    from an LDS tile;
-//  * row bands (pairs larger than the LDS, up to 256 x 256): one wave per
-//    column, the pair staged a band of rows at a time; the 16-bit forms (scene
-//    sides a multiple of 16) round each value in the build and stage 2-byte
-//    columns, a chunk at a time, which a second kernel interleaves into the
-//    8-slot groups.
+//    of 8, pairs that fit the LDS): one wave per column, 16 columns per
+//    workgroup, units assembled from an LDS tile.
 // The 16-bit forms of the other builds (and of columns that need float32
 // post-processing, the flux-preserving rescale) are built as float32 columns
 // into scratch and packed by a second kernel (scale by 2^-e_j, round to
@@ -282,242 +279,6 @@ __global__ __launch_bounds__(1024) void build_lds_kernel(const float* __restrict
   }
   tsum = wave_sum_f64(tsum);
   if (lane == 0) tau[j] = tsum;
-}
-
-// PSFs whose bordered pair exceeds the LDS are staged in bands of H rows of
-// the bordered array that overlap by one row: band b holds bordered rows
-// [b (H-1), b (H-1) + H).  The two tap rows of an output pixel, R = r0 + 1
-// and R + 1, both lie in band b when b (H-1) <= R <= b (H-1) + H - 2 (the
-// last band takes every R up to n), so each pixel is produced in exactly one
-// band; pixels whose taps miss the array in the row direction are zeros,
-// written in the first band (R < 0) or the last (R > n).  Per band and block
-// of 64 image columns, a conservative range of image rows that can reach the
-// band is derived from the column's angle (the extreme source rows of the
-// block's end pixels, with a margin); over those rows every lane forms its
-// pixel's row coordinate (the oracle's float64 operations) to test membership
-// exactly, and does the rest of the element's work only for pixels of the
-// band.  A wave builds a column j of the first half of the scene grid (or the
-// centre of an odd grid) and, in the same step, its half turn about the star,
-// column N^2-1-j, whose entry (n-1-a, n-1-b) is entry (a, b) of column j (the
-// same float64 products, negated twice); every element is written once.
-// OUT: 0 = float32 columns; 1, 2 = the columns rounded to BF16 / FP16 after
-// scaling by 2^-e_j (the column's exponent, known from the geometry), the
-// values packing would give, as 2-byte column-major staging.
-template <int OUT>
-__device__ __forceinline__ uint16_t band_round16(float v, int32_t e) {
-  const float x = ldexpf(v, -e);
-  if constexpr (OUT == 1) {
-    uint32_t w = __float_as_uint(x);
-    w += 0x7FFFu + ((w >> 16) & 1u);
-    return (uint16_t)(w >> 16);
-  } else {
-    return __builtin_bit_cast(uint16_t, (_Float16)x);
-  }
-}
-
-template <int E, bool FULL, int OUT>
-__global__ __launch_bounds__(1024) void build_band_kernel(const float* __restrict__ cube, int K,
-                                                          const ColGeom* __restrict__ geo,
-                                                          const int32_t* __restrict__ order,
-                                                          const int4* __restrict__ items,
-                                                          const int32_t* __restrict__ nitems,
-                                                          int nb, int n, int ls, int H, int nbands,
-                                                          int64_t M, int64_t ncols, int64_t jbase,
-                                                          void* __restrict__ A_lo,
-                                                          void* __restrict__ A_hi, int64_t p0,
-                                                          double* __restrict__ tau) {
-  using T = typename std::conditional<OUT == 0, float, uint16_t>::type;
-  // order[] holds columns relative to jbase (absolute column jbase + j, at
-  // A_lo + j M); the half turn j2 = ncols-1-(jbase+j) goes to A_hi + (j2 - p0) M
-  extern __shared__ float2 P2[];  // H rows of the bordered pair array, row stride ls
-  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
-  const int4 it = items[blockIdx.x];
-  const int bkt = it.x, start = it.y, len = it.z;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int np = n + 2;
-  if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
-    if (wave >= len) return;
-    const int64_t jr = order[start + wave], j = jbase + jr, j2 = ncols - 1 - j;
-    T* col = reinterpret_cast<T*>(A_lo) + jr * M;
-    T* col2 = reinterpret_cast<T*>(A_hi) + (j2 - p0) * M;
-    for (int a = 0; a < n; ++a)
-#pragma unroll
-      for (int v = 0; v < E; ++v) {
-        const int b = lane + 64 * v;
-        if (FULL || b < n) {
-          __builtin_nontemporal_store((T)0, col + a * n + b);
-          if (j2 != j) __builtin_nontemporal_store((T)0, col2 + a * n + b);
-        }
-      }
-    if (lane == 0) tau[j] = tau[j2] = 0.0;
-    return;
-  }
-  const float* Pk = cube + (int64_t)bkt * M;
-  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
-  const bool live = wave < len;
-  int64_t jr = 0;
-  ColGeom g;
-  g.ct = 1.0; g.st = 0.0; g.w = 0.0;
-  if (live) {
-    jr = order[start + wave];
-    g = geo[jbase + jr];
-  }
-  // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
-  const int64_t j = jbase + jr, j2 = ncols - 1 - j;
-  const bool pair = j2 != j;
-  T* col = reinterpret_cast<T*>(A_lo) + jr * M;
-  T* col2 = reinterpret_cast<T*>(A_hi) + (j2 - p0) * M;
-  // 16-bit staging: the half turn has the same radius, so the same exponent
-  const int32_t ecol = (OUT != 0 && live) ? g.e : 0;
-  const double c = (double)(n - 1) * 0.5;
-  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
-  double ctux[E], mstux[E];
-#pragma unroll
-  for (int v = 0; v < E; ++v) {
-#pragma clang fp contract(off)
-    const double ux = (double)(lane + 64 * v) - c;
-    ctux[v] = g.ct * ux;
-    mstux[v] = (-g.st) * ux;
-  }
-  const bool vec = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(cube) & 15) == 0;
-  double tsum = 0.0;
-  for (int bi = 0; bi < nbands; ++bi) {
-    const int s0 = bi * (H - 1);
-    const int rows = (np - s0 < H) ? np - s0 : H;
-    const int lo = s0, hi = (bi == nbands - 1) ? n : s0 + H - 2;
-    __syncthreads();  // the previous band's reads are done
-    // bordered rows s0 .. s0+rows-1: zero border rows and columns, PSF rows inside
-    for (int r = tid; r < rows; r += 1024) {
-      P2[r * ls] = make_float2(0.0f, 0.0f);
-      P2[r * ls + np - 1] = make_float2(0.0f, 0.0f);
-    }
-    if (vec) {
-      const int nq = n >> 2;
-      for (int q = tid; q < rows * nq; q += 1024) {
-        const int r = q / nq, cc = 4 * (q - r * nq);
-        const int pr = s0 + r - 1;  // PSF row
-        f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f};
-        if ((unsigned)pr < (unsigned)n) {
-          x = *reinterpret_cast<const f32x4*>(Pk + pr * n + cc);
-          if (Pk1) y = *reinterpret_cast<const f32x4*>(Pk1 + pr * n + cc);
-        }
-        float2* dst = P2 + r * ls + cc + 1;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[e] = make_float2(x[e], y[e]);
-      }
-    } else {
-      for (int q = tid; q < rows * n; q += 1024) {
-        const int r = q / n, cc = q - r * n;
-        const int pr = s0 + r - 1;
-        float2 v = make_float2(0.0f, 0.0f);
-        if ((unsigned)pr < (unsigned)n) v = make_float2(Pk[pr * n + cc], Pk1 ? Pk1[pr * n + cc] : 0.0f);
-        P2[r * ls + cc + 1] = v;
-      }
-    }
-    __syncthreads();
-    if (!live) continue;
-    // Rows a whose pixels in lane block v can have R in [lo, hi] (the first
-    // band open below, the last open above): the source row is
-    // c - st (b - c) + ct (a - c) up to rounding, so over the block's ends
-    // b0, b1 it spans [c + m1 + ct (a - c), c + m2 + ct (a - c)], which must meet
-    // [lo - 1, hi + 1] (a margin of a row on each side, and 1e-6).
-    int alo[E], ahi[E], afirst = n, alast = -1;
-#pragma unroll
-    for (int v = 0; v < E; ++v) {
-      const double b0 = (double)(64 * v) - c;
-      const double b1 = (double)((64 * v + 63 < n - 1) ? 64 * v + 63 : n - 1) - c;
-      const double t0 = -g.st * b0, t1 = -g.st * b1;
-      const double m1 = fmin(t0, t1), m2 = fmax(t0, t1);
-      const double LO = (bi == 0) ? -1e30 : (double)lo - 1.0 - 1e-6;
-      const double HI = (bi == nbands - 1) ? 1e30 : (double)hi + 1.0 + 1e-6;
-      const double U1 = LO - c - m2, U2 = HI - c - m1;  // need U1 <= ct (a - c) <= U2
-      double amin, amax;
-      if (g.ct > 1e-9) {
-        amin = c + U1 / g.ct;
-        amax = c + U2 / g.ct;
-      } else if (g.ct < -1e-9) {
-        amin = c + U2 / g.ct;
-        amax = c + U1 / g.ct;
-      } else {  // |ct| tiny: ct (a - c) is ~0 for every row
-        const bool any = U1 <= 1e-6 && U2 >= -1e-6;
-        amin = any ? -1e30 : 1e30;
-        amax = any ? 1e30 : -1e30;
-      }
-      amin = fmax(floor(amin) - 1.0, 0.0);
-      amax = fmin(ceil(amax) + 1.0, (double)(n - 1));
-      alo[v] = __builtin_amdgcn_readfirstlane((int)fmin(amin, (double)n));
-      ahi[v] = __builtin_amdgcn_readfirstlane((int)fmax(amax, -1.0));
-      afirst = alo[v] < afirst ? alo[v] : afirst;
-      alast = ahi[v] > alast ? ahi[v] : alast;
-    }
-    for (int a = afirst; a <= alast; ++a) {
-      double stuy, ctuy;
-      {
-#pragma clang fp contract(off)
-        const double uy = (double)a - c;
-        stuy = g.st * uy;
-        ctuy = g.ct * uy;
-      }
-      float rowsum = 0.0f;
-#pragma unroll
-      for (int v = 0; v < E; ++v) {
-        if (a < alo[v] || a > ahi[v]) continue;  // uniform
-        const int b = lane + 64 * v;
-        if (!(FULL || b < n)) continue;
-        int R;
-        double rowf;
-        {
-#pragma clang fp contract(off)
-          const double sy = mstux[v] + ctuy;
-          rowf = c + sy;
-          R = (int)floor(rowf) + 1;  // |rowf| < 3n: exact
-        }
-        const bool rok = (unsigned)R <= (unsigned)n;
-        const int Rc = R < 0 ? 0 : (R > n ? n : R);  // rows off the array: first or last band
-        if (Rc < lo || Rc > hi) continue;
-        double colf;
-        {
-#pragma clang fp contract(off)
-          const double sx = ctux[v] + stuy;
-          colf = c + sx;
-        }
-        const double c0f = floor(colf), r0f = (double)(R - 1);
-        const double fx = colf - c0f, fy = rowf - r0f;
-        const float tfx = (float)fx, tgx = (float)(1.0 - fx);
-        const float tfy = (float)fy, tgy = (float)(1.0 - fy);
-        const int C = (int)c0f + 1;
-        const bool ok = rok && (unsigned)C <= (unsigned)n;
-        const int idx = ok ? (R - s0) * ls + C : 0;
-        const float2 p00 = P2[idx], p01 = P2[idx + 1];
-        const float2 p10 = P2[idx + ls], p11 = P2[idx + ls + 1];
-        const float q00 = fmaf(wk1, p00.y, wk0 * p00.x);
-        const float q01 = fmaf(wk1, p01.y, wk0 * p01.x);
-        const float q10 = fmaf(wk1, p10.y, wk0 * p10.x);
-        const float q11 = fmaf(wk1, p11.y, wk0 * p11.x);
-        float val = (tgy * tgx) * q00;
-        val = fmaf(tgy * tfx, q01, val);
-        val = fmaf(tfy * tgx, q10, val);
-        val = fmaf(tfy * tfx, q11, val);
-        val = ok ? val : 0.0f;
-        if constexpr (OUT == 0) {
-          __builtin_nontemporal_store(val, col + a * n + b);
-          if (pair) __builtin_nontemporal_store(val, col2 + (n - 1 - a) * n + (n - 1 - b));
-        } else {
-          const uint16_t h = band_round16<OUT>(val, ecol);
-          __builtin_nontemporal_store(h, col + a * n + b);
-          if (pair) __builtin_nontemporal_store(h, col2 + (n - 1 - a) * n + (n - 1 - b));
-        }
-        rowsum += val;
-      }
-      tsum += (double)rowsum;
-    }
-  }
-  if (!live) return;
-  tsum = wave_sum_f64(tsum);
-  if (lane == 0) {
-    tau[j] = tsum;
-    if (pair) tau[j2] = tsum;
-  }
 }
 
 // ------------------------------------------- 16-bit build, slot order -----
@@ -1200,6 +961,229 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
+// Float32 orbit build for pairs larger than the LDS (141 < n <= 256).  The
+// rotation map is affine, so a 32 x 32 tile of the base column draws its taps
+// from a small box of the bordered pair: every float64 step of the source
+// coordinates (the products with the cosine and sine, the two sums) is
+// correctly rounded, hence monotone in the pixel's column for a fixed row and
+// in its row for a fixed column, so the extreme source rows and columns over a
+// tile are those of its four corners, exactly.  The box spans at most
+// 31 (|cos| + |sin|) <= 43.85 source units, i.e. at most 45 tap origins and 46
+// rows (columns) of the bordered array.  Each wave stages its tile's box in a
+// private LDS region, already blended along the radius (the value
+// (1-w) P_k + w P_{k+1} at each pixel, formed with the same float32 operations
+// as the pair kernels' taps, so the entries are bitwise theirs), then forms the
+// tile's 4 x 4 blocks and writes the four quarter turns as build_orbit_kernel
+// does.  Sixteen waves per workgroup, 8.6 KiB of LDS each; no workgroup
+// barrier (a wave orders its own LDS writes and reads).
+constexpr int kFpSpan = 46;                     // box rows or columns, at most
+constexpr int kFpRegion = kFpSpan * (kFpSpan + 1);  // floats per wave (odd row stride)
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// floor of the source row and column of image pixel (a, b) (tap_coords' steps)
+__device__ __forceinline__ void tap_origin(const ColGeom& g, double c, int a, int b, int& r0, int& c0) {
+#pragma clang fp contract(off)
+  const double ux = (double)b - c, uy = (double)a - c;
+  const double ctux = g.ct * ux, mstux = (-g.st) * ux;
+  const double stuy = g.st * uy, ctuy = g.ct * uy;
+  const double colf = c + (ctux + stuy);
+  const double rowf = c + (mstux + ctuy);
+  c0 = (int)floor(colf);
+  r0 = (int)floor(rowf);
+}
+
+// one element from the staged box (origin: bordered row Rlo, column Clo)
+__device__ __forceinline__ float box_value(const float* __restrict__ Q, double ctux, double mstux,
+                                           double stuy, double ctuy, double c, int n, int bs,
+                                           int base) {
+  const Tap t = tap_coords(ctux, mstux, stuy, ctuy, c, n, bs);
+  const int i = t.ok ? t.idx - base : 0;
+  const float q00 = Q[i], q01 = Q[i + 1];
+  const float q10 = Q[i + bs], q11 = Q[i + bs + 1];
+  float val = (t.gy * t.gx) * q00;
+  val = fmaf(t.gy * t.fx, q01, val);
+  val = fmaf(t.fy * t.gx, q10, val);
+  val = fmaf(t.fy * t.fx, q11, val);
+  return t.ok ? val : 0.0f;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __restrict__ cube, int K,
+                                                               const ColGeom* __restrict__ geo,
+                                                               const int32_t* __restrict__ reps,
+                                                               const int4* __restrict__ items,
+                                                               const int32_t* __restrict__ nitems,
+                                                               int nb, int n, int N, int64_t M,
+                                                               int rpr, int64_t nreps,
+                                                               float* __restrict__ A,
+                                                               double* __restrict__ part) {
+  extern __shared__ float QS[];  // 16 regions of kFpRegion floats
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  const int sp = w0 + wave;
+  if (sp < first || sp >= first + len) return;  // uniform per wave; no workgroup barrier
+  const int64_t j0 = reps[sp];
+  const bool centre = orbit_is_centre(j0, N);
+  float* C0 = A + j0 * M;
+  float* C1 = A + orbit_member(j0, N, 1) * M;
+  float* C2 = A + orbit_member(j0, N, 2) * M;
+  float* C3 = A + orbit_member(j0, N, 3) * M;
+  if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
+    for (int x = lane; x < (rb - ra) * n; x += 64) {
+      const int64_t p = (int64_t)ra * n + x;
+      __builtin_nontemporal_store(0.0f, C0 + p);
+      if (!centre) {
+        __builtin_nontemporal_store(0.0f, C1 + p);
+        __builtin_nontemporal_store(0.0f, C2 + p);
+        __builtin_nontemporal_store(0.0f, C3 + p);
+      }
+    }
+    if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = 0.0;
+    return;
+  }
+  float* Q = QS + wave * kFpRegion;
+  const float* Pk = cube + (int64_t)bkt * M;
+  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+  const ColGeom g = geo[j0];
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const int li = lane >> 3, lk = lane & 7;
+  double tsum = 0.0;
+  for (int a0 = ra; a0 < rb; a0 += 32) {
+    const int ae = (a0 + 32 < rb) ? a0 + 32 : rb;
+    const int ab = a0 + 4 * li;
+    for (int b0 = 0; b0 < n; b0 += 32) {
+      const int be = (b0 + 32 < n) ? b0 + 32 : n;
+      // the tile's box of bordered rows [Rlo, Rlo + bh) and columns [Clo, Clo + bw)
+      int rmin, rmax, cmin, cmax;
+      {
+        int r0, c0;
+        tap_origin(g, c, a0, b0, r0, c0);
+        rmin = rmax = r0;
+        cmin = cmax = c0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          tap_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, r0, c0);
+          rmin = min(rmin, r0);
+          rmax = max(rmax, r0);
+          cmin = min(cmin, c0);
+          cmax = max(cmax, c0);
+        }
+      }
+      const int Rlo = max(rmin + 1, 0), Clo = max(cmin + 1, 0);
+      const int bh = min(max(min(rmax + 2, n + 1) - Rlo + 1, 0), kFpSpan);
+      const int bw = min(max(min(cmax + 2, n + 1) - Clo + 1, 0), kFpSpan);
+      const int bs = bw | 1;
+      wave_lds_sync();  // the previous tile's reads are done
+      if (bh > 0 && bw > 0) {
+        const int q64 = 64 / bw, r64 = 64 - q64 * bw;
+        int rr = lane / bw, cc = lane - rr * bw;
+        while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
+          float xv[8], yv[8];
+          int dst[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int R = Rlo + rr, C = Clo + cc;
+            const bool in = rr < bh;
+            const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
+            const int off = (R - 1) * n + (C - 1);
+            xv[k] = inner ? Pk[off] : 0.0f;
+            yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
+            dst[k] = in ? rr * bs + cc : -1;
+            cc += r64;
+            rr += q64;
+            if (cc >= bw) {
+              cc -= bw;
+              ++rr;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
+        }
+      }
+      wave_lds_sync();  // the box is staged
+      const int base = Rlo * bs + Clo;
+      const int bb = b0 + 4 * lk;
+      if (ab >= ae || bb >= be) continue;  // VEC: the whole block is outside the tile
+      double ctux[4], mstux[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma clang fp contract(off)
+        const double ux = (double)(bb + q) - c;
+        ctux[q] = g.ct * ux;
+        mstux[q] = (-g.st) * ux;
+      }
+      float x[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = ab + r;
+        double stuy, ctuy;
+        {
+#pragma clang fp contract(off)
+          const double uy = (double)a - c;
+          stuy = g.st * uy;
+          ctuy = g.ct * uy;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[r][q] = 0.0f;
+          if (VEC || (a < ae && bb + q < be)) {
+            x[r][q] = box_value(Q, ctux[q], mstux[q], stuy, ctuy, c, n, bs, base);
+            tsum += (double)x[r][q];
+          }
+          if (q == 1) __builtin_amdgcn_sched_barrier(0);  // two elements in flight
+        }
+        if constexpr (VEC) {  // the row's runs of C0 and C2
+          __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
+                                      reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
+          if (!centre)
+            __builtin_nontemporal_store((f32x4){x[r][3], x[r][2], x[r][1], x[r][0]},
+                                        reinterpret_cast<f32x4*>(C2 + (int64_t)(n - 1 - a) * n + (n - 4 - bb)));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (VEC) {
+        if (!centre) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = bb + q;
+            __builtin_nontemporal_store((f32x4){x[3][q], x[2][q], x[1][q], x[0][q]},
+                                        reinterpret_cast<f32x4*>(C1 + (int64_t)b * n + (n - 4 - ab)));
+            __builtin_nontemporal_store((f32x4){x[0][q], x[1][q], x[2][q], x[3][q]},
+                                        reinterpret_cast<f32x4*>(C3 + (int64_t)(n - 1 - b) * n + ab));
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int a = ab + r, b = bb + q;
+            if (a >= ae || b >= be) continue;
+            __builtin_nontemporal_store(x[r][q], C0 + (int64_t)a * n + b);
+            if (centre) continue;
+            __builtin_nontemporal_store(x[r][q], C1 + (int64_t)b * n + (n - 1 - a));
+            __builtin_nontemporal_store(x[r][q], C2 + (int64_t)(n - 1 - a) * n + (n - 1 - b));
+            __builtin_nontemporal_store(x[r][q], C3 + (int64_t)(n - 1 - b) * n + a);
+          }
+      }
+    }
+  }
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
 // 16-bit orbit build (N a multiple of 8: no centre, whole blocks of 8 bases).
 // A window of 16 bases is two blocks; block h's member k is group
 // 4 (w0/8 + h) + k, whose unit at an image pixel holds the 8 bases' member
@@ -1340,6 +1324,192 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
+// 16-bit orbit build for pairs larger than the LDS (141 < n <= 256, N a
+// multiple of 8): build_orbit16_kernel's unit tiles and copies, with each
+// wave's taps read from a staged box (as build_orbit_box_kernel) of the 32 x 32
+// pixels it forms as four 8 x 32 tiles.  LDS: 16 box regions, then the two
+// unit tiles.
+template <bool BF16>
+__global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __restrict__ cube, int K,
+                                                                 const ColGeom* __restrict__ geo,
+                                                                 const int32_t* __restrict__ reps,
+                                                                 const int4* __restrict__ items,
+                                                                 const int32_t* __restrict__ nitems,
+                                                                 int nb, int n, int64_t M, int rpr,
+                                                                 int64_t nreps,
+                                                                 uint16_t* __restrict__ Mh,
+                                                                 double* __restrict__ part) {
+  constexpr int TA = 8, TB = 32, TP = TB + 1;
+  constexpr int TILE = 2 * TA * TP * 8;  // uint16 per buffer
+  extern __shared__ float QS[];
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  uint16_t* tiles = reinterpret_cast<uint16_t*>(QS + 16 * kFpRegion);
+  float* Q = QS + wave * kFpRegion;
+  const int sp = w0 + wave;
+  const bool live = sp >= first && sp < first + len;  // uniform per wave
+  const int h = wave >> 3, u = wave & 7;
+  ColGeom g;
+  g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
+  if (live) g = geo[reps[sp]];
+  const double c = (double)(n - 1) * 0.5;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const float* Pk = cube + (int64_t)(zero_bucket ? 0 : bkt) * M;
+  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
+  const int64_t G0 = (int64_t)(w0 / 8) * 4;
+  int lo[2], hi[2];  // the item's slots of each block, relative to the block
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int s0 = w0 + 8 * q;
+    lo[q] = (first > s0) ? first - s0 : 0;
+    hi[q] = (first + len < s0 + 8) ? first + len - s0 : 8;
+  }
+  const int li = lane >> 3, lk = lane & 7;
+  // copy roles: threads 0..511 along rows, 512..1023 along columns
+  const bool along_cols = tid >= 512;
+  const int cq = (tid & 511) >> 8, crem = tid & 255;
+  double tsum = 0.0;
+  int buf = 0;
+  for (int a0 = ra; a0 < rb; a0 += 32) {
+    const int ae = (a0 + 32 < rb) ? a0 + 32 : rb;
+    for (int b0 = 0; b0 < n; b0 += TB) {
+      const int be = (b0 + TB < n) ? b0 + TB : n;
+      int bs = 1, base = 0;
+      if (live && !zero_bucket) {  // uniform per wave: stage the box of rows [a0, ae), columns [b0, be)
+        int rmin, rmax, cmin, cmax;
+        {
+          int r0, c0;
+          tap_origin(g, c, a0, b0, r0, c0);
+          rmin = rmax = r0;
+          cmin = cmax = c0;
+#pragma unroll
+          for (int k = 1; k < 4; ++k) {
+            tap_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, r0, c0);
+            rmin = min(rmin, r0);
+            rmax = max(rmax, r0);
+            cmin = min(cmin, c0);
+            cmax = max(cmax, c0);
+          }
+        }
+        const int Rlo = max(rmin + 1, 0), Clo = max(cmin + 1, 0);
+        const int bh = min(max(min(rmax + 2, n + 1) - Rlo + 1, 0), kFpSpan);
+        const int bw = min(max(min(cmax + 2, n + 1) - Clo + 1, 0), kFpSpan);
+        bs = bw | 1;
+        base = Rlo * bs + Clo;
+        if (bh > 0 && bw > 0) {
+          const int q64 = 64 / bw, r64 = 64 - q64 * bw;
+          int rr = lane / bw, cc = lane - rr * bw;
+          while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
+            float xv[8], yv[8];
+            int dst[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int R = Rlo + rr, C = Clo + cc;
+              const bool in = rr < bh;
+              const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
+              const int off = (R - 1) * n + (C - 1);
+              xv[k] = inner ? Pk[off] : 0.0f;
+              yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
+              dst[k] = in ? rr * bs + cc : -1;
+              cc += r64;
+              rr += q64;
+              if (cc >= bw) {
+                cc -= bw;
+                ++rr;
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
+          }
+        }
+        wave_lds_sync();  // the box is staged
+      }
+      for (int a1 = a0; a1 < ae; a1 += TA, buf ^= 1) {  // uniform over the workgroup
+        uint16_t* tile = tiles + buf * TILE;
+        if (live) {
+          const int a = a1 + li, bb = b0 + 4 * lk;
+          if (a < ae) {
+            double stuy, ctuy;
+            {
+#pragma clang fp contract(off)
+              const double uy = (double)a - c;
+              stuy = g.st * uy;
+              ctuy = g.ct * uy;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (bb + q >= n) continue;
+              double ctux, mstux;
+              {
+#pragma clang fp contract(off)
+                const double ux = (double)(bb + q) - c;
+                ctux = g.ct * ux;
+                mstux = (-g.st) * ux;
+              }
+              const float val = zero_bucket ? 0.0f
+                                            : box_value(Q, ctux, mstux, stuy, ctuy, c, n, bs, base);
+              tsum += (double)val;
+              const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
+              uint32_t hv;
+              if constexpr (BF16) {
+                uint32_t w = __float_as_uint(xs);
+                w += 0x7FFFu + ((w >> 16) & 1u);  // finite: round to nearest, ties to even
+                hv = w >> 16;
+              } else {
+                hv = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)xs);
+              }
+              tile[((h * TA + li) * TP + 4 * lk + q) * 8 + u] = (uint16_t)hv;
+            }
+          }
+        }
+        __syncthreads();
+        // one unit per thread: block cq, 8 rows x 32 columns
+        if (lo[cq] < hi[cq]) {
+          int r, cb;
+          if (along_cols) {
+            cb = crem >> 3;
+            r = crem & 7;
+          } else {
+            r = crem >> 5;
+            cb = crem & 31;
+          }
+          const int a = a1 + r, b = b0 + cb;
+          if (a < ae && b < n) {
+            const uint16_t* src = tile + ((cq * TA + r) * TP + cb) * 8;
+            uint16_t* dA;
+            uint16_t* dB;
+            if (along_cols) {
+              dA = Mh + ((G0 + 4 * cq + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
+              dB = Mh + ((G0 + 4 * cq + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
+            } else {
+              dA = Mh + ((G0 + 4 * cq + 0) * M + (int64_t)a * n + b) * 8;
+              dB = Mh + ((G0 + 4 * cq + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
+            }
+            if (lo[cq] == 0 && hi[cq] == 8) {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dA));
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dB));
+            } else {
+              for (int s = lo[cq]; s < hi[cq]; ++s) {
+                dA[s] = src[s];
+                dB[s] = src[s];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!live) return;
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
 // ------------------------------------------------------------- launch -----
 static int lds_e(int n) { return (n + 63) / 64; }
 
@@ -1357,20 +1527,14 @@ static bool pair_fits_lds(int n) {
   return (size_t)(n + 2) * (n + 2) * sizeof(float2) <= (size_t)kLdsBuildMaxBytes;
 }
 
-// banded staging: row stride n+2 rounded up to 5 mod 8 (as lds_stride), and
-// the rows of that stride that fit the LDS
-static int band_stride(int n) {
-  const int np = n + 2;
-  return np + ((5 - np % 8) + 8) % 8;
-}
-static int band_rows(int n) { return (int)((size_t)kLdsBuildMaxBytes / ((size_t)band_stride(n) * sizeof(float2))); }
+static bool orbit_sort_fits(int K, int N);
 
-bool build_lds_supported(int n, int K) {
-  // the bordered pair fits the LDS whole, or in bands of at least 16 rows with
-  // at most 4 image columns per lane; the bucket histograms (8 B per bucket)
+bool build_lds_supported(int n, int K, int N) {
+  // the bordered pair fits the LDS whole, or (up to 256 x 256) the orbit
+  // builds stage a box of it per tile; the bucket histograms (8 B per bucket)
   // must fit the sort kernels' LDS
   if (K > 8192) return false;
-  return pair_fits_lds(n) || (n <= 256 && band_rows(n) >= 16);
+  return pair_fits_lds(n) || (n <= 256 && orbit_sort_fits(K, N));
 }
 
 static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
@@ -1513,31 +1677,6 @@ hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGe
   return e;
 }
 
-// the banded build over the sorted columns of `bp` (relative to jbase, see
-// build_band_kernel)
-template <int OUT>
-static hipError_t launch_band(const float* cube, int K, const ColGeom* geo, const BucketPlan& bp,
-                              int n, int64_t M, int64_t ncols, int64_t jbase, void* A_lo,
-                              void* A_hi, int64_t p0, double* tau, hipStream_t s) {
-  const int ls = band_stride(n), H = band_rows(n), np = n + 2;
-  const int nbands = (np - 1 + (H - 1) - 1) / (H - 1);
-  const size_t lds = (size_t)H * ls * sizeof(float2);
-  const bool full = (n % 64) == 0;
-  auto launch = [&](auto kern) -> hipError_t {
-    const void* fn = reinterpret_cast<const void*>(kern);
-    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(cube, K, geo, bp.order, bp.items, bp.nitems, bp.nb,
-                                                   n, ls, H, nbands, M, ncols, jbase, A_lo, A_hi, p0,
-                                                   tau);
-    return hipGetLastError();
-  };
-  switch (lds_e(n)) {  // n > 141 here
-    case 3: return full ? launch(build_band_kernel<3, true, OUT>) : launch(build_band_kernel<3, false, OUT>);
-    default: return full ? launch(build_band_kernel<4, true, OUT>) : launch(build_band_kernel<4, false, OUT>);
-  }
-}
-
 static bool build_orbit_supported(int n, int K, int N);
 static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
                                      int64_t M, float* A32, double* tau, void* scratch, hipStream_t s);
@@ -1545,12 +1684,10 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int N, int64_t M,
                             float* A32, double* tau, void* scratch, hipStream_t s) {
   if (build_orbit_supported(n, K, N)) return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, s);
+  if (!pair_fits_lds(n)) return hipErrorInvalidValue;  // larger pairs: the orbit builds only
   const int64_t ncols = (int64_t)N * N;
-  // banded pairs: the first half of the columns (and the centre of an odd
-  // grid), each written with its half turn; otherwise every column
-  const int64_t nsort = pair_fits_lds(n) ? ncols : (ncols + 1) / 2;
   BucketPlan bp;
-  hipError_t e = launch_bucket_sort(geo, nsort, K, scratch, &bp, s);
+  hipError_t e = launch_bucket_sort(geo, ncols, K, scratch, &bp, s);
   if (e != hipSuccess) return e;
   const int32_t* order = bp.order;
   const int4* items = bp.items;
@@ -1560,7 +1697,6 @@ hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n,
 
   const unsigned grid = (unsigned)items_max;
   const bool full = (n % 64) == 0;
-  if (!pair_fits_lds(n)) return launch_band<0>(cube, K, geo, bp, n, M, ncols, 0, A32, A32, 0, tau, s);
   const int ls = lds_stride(n);
   const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
   const void* fn;
@@ -1648,10 +1784,24 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, nullptr, nullptr, nullptr, s);
   if (e != hipSuccess) return e;
-  const int ls = lds_stride(n);
-  const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
   const bool vec = (n % 4) == 0;
   const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  if (!pair_fits_lds(n)) {  // a staged box per 32 x 32 tile
+    const size_t lds = (size_t)16 * kFpRegion * sizeof(float);
+    auto launch = [&](auto kern) -> hipError_t {
+      const void* fn = reinterpret_cast<const void*>(kern);
+      hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (err != hipSuccess) return err;
+      kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, N, M, pl.rpr,
+                                   pl.o.nreps, A32, pl.part);
+      return hipGetLastError();
+    };
+    e = vec ? launch(build_orbit_box_kernel<true>) : launch(build_orbit_box_kernel<false>);
+    if (e != hipSuccess) return e;
+    return orbit_finish(pl, tau, s);
+  }
+  const int ls = lds_stride(n);
+  const size_t lds = (size_t)(n + 2) * ls * sizeof(float2);
   auto launch = [&](auto kern) -> hipError_t {
     const void* fn = reinterpret_cast<const void*>(kern);
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1671,12 +1821,20 @@ static size_t orbit16_pair_bytes(int n) {
 }
 static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)2 * (2 * 8 * 33 * 16); }
 
+// LDS of the 16-bit box kernel: 16 box regions, then the two unit tiles
+static size_t orbit16_box_lds_bytes() { return (size_t)16 * kFpRegion * sizeof(float) + (size_t)2 * (2 * 8 * 33 * 16); }
+
+// the pair in LDS with the unit tiles, or (up to 256 x 256) staged boxes
 bool build_orbit16_supported(int n, int K, int N) {
-  return N % 8 == 0 && pair_fits_lds(n) && orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes &&
-         orbit_sort_fits(K, N);
+  if (N % 8 != 0 || !orbit_sort_fits(K, N)) return false;
+  if (pair_fits_lds(n)) return orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes;
+  return n <= 256 && orbit16_box_lds_bytes() <= (size_t)kLdsBuildMaxBytes;
 }
 
-static bool build_orbit_supported(int n, int K, int N) { return pair_fits_lds(n) && orbit_sort_fits(K, N); }
+// float32: the pair in LDS, or (up to 256 x 256) a staged box per tile
+static bool build_orbit_supported(int n, int K, int N) {
+  return (pair_fits_lds(n) || n <= 256) && orbit_sort_fits(K, N);
+}
 
 size_t build_lds_scratch_bytes(int K, int N, int n) {
   return build_orbit_supported(n, K, N) ? build_orbit_scratch_bytes(K, N, n)
@@ -1689,10 +1847,25 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, perm, slot_of, eslot, s);
   if (e != hipSuccess) return e;
-  const int ls = lds_stride(n);
-  const size_t lds = orbit16_lds_bytes(n);
   uint16_t* Mh = reinterpret_cast<uint16_t*>(lib);
   const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  if (!pair_fits_lds(n)) {  // a staged box per 32 x 32 pixels
+    const size_t lds = orbit16_box_lds_bytes();
+    auto launch = [&](auto kern) -> hipError_t {
+      const void* fn = reinterpret_cast<const void*>(kern);
+      hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (err != hipSuccess) return err;
+      kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, pl.rpr,
+                                   pl.o.nreps, Mh, pl.part);
+      return hipGetLastError();
+    };
+    e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true>)
+                                    : launch(build_orbit16_box_kernel<false>);
+    if (e != hipSuccess) return e;
+    return orbit_finish(pl, tau, s);
+  }
+  const int ls = lds_stride(n);
+  const size_t lds = orbit16_lds_bytes(n);
   auto launch = [&](auto kern) -> hipError_t {
     const void* fn = reinterpret_cast<const void*>(kern);
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1707,116 +1880,4 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
 }
 
 
-// Interleave 16-bit column-major staging into the 8-slot groups:
-// M16[g][i][u] = S[8g+u][i] (column j of the staging at S + (j - col0) M),
-// zeros past ncols.  A thread takes 8 rows, one 16-byte load per column
-// (VEC, M % 2048 == 0: 1 KiB per wave and column), transposes the 8 x 8 values
-// in registers and, through LDS, the workgroup writes its 2048 rows 1 KiB per
-// store instruction.
-template <bool VEC>
-__global__ __launch_bounds__(256) void pack16_staged_kernel(const uint16_t* __restrict__ S,
-                                                            int64_t M, int64_t ncols,
-                                                            u32x4* __restrict__ Mp, int64_t g0,
-                                                            int64_t col0) {
-  const int64_t grp = g0 + blockIdx.y;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
-  if (!VEC && i0 >= M) return;  // VEC: every row of the workgroup is in the image
-  uint32_t w[8][4];  // column u, rows 2k, 2k+1 in word k
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int64_t j = grp * 8 + u;
-    if constexpr (VEC) {
-      u32x4 t = {0u, 0u, 0u, 0u};
-      if (j < ncols) t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(S + (j - col0) * M + i0));
-      w[u][0] = t.x; w[u][1] = t.y; w[u][2] = t.z; w[u][3] = t.w;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t lo = 0u, hi = 0u;
-        if (j < ncols) {
-          if (i0 + 2 * k < M) lo = S[(j - col0) * M + i0 + 2 * k];
-          if (i0 + 2 * k + 1 < M) hi = S[(j - col0) * M + i0 + 2 * k + 1];
-        }
-        w[u][k] = lo | (hi << 16);
-      }
-    }
-  }
-  u32x4 pk[8];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int k = r >> 1, sh = 16 * (r & 1);
-    pk[r].x = ((w[0][k] >> sh) & 0xFFFFu) | (((w[1][k] >> sh) & 0xFFFFu) << 16);
-    pk[r].y = ((w[2][k] >> sh) & 0xFFFFu) | (((w[3][k] >> sh) & 0xFFFFu) << 16);
-    pk[r].z = ((w[4][k] >> sh) & 0xFFFFu) | (((w[5][k] >> sh) & 0xFFFFu) << 16);
-    pk[r].w = ((w[6][k] >> sh) & 0xFFFFu) | (((w[7][k] >> sh) & 0xFFFFu) << 16);
-  }
-  if constexpr (VEC) {
-    // through LDS, so each store instruction writes 1 KiB of consecutive rows
-    // (the workgroup's 2048 rows are whole: M % 2048 == 0)
-    __shared__ u32x4 rows[2048];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) rows[8 * threadIdx.x + r] = pk[r];
-    __syncthreads();
-    u32x4* dst = Mp + grp * M + (int64_t)blockIdx.x * 2048;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) dst[threadIdx.x + 256 * r] = rows[threadIdx.x + 256 * r];
-  } else {
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      if (i0 + r < M) Mp[grp * M + i0 + r] = pk[r];
-  }
-}
-
-static hipError_t launch_pack16_staged(const uint16_t* S, int64_t col0, int64_t g0, int64_t g1,
-                                       int64_t M, int64_t ncols, void* lib, hipStream_t s) {
-  if (g1 <= g0) return hipSuccess;
-  const dim3 pgrid((unsigned)((M + 2047) / 2048), (unsigned)(g1 - g0));
-  u32x4* Mp = reinterpret_cast<u32x4*>(lib);
-  if (M % 2048 == 0 && (reinterpret_cast<uintptr_t>(S) & 15) == 0)
-    pack16_staged_kernel<true><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
-  else
-    pack16_staged_kernel<false><<<pgrid, 256, 0, s>>>(S, M, ncols, Mp, g0, col0);
-  return hipGetLastError();
-}
-
-// 16-bit libraries of banded PSF pairs, a chunk of columns at a time: chunk
-// [c0, c1) of the first half of the scene grid and its half turns
-// [N^2-c1, N^2-c0) are built, already rounded to the format, into a 16-bit
-// column-major staging buffer (2 CH columns) and interleaved into the groups
-// before the next chunk, so the staging needs 2 CH n^2 2-byte values instead
-// of a float32 copy of the library.  N % 16 == 0 (whole 8-column groups on
-// both sides, no centre column).
-static int64_t band16_chunk(int N) {
-  const int64_t nhalf = (int64_t)N * N / 2;
-  return nhalf < kBand16ChunkCols ? nhalf : kBand16ChunkCols;
-}
-
-bool build_band16_chunked_supported(int n, int K, int N) {
-  return !pair_fits_lds(n) && build_lds_supported(n, K) && N % 16 == 0;
-}
-
-size_t band16_stage_bytes(int N, int64_t M) { return (size_t)2 * band16_chunk(N) * (size_t)M * 2; }
-
-hipError_t launch_build_band16_chunked(int storage, const float* cube, int K, const ColGeom* geo,
-                                       int n, int N, int64_t M, void* lib, double* tau,
-                                       void* scratch, void* stage, hipStream_t s) {
-  const int64_t ncols = (int64_t)N * N, nhalf = ncols / 2, CH = band16_chunk(N);
-  uint16_t* A_lo = reinterpret_cast<uint16_t*>(stage);
-  uint16_t* A_hi = A_lo + CH * M;
-  const bool bf = storage == PSFLIB_BF16_POW2;
-  for (int64_t c0 = 0; c0 < nhalf; c0 += CH) {
-    const int64_t c1 = (c0 + CH < nhalf) ? c0 + CH : nhalf;
-    BucketPlan bp;
-    hipError_t e = launch_bucket_sort(geo + c0, c1 - c0, K, scratch, &bp, s);
-    if (e != hipSuccess) return e;
-    e = bf ? launch_band<1>(cube, K, geo, bp, n, M, ncols, c0, A_lo, A_hi, ncols - c1, tau, s)
-           : launch_band<2>(cube, K, geo, bp, n, M, ncols, c0, A_lo, A_hi, ncols - c1, tau, s);
-    if (e != hipSuccess) return e;
-    e = launch_pack16_staged(A_lo, c0, c0 / 8, c1 / 8, M, ncols, lib, s);
-    if (e != hipSuccess) return e;
-    e = launch_pack16_staged(A_hi, ncols - c1, (ncols - c1) / 8, (ncols - c0) / 8, M, ncols, lib, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
 }  // namespace psflib

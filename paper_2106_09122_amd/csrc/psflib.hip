@@ -321,25 +321,24 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // Cubic-spline rotation: spline coefficients of the cube, then a build over
   // coefficient pairs staged in LDS (in row bands when large), or a gather
   // past 256 x 256.  Bilinear: the bucketed LDS build, the pair staged whole
-  // when it fits the LDS and in row bands up to 256 x 256; larger PSFs gather
-  // from a pair-interleaved copy of the cube.  The LDS build writes float32 columns,
-  // and so does every build when the flux-preserving rescale follows; the
-  // 16-bit forms then pack those columns in a last pass.
+  // when it fits the LDS, else (up to 256 x 256) a box of it per tile, read
+  // by the rotation-orbit builds; larger PSFs gather from a pair-interleaved
+  // copy of the cube.  The builds write float32 columns when the
+  // flux-preserving rescale follows, or when a 16-bit library cannot be
+  // written directly; the 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
   const bool lds = cubic ? psflib::build_cubic_lds_supported(desc->n)
-                         : psflib::build_lds_supported(desc->n, K);
-  // 16-bit libraries of bilinear, unrescaled columns whose pair fits the LDS
-  // are written directly in bracket order; the other 16-bit builds go through
-  // float32 columns and a packing pass (natural order)
-  const bool direct16 = storage != PSFLIB_FP32 && !cubic && !flux && lds &&
-                        psflib::build_lds16_supported(desc->n, K, L.ncols);
-  const bool orbit16 = direct16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
+                         : psflib::build_lds_supported(desc->n, K, desc->N);
+  // 16-bit libraries of bilinear, unrescaled columns are written directly in
+  // bracket order: by quarter-turn orbits when N is a multiple of 8 (up to
+  // 256 x 256 PSFs), else column by column when the pair fits the LDS; the
+  // other 16-bit builds go through float32 columns and a packing pass
+  // (natural order)
+  const bool plain16 = storage != PSFLIB_FP32 && !cubic && !flux && lds;
+  const bool orbit16 = plain16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
+  const bool direct16 = orbit16 || (plain16 && psflib::build_lds16_supported(desc->n, K, L.ncols));
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
-  // banded 16-bit builds without the rescale stage through float32 a chunk of
-  // columns at a time (each chunk packed before the next)
-  const bool band16 = stage32 && !cubic && !flux &&
-                      psflib::build_band16_chunked_supported(desc->n, K, desc->N);
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
       spline_bytes + align256(orbit16    ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
@@ -348,9 +347,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               : lds    ? psflib::build_lds_scratch_bytes(K, desc->N, desc->n)
                               : cubic  ? 0
                                        : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
-  const size_t stage_bytes = align256(band16    ? psflib::band16_stage_bytes(desc->N, L.M)
-                                      : stage32 ? (size_t)L.ncols * (size_t)L.M * 4
-                                                : 0);
+  const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
   const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
   void* tmp = nullptr;
@@ -411,10 +408,6 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                    reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
                                    path_tmp, s);
     if (e != hipSuccess) return bail(e, "16-bit LDS build kernels");
-  } else if (band16) {
-    e = psflib::launch_build_band16_chunked(storage, d_cube, K, h->geo, desc->n, desc->N, L.M, d_lib,
-                                            tau, path_tmp, A32, s);
-    if (e != hipSuccess) return bail(e, "16-bit banded build kernels");
   } else if (lds) {
     e = psflib::launch_build_lds(d_cube, K, h->geo, desc->n, desc->N, L.M,
                                  reinterpret_cast<float*>(bdst), tau, path_tmp, s);
@@ -433,7 +426,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                     L.ncols, tau, exps, storage != PSFLIB_FP32, s);
     if (e != hipSuccess) return bail(e, "flux rescale kernel");
   }
-  if (stage32 && !band16) {
+  if (stage32) {
     e = psflib::launch_pack16(storage, A32, h->geo, L.M, L.ncols, L.ncols_pad, d_lib, s);
     if (e != hipSuccess) return bail(e, "16-bit packing kernel");
   }

@@ -45,7 +45,6 @@ constexpr int32_t kZeroColumnExp = PSFLIB_ZERO_COLUMN_EXPONENT;  // exponent of 
 constexpr int kLdsCols = 16;         // LDS build: columns per work item (one wave each)
 constexpr int kLdsBuildMaxBytes = 163840;  // LDS build: bordered PSF pair must fit the CU's LDS
 constexpr int kSplinePad = 12;       // cubic rotation: zero pixels padded on each side before the spline filter
-constexpr int64_t kBand16ChunkCols = 16384;  // banded 16-bit builds: base columns per staging chunk
 constexpr int kLdsMaxBuckets = 8193; // LDS builds: radial brackets + the zero-column bucket, at most
 
 struct Layout {
@@ -157,7 +156,7 @@ hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo,
                                   hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
-bool build_lds_supported(int n, int K);
+bool build_lds_supported(int n, int K, int N);
 // scratch of launch_build_lds for an N x N scene
 size_t build_lds_scratch_bytes(int K, int N, int n);
 // Columns grouped by radial bracket on the device: order[] lists the columns
@@ -175,10 +174,12 @@ size_t bucket_scratch_bytes(int K, int64_t ncols);
 hipError_t launch_bucket_sort(const ColGeom* geo, int64_t ncols, int K, void* scratch,
                               BucketPlan* plan, hipStream_t s);
 // float32 columns (A32[j*M + i]) and their float64 sums: the rotation-orbit
-// build when the pair fits the LDS, else the banded build
+// build (the pair in LDS, or a staged box of it per tile), else columns in
+// bracket order with the pair in LDS
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int N, int64_t M,
                             float* A32, double* tau, void* scratch, hipStream_t s);
-// 16-bit storage built by rotation orbits (N % 8 == 0, pair and tile in LDS):
+// 16-bit storage built by rotation orbits (N % 8 == 0; the pair, or a box of
+// it per tile, and the unit tiles in LDS):
 // slot 32 (s/8) + 8 k + s%8 holds member k of the s-th base column in
 // bracket order (perm, slot_of, eslot written here); column sums in tau.
 bool build_orbit16_supported(int n, int K, int N);
@@ -203,14 +204,6 @@ hipError_t launch_pack16(int storage, const float* A32, const ColGeom* geo, int6
 hipError_t launch_pack16_range(int storage, const float* A32, int64_t col0, int64_t g0, int64_t g1,
                                const ColGeom* geo, int64_t M, int64_t ncols, void* lib,
                                hipStream_t s);
-// 16-bit storage of a banded build (pairs beyond the LDS; N % 16 == 0): a chunk
-// of columns at a time, rounded to the format in the build and staged as 2-byte
-// columns (band16_stage_bytes of staging), then interleaved into the groups
-bool build_band16_chunked_supported(int n, int K, int N);
-size_t band16_stage_bytes(int N, int64_t M);
-hipError_t launch_build_band16_chunked(int storage, const float* cube, int K, const ColGeom* geo,
-                                       int n, int N, int64_t M, void* lib, double* tau,
-                                       void* scratch, void* stage, hipStream_t s);
 // Flux-preserving rescale of float32 columns: sums[k] = sum(P_k) (float64),
 // column j scaled by t_j / tau_j, tau_j recomputed; with want_exp the 16-bit
 // exponents (geo[j].e and exps[j]) follow the rescaled bound.

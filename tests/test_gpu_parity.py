@@ -168,13 +168,15 @@ SHAPES = [
     # tiles, zero columns past the last offset, odd PSF sides, nearest samples
     (20, 16, 0.6, 5, "linear", "linear", "zero"),
     (33, 24, 0.3, 4, "nonuniform", "nearest", "zero"),
-    # bordered PSF pairs larger than the LDS: staged in row bands (2, 3 and 4
-    # bands; 199 also takes the scalar staging loads and partial lanes)
+    # bordered PSF pairs larger than the LDS: the orbit builds stage a box of
+    # the pair per 32 x 32 tile (odd sides: partial tiles and scalar stores;
+    # odd N: the centre orbit; N = 16: the 16-bit box kernel)
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),
     (150, 33, 0.3, 6, "linear", "linear", "zero"),   # 1089 position angles
-    (150, 16, 0.4, 4, "linear", "linear", "zero"),   # 16-bit: 2-byte staging, scalar interleave
-    (192, 16, 0.35, 4, "nonuniform", "linear", "zero"),  # 16-bit: 2-byte staging, 1 KiB interleave stores
-    (151, 16, 0.45, 3, "linear", "nearest", "clamp"),  # 16-bit: odd image size in the 2-byte staging
+    (150, 16, 0.4, 4, "linear", "linear", "zero"),
+    (192, 16, 0.35, 4, "nonuniform", "linear", "zero"),
+    (151, 16, 0.45, 3, "linear", "nearest", "clamp"),  # odd PSF side in the 16-bit box kernel
+    (142, 24, 0.5, 5, "linear", "linear", "zero"),  # smallest pair beyond the LDS; 8-base blocks across brackets
     (199, 4, 0.5, 3, "nonuniform", "linear", "zero"),
     (256, 3, 0.9, 3, "linear", "linear", "clamp"),
     # PSFs larger than 256 x 256 take the gather path
@@ -215,7 +217,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + [SHAPES[13], SHAPES[14], SHAPES[15], SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + [SHAPES[13], SHAPES[14], SHAPES[15], SHAPES[16], SHAPES[-3], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
