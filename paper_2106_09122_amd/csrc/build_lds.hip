@@ -22,7 +22,7 @@
 //    all four (float32: 16-byte runs straight from registers; 16-bit: rounded
 //    into an LDS tile of 8-slot units, slots ordered so that a group holds one
 //    quarter turn of 8 base columns).  The pair is staged whole when it fits
-//    the LDS; larger pairs (up to 256 x 256) are read through a small box per
+//    the LDS; larger pairs (up to 8192 x 8192) are read through a small box per
 //    32 x 32 pixel tile, staged by each wave in its own LDS region;
 //  * columns in bracket order (16-bit forms whose scene size is not a multiple
 //    of 8, pairs that fit the LDS): one wave per column, 16 columns per
@@ -961,7 +961,7 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
-// Float32 orbit build for pairs larger than the LDS (141 < n <= 256).  The
+// Float32 orbit build for pairs larger than the LDS (n > 141).  The
 // rotation map is affine, so a 32 x 32 tile of the base column draws its taps
 // from a small box of the bordered pair: every float64 step of the source
 // coordinates (the products with the cosine and sine, the two sums) is
@@ -978,6 +978,7 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
 // barrier (a wave orders its own LDS writes and reads).
 constexpr int kFpSpan = 46;                     // box rows or columns, at most
 constexpr int kFpRegion = kFpSpan * (kFpSpan + 1);  // floats per wave (odd row stride)
+constexpr int kBoxMaxN = 8192;  // PSF side: pixel offsets n^2 and row-range sizes stay in int
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1324,7 +1325,7 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
-// 16-bit orbit build for pairs larger than the LDS (141 < n <= 256, N a
+// 16-bit orbit build for pairs larger than the LDS (n > 141, N a
 // multiple of 8): build_orbit16_kernel's unit tiles and copies, with each
 // wave's taps read from a staged box (as build_orbit_box_kernel) of the 32 x 32
 // pixels it forms as four 8 x 32 tiles.  LDS: 16 box regions, then the two
@@ -1530,11 +1531,11 @@ static bool pair_fits_lds(int n) {
 static bool orbit_sort_fits(int K, int N);
 
 bool build_lds_supported(int n, int K, int N) {
-  // the bordered pair fits the LDS whole, or (up to 256 x 256) the orbit
+  // the bordered pair fits the LDS whole, or (up to kBoxMaxN) the orbit
   // builds stage a box of it per tile; the bucket histograms (8 B per bucket)
   // must fit the sort kernels' LDS
   if (K > 8192) return false;
-  return pair_fits_lds(n) || (n <= 256 && orbit_sort_fits(K, N));
+  return pair_fits_lds(n) || (n <= kBoxMaxN && orbit_sort_fits(K, N));
 }
 
 static int nbuckets(int K) { return ((K > 1) ? K - 1 : 1) + 1; }
@@ -1824,16 +1825,16 @@ static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)
 // LDS of the 16-bit box kernel: 16 box regions, then the two unit tiles
 static size_t orbit16_box_lds_bytes() { return (size_t)16 * kFpRegion * sizeof(float) + (size_t)2 * (2 * 8 * 33 * 16); }
 
-// the pair in LDS with the unit tiles, or (up to 256 x 256) staged boxes
+// the pair in LDS with the unit tiles, or (up to kBoxMaxN) staged boxes
 bool build_orbit16_supported(int n, int K, int N) {
   if (N % 8 != 0 || !orbit_sort_fits(K, N)) return false;
   if (pair_fits_lds(n)) return orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes;
-  return n <= 256 && orbit16_box_lds_bytes() <= (size_t)kLdsBuildMaxBytes;
+  return n <= kBoxMaxN && orbit16_box_lds_bytes() <= (size_t)kLdsBuildMaxBytes;
 }
 
-// float32: the pair in LDS, or (up to 256 x 256) a staged box per tile
+// float32: the pair in LDS, or (up to kBoxMaxN) a staged box per tile
 static bool build_orbit_supported(int n, int K, int N) {
-  return (pair_fits_lds(n) || n <= 256) && orbit_sort_fits(K, N);
+  return (pair_fits_lds(n) || n <= kBoxMaxN) && orbit_sort_fits(K, N);
 }
 
 size_t build_lds_scratch_bytes(int K, int N, int n) {

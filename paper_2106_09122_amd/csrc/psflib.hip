@@ -321,20 +321,23 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // Cubic-spline rotation: spline coefficients of the cube, then a build over
   // coefficient pairs staged in LDS (in row bands when large), or a gather
   // past 256 x 256.  Bilinear: the bucketed LDS build, the pair staged whole
-  // when it fits the LDS, else (up to 256 x 256) a box of it per tile, read
-  // by the rotation-orbit builds; larger PSFs gather from a pair-interleaved
-  // copy of the cube.  The builds write float32 columns when the
-  // flux-preserving rescale follows, or when a 16-bit library cannot be
-  // written directly; the 16-bit forms then pack those columns in a last pass.
+  // when it fits the LDS, else a box of it per tile, read by the
+  // rotation-orbit builds; the gather from a pair-interleaved copy of the cube
+  // serves what those cannot (bracket or column counts beyond the sort's
+  // bounds), and the 16-bit libraries of PSFs larger than 256 x 256 that would
+  // need a float32 copy (N not a multiple of 8, no rescale), which it writes
+  // directly.  The builds write float32 columns when the flux-preserving
+  // rescale follows, or when a 16-bit library cannot be written directly; the
+  // 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
+  const bool big16 = !cubic && desc->n > 256 && storage != PSFLIB_FP32 && !flux && desc->N % 8 != 0;
   const bool lds = cubic ? psflib::build_cubic_lds_supported(desc->n)
-                         : psflib::build_lds_supported(desc->n, K, desc->N);
+                         : !big16 && psflib::build_lds_supported(desc->n, K, desc->N);
   // 16-bit libraries of bilinear, unrescaled columns are written directly in
-  // bracket order: by quarter-turn orbits when N is a multiple of 8 (up to
-  // 256 x 256 PSFs), else column by column when the pair fits the LDS; the
-  // other 16-bit builds go through float32 columns and a packing pass
-  // (natural order)
+  // bracket order: by quarter-turn orbits when N is a multiple of 8, else
+  // column by column when the pair fits the LDS; the other 16-bit builds go
+  // through float32 columns and a packing pass (natural order)
   const bool plain16 = storage != PSFLIB_FP32 && !cubic && !flux && lds;
   const bool orbit16 = plain16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
   const bool direct16 = orbit16 || (plain16 && psflib::build_lds16_supported(desc->n, K, L.ncols));
