@@ -97,10 +97,11 @@ __device__ __forceinline__ float2 tap_pair(const float2* __restrict__ P, int Np,
 
 // Cubic-spline rotation: the same source point as the bilinear form, in the
 // coordinates of the spline coefficients (padded by kSplinePad), sampled with
-// the 4 x 4 B-spline weights, taps outside the padded array zero.  The taps
-// are summed separably — each row's weighted sum of the k and k+1
-// coefficients, those rows weighted, then the radial blend — in the order the
-// LDS-staged cubic build uses, so both forms give identical values.
+// the 4 x 4 B-spline weights, taps outside the padded array zero.  Each tap
+// is the radial blend (1-w) C_k + w C_{k+1} of its coefficient pair; the taps
+// are summed separably (each row's weighted sum, then those rows weighted) in
+// the order the LDS-staged cubic orbit build uses, so both forms give
+// identical values.
 __device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int Np, double c,
                                                     double ux, double uy) {
 #pragma clang fp contract(off)
@@ -114,23 +115,23 @@ __device__ __forceinline__ float column_value_cubic(const ColumnParams& cp, int 
   float wy[4], wx[4];
   cubic_weights(rowf - r0f, wy);
   cubic_weights(colf - c0f, wx);
-  float X = 0.0f, Y = 0.0f;
+  float V = 0.0f;
 #pragma unroll
   for (int dr = 0; dr < 4; ++dr) {
     const int r = r0 + dr - 1;
-    const float2 p0 = tap_pair(cp.src, Np, r, c0 - 1), p1 = tap_pair(cp.src, Np, r, c0);
-    const float2 p2 = tap_pair(cp.src, Np, r, c0 + 1), p3 = tap_pair(cp.src, Np, r, c0 + 2);
-    float x = wx[0] * p0.x, y = wx[0] * p0.y;
-    x = fmaf(wx[1], p1.x, x);
-    y = fmaf(wx[1], p1.y, y);
-    x = fmaf(wx[2], p2.x, x);
-    y = fmaf(wx[2], p2.y, y);
-    x = fmaf(wx[3], p3.x, x);
-    y = fmaf(wx[3], p3.y, y);
-    X = fmaf(wy[dr], x, X);
-    Y = fmaf(wy[dr], y, Y);
+    float q[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float2 p = tap_pair(cp.src, Np, r, c0 - 1 + e);
+      q[e] = fmaf(cp.wk1, p.y, cp.wk0 * p.x);
+    }
+    float v = wx[0] * q[0];
+    v = fmaf(wx[1], q[1], v);
+    v = fmaf(wx[2], q[2], v);
+    v = fmaf(wx[3], q[3], v);
+    V = fmaf(wy[dr], v, V);
   }
-  return fmaf(cp.wk1, Y, cp.wk0 * X);
+  return V;
 }
 
 template <int STORE, bool CUBIC>

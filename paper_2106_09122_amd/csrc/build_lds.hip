@@ -1511,6 +1511,222 @@ __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
+// Cubic-spline orbit build: the quarter-turn orbits of the bilinear builds
+// (the four members of an orbit sample the spline at the same source points,
+// so one base column is computed and four are written), each 32 x 32 pixel
+// tile reading its 4 x 4 B-spline taps from a box of the padded coefficient
+// pair that the wave stages in its own LDS region.  A pixel's tap origin is
+// clamped to padded indices [-3, Np+1] (where that moves it, all its taps lay
+// outside the padded array and read zeros, as before the clamp); the clamp and
+// the floors are monotone, so the tile's extreme origins are those of its
+// corners and the box spans at most 44 + 4 = 48 rows and columns.  The box
+// holds the radial blend (1-w) C_k + w C_{k+1} (zero outside the array), and a
+// pixel is the 4 x 4 weighted sum of the blend, row by row, in the order of
+// the gather form, so both give identical values.
+constexpr int kCbSpan = 48;                        // box rows or columns, at most
+constexpr int kCbRegion = kCbSpan * (kCbSpan + 1);  // floats per wave (odd row stride)
+
+__device__ __forceinline__ int clamp_origin(int v, int Np) { return v < -3 ? -3 : (v > Np + 1 ? Np + 1 : v); }
+
+// clamped tap origin (padded row and column) of image pixel (a, b)
+__device__ __forceinline__ void cubic_origin(const ColGeom& g, double c, int a, int b, int Np,
+                                             int& r0, int& c0) {
+#pragma clang fp contract(off)
+  const double ux = (double)b - c, uy = (double)a - c;
+  const double pad = (double)kSplinePad;
+  const double rowf = c + ((-g.st) * ux + g.ct * uy) + pad;
+  const double colf = c + (g.ct * ux + g.st * uy) + pad;
+  r0 = clamp_origin((int)floor(rowf), Np);
+  c0 = clamp_origin((int)floor(colf), Np);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* __restrict__ pairs,
+                                                                 int Np,
+                                                                 const ColGeom* __restrict__ geo,
+                                                                 const int32_t* __restrict__ reps,
+                                                                 const int4* __restrict__ items,
+                                                                 const int32_t* __restrict__ nitems,
+                                                                 int nb, int n, int N, int64_t M,
+                                                                 int rpr, int64_t nreps,
+                                                                 float* __restrict__ A,
+                                                                 double* __restrict__ part) {
+  extern __shared__ float QS[];  // 16 regions of kCbRegion floats
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  const int sp = w0 + wave;
+  if (sp < first || sp >= first + len) return;  // uniform per wave; no workgroup barrier
+  const int64_t j0 = reps[sp];
+  const bool centre = orbit_is_centre(j0, N);
+  float* C0 = A + j0 * M;
+  float* C1 = A + orbit_member(j0, N, 1) * M;
+  float* C2 = A + orbit_member(j0, N, 2) * M;
+  float* C3 = A + orbit_member(j0, N, 3) * M;
+  if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
+    for (int x = lane; x < (rb - ra) * n; x += 64) {
+      const int64_t p = (int64_t)ra * n + x;
+      __builtin_nontemporal_store(0.0f, C0 + p);
+      if (!centre) {
+        __builtin_nontemporal_store(0.0f, C1 + p);
+        __builtin_nontemporal_store(0.0f, C2 + p);
+        __builtin_nontemporal_store(0.0f, C3 + p);
+      }
+    }
+    if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = 0.0;
+    return;
+  }
+  float* Q = QS + wave * kCbRegion;
+  const float2* src = pairs + (int64_t)bkt * Np * Np;
+  const ColGeom g = geo[j0];
+  const double c = (double)(n - 1) * 0.5;
+  const double pad = (double)kSplinePad;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const int li = lane >> 3, lk = lane & 7;
+  double tsum = 0.0;
+  for (int a0 = ra; a0 < rb; a0 += 32) {
+    const int ae = (a0 + 32 < rb) ? a0 + 32 : rb;
+    const int ab = a0 + 4 * li;
+    for (int b0 = 0; b0 < n; b0 += 32) {
+      const int be = (b0 + 32 < n) ? b0 + 32 : n;
+      // the tile's box of padded rows [Rlo, Rlo + bh) and columns [Clo, Clo + bw)
+      int rmin, rmax, cmin, cmax;
+      {
+        int r0, c0;
+        cubic_origin(g, c, a0, b0, Np, r0, c0);
+        rmin = rmax = r0;
+        cmin = cmax = c0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          cubic_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, Np, r0, c0);
+          rmin = min(rmin, r0);
+          rmax = max(rmax, r0);
+          cmin = min(cmin, c0);
+          cmax = max(cmax, c0);
+        }
+      }
+      const int Rlo = rmin - 1, Clo = cmin - 1;
+      const int bh = min(rmax - rmin + 4, kCbSpan), bw = min(cmax - cmin + 4, kCbSpan);
+      const int bs = bw | 1;
+      wave_lds_sync();  // the previous tile's reads are done
+      {
+        const int q64 = 64 / bw, r64 = 64 - q64 * bw;
+        int rr = lane / bw, cc = lane - rr * bw;
+        while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
+          float2 pv[8];
+          int dst[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int R = Rlo + rr, C = Clo + cc;
+            const bool in = rr < bh;
+            const bool inner = in && (unsigned)R < (unsigned)Np && (unsigned)C < (unsigned)Np;
+            pv[k] = inner ? src[R * Np + C] : make_float2(0.0f, 0.0f);
+            dst[k] = in ? rr * bs + cc : -1;
+            cc += r64;
+            rr += q64;
+            if (cc >= bw) {
+              cc -= bw;
+              ++rr;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, pv[k].y, wk0 * pv[k].x);
+        }
+      }
+      wave_lds_sync();  // the box is staged
+      const int bb = b0 + 4 * lk;
+      if (ab >= ae || bb >= be) continue;  // VEC: the whole block is outside the tile
+      double ctux[4], mstux[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma clang fp contract(off)
+        const double ux = (double)(bb + q) - c;
+        ctux[q] = g.ct * ux;
+        mstux[q] = (-g.st) * ux;
+      }
+      float x[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = ab + r;
+        double stuy, ctuy;
+        {
+#pragma clang fp contract(off)
+          const double uy = (double)a - c;
+          stuy = g.st * uy;
+          ctuy = g.ct * uy;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[r][q] = 0.0f;
+          if (VEC || (a < ae && bb + q < be)) {
+#pragma clang fp contract(off)
+            const double rowf = c + (mstux[q] + ctuy) + pad;
+            const double colf = c + (ctux[q] + stuy) + pad;
+            const double r0f = floor(rowf), c0f = floor(colf);
+            const int r0 = clamp_origin((int)r0f, Np), c0 = clamp_origin((int)c0f, Np);
+            float wy[4], wx[4];
+            cubic_weights(rowf - r0f, wy);
+            cubic_weights(colf - c0f, wx);
+            const float* t = Q + (r0 - 1 - Rlo) * bs + (c0 - 1 - Clo);
+            float V = 0.0f;
+#pragma unroll
+            for (int dr = 0; dr < 4; ++dr) {
+              const float* tr = t + dr * bs;
+              float v = wx[0] * tr[0];
+              v = fmaf(wx[1], tr[1], v);
+              v = fmaf(wx[2], tr[2], v);
+              v = fmaf(wx[3], tr[3], v);
+              V = fmaf(wy[dr], v, V);
+            }
+            x[r][q] = V;
+            tsum += (double)V;
+          }
+        }
+        if constexpr (VEC) {  // the row's runs of C0 and C2
+          __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
+                                      reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
+          if (!centre)
+            __builtin_nontemporal_store((f32x4){x[r][3], x[r][2], x[r][1], x[r][0]},
+                                        reinterpret_cast<f32x4*>(C2 + (int64_t)(n - 1 - a) * n + (n - 4 - bb)));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (VEC) {
+        if (!centre) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = bb + q;
+            __builtin_nontemporal_store((f32x4){x[3][q], x[2][q], x[1][q], x[0][q]},
+                                        reinterpret_cast<f32x4*>(C1 + (int64_t)b * n + (n - 4 - ab)));
+            __builtin_nontemporal_store((f32x4){x[0][q], x[1][q], x[2][q], x[3][q]},
+                                        reinterpret_cast<f32x4*>(C3 + (int64_t)(n - 1 - b) * n + ab));
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int a = ab + r, b = bb + q;
+            if (a >= ae || b >= be) continue;
+            __builtin_nontemporal_store(x[r][q], C0 + (int64_t)a * n + b);
+            if (centre) continue;
+            __builtin_nontemporal_store(x[r][q], C1 + (int64_t)b * n + (n - 1 - a));
+            __builtin_nontemporal_store(x[r][q], C2 + (int64_t)(n - 1 - a) * n + (n - 1 - b));
+            __builtin_nontemporal_store(x[r][q], C3 + (int64_t)(n - 1 - b) * n + a);
+          }
+      }
+    }
+  }
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
 // ------------------------------------------------------------- launch -----
 static int lds_e(int n) { return (n + 63) / 64; }
 
@@ -1812,6 +2028,35 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
     return hipGetLastError();
   };
   e = vec ? launch(build_orbit_kernel<true>) : launch(build_orbit_kernel<false>);
+  if (e != hipSuccess) return e;
+  return orbit_finish(pl, tau, s);
+}
+
+// cubic-spline orbit build from staged boxes of the padded coefficient pairs
+bool build_cubic_orbit_supported(int n, int K, int N) {
+  return K <= 8192 && n <= kBoxMaxN && orbit_sort_fits(K, N) &&
+         (size_t)16 * kCbRegion * sizeof(float) <= (size_t)kLdsBuildMaxBytes;
+}
+
+hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* geo, int n, int N,
+                                    int64_t M, float* A32, double* tau, void* scratch,
+                                    hipStream_t s) {
+  const OrbitPlan pl = orbit_plan(K, N, n, scratch);
+  hipError_t e = orbit_sort(geo, pl, nullptr, nullptr, nullptr, s);
+  if (e != hipSuccess) return e;
+  const int Np = n + 2 * kSplinePad;
+  const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  const size_t lds = (size_t)16 * kCbRegion * sizeof(float);
+  const float2* P = reinterpret_cast<const float2*>(pairs);
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<grid, 1024, lds, s>>>(P, Np, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, N, M, pl.rpr,
+                                 pl.o.nreps, A32, pl.part);
+    return hipGetLastError();
+  };
+  e = (n % 4) == 0 ? launch(build_cubic_orbit_kernel<true>) : launch(build_cubic_orbit_kernel<false>);
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
 }

@@ -318,22 +318,22 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   char* lib = reinterpret_cast<char*>(d_lib);
   double* tau = reinterpret_cast<double*>(lib + L.off_tau);
   int32_t* exps = (storage == PSFLIB_FP32) ? nullptr : reinterpret_cast<int32_t*>(lib + L.off_exp);
-  // Cubic-spline rotation: spline coefficients of the cube, then a build over
-  // coefficient pairs staged in LDS (in row bands when large), or a gather
-  // past 256 x 256.  Bilinear: the bucketed LDS build, the pair staged whole
-  // when it fits the LDS, else a box of it per tile, read by the
-  // rotation-orbit builds; the gather from a pair-interleaved copy of the cube
-  // serves what those cannot (bracket or column counts beyond the sort's
-  // bounds), and the 16-bit libraries of PSFs larger than 256 x 256 that would
-  // need a float32 copy (N not a multiple of 8, no rescale), which it writes
-  // directly.  The builds write float32 columns when the flux-preserving
-  // rescale follows, or when a 16-bit library cannot be written directly; the
-  // 16-bit forms then pack those columns in a last pass.
+  // Cubic-spline rotation: spline coefficients of the cube, then the
+  // quarter-turn orbit build with a box of the coefficient pair staged per
+  // tile.  Bilinear: the bucketed LDS build, the pair staged whole when it
+  // fits the LDS, else a box of it per tile, read by the rotation-orbit
+  // builds.  The gathers from pair-interleaved copies serve what those cannot
+  // (bracket or column counts beyond the sort's bounds), and the 16-bit
+  // libraries of PSFs larger than 256 x 256 that would need a float32 copy
+  // (bilinear: N not a multiple of 8; cubic: any N; no rescale), which they
+  // write directly.  The builds write float32 columns when the
+  // flux-preserving rescale follows, or when a 16-bit library cannot be
+  // written directly; the 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
-  const bool big16 = !cubic && desc->n > 256 && storage != PSFLIB_FP32 && !flux && desc->N % 8 != 0;
-  const bool lds = cubic ? psflib::build_cubic_lds_supported(desc->n)
-                         : !big16 && psflib::build_lds_supported(desc->n, K, desc->N);
+  const bool big16 = desc->n > 256 && storage != PSFLIB_FP32 && !flux && (cubic || desc->N % 8 != 0);
+  const bool lds = !big16 && (cubic ? psflib::build_cubic_orbit_supported(desc->n, K, desc->N)
+                                    : psflib::build_lds_supported(desc->n, K, desc->N));
   // 16-bit libraries of bilinear, unrescaled columns are written directly in
   // bracket order: by quarter-turn orbits when N is a multiple of 8, else
   // column by column when the pair fits the LDS; the other 16-bit builds go
@@ -346,7 +346,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   const size_t path_bytes =
       spline_bytes + align256(orbit16    ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
                               : direct16 ? psflib::build_lds16_scratch_bytes(K, L.ncols)
-                              : cubic && lds ? psflib::build_cubic_lds_scratch_bytes(K, L.ncols)
+                              : cubic && lds ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
                               : lds    ? psflib::build_lds_scratch_bytes(K, desc->N, desc->n)
                               : cubic  ? 0
                                        : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
@@ -389,10 +389,10 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
   if (cubic && lds) {
-    e = psflib::launch_build_cubic_lds(psflib::spline_pairs_of(path_tmp, K, desc->n), K, h->geo,
-                                       desc->n, L.M, L.ncols, reinterpret_cast<float*>(bdst), tau,
-                                       tp + spline_bytes, s);
-    if (e != hipSuccess) return bail(e, "cubic LDS build kernels");
+    e = psflib::launch_build_cubic_orbit(psflib::spline_pairs_of(path_tmp, K, desc->n), K, h->geo,
+                                         desc->n, desc->N, L.M, reinterpret_cast<float*>(bdst), tau,
+                                         tp + spline_bytes, s);
+    if (e != hipSuccess) return bail(e, "cubic orbit build kernels");
   } else if (cubic) {
     e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
                                    desc->n, L.M, L.ncols, L.ncols_pad, bdst, tau, s);

@@ -147,13 +147,13 @@ const float* spline_pairs_of(const void* scratch, int K, int n);
 hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                               int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
                               hipStream_t s);
-// Cubic build with the coefficient pair staged in LDS by row bands (float32
-// columns); false if the PSF is too large for bands of useful height.
-bool build_cubic_lds_supported(int n);
-size_t build_cubic_lds_scratch_bytes(int K, int64_t ncols);
-hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo, int n, int64_t M,
-                                  int64_t ncols, float* A32, double* tau, void* scratch,
-                                  hipStream_t s);
+// Cubic build by quarter-turn orbits, the taps read from a box of the padded
+// coefficient pair staged per tile in LDS (float32 columns); scratch of
+// build_orbit_scratch_bytes(K, N, n) bytes.
+bool build_cubic_orbit_supported(int n, int K, int N);
+hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* geo, int n, int N,
+                                    int64_t M, float* A32, double* tau, void* scratch,
+                                    hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K, int N);

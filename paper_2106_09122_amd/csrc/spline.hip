@@ -1,4 +1,5 @@
-// Cubic-spline rotation, part 1: spline coefficients of the sampled PSFs.
+// Cubic-spline rotation: spline coefficients of the sampled PSFs, which the
+// cubic orbit build (build_lds.hip) and the cubic gather (build.hip) sample.
 //
 // The rotation step of Sec. 2 uses SciPy's rotate(), whose default
 // interpolation is a cubic spline.  The spline that interpolates a PSF
@@ -182,175 +183,6 @@ __global__ __launch_bounds__(256) void spline_absmax_kernel(const double* __rest
   if (threadIdx.x == 0) cmax[blockIdx.x] = red[0];
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// The padded coefficient pair is staged in LDS with 4 more zero rows and
-// columns on every side (the extended array, Ne = Np + 8 per side, row
-// stride ls >= Ne).  A pixel's tap origin is clamped to padded indices
-// [-3, Np+1]: where that moves it, all 4 x 4 taps lay outside the padded
-// array and the clamped taps all read the zero margin, so the value is still
-// exactly zero; every tap is then a plain LDS read at a fixed offset from one
-// base address, with no bounds tests or weight masking.
-constexpr int kCubicMargin = 4;
-
-__host__ __device__ inline int cubic_ext(int Np) { return Np + 2 * kCubicMargin; }
-
-// row stride of the extended array: Ne rounded up to 5 mod 8 (spreads the
-// taps of a near-vertical line over the banks, as in the bilinear build)
-__host__ __device__ inline int cubic_stride(int Np) {
-  const int ne = cubic_ext(Np);
-  return ne + ((5 - ne % 8) + 8) % 8;
-}
-
-// Rows per LDS band of the extended array.
-__host__ __device__ inline int cubic_band_rows(int Np) {
-  const int h = (int)((size_t)kLdsBuildMaxBytes / ((size_t)cubic_stride(Np) * sizeof(float2)));
-  const int ne = cubic_ext(Np);
-  return h < ne ? h : ne;
-}
-
-// Cubic-spline build with the bracket's coefficient pair (C_k, C_{k+1}) staged
-// in LDS.  When the extended array exceeds the LDS it is staged in bands of H
-// rows that overlap by 3, band b holding extended rows [b (H-3), b (H-3) + H);
-// the 4 tap rows of a pixel, from its (clamped) origin row R - 1 on, all lie
-// in band min((R - 1) / (H-3), last), so each pixel is produced in exactly
-// one band.  A work item is up to kLdsCols columns of one bracket (columns of
-// the first half of the scene grid, and the centre of an odd grid, grouped on
-// the device), one wave per column, which writes every element also to the
-// half-turned column N^2-1-j at the mirrored pixel (n-1-a, n-1-b): that
-// column's tap coordinates there are the same float64 values, so its entry is
-// the same.  A wave walks its column in
-// tiles of 8 x 8 image pixels (lane l: row 8 a' + l / 8, column 8 b' + l % 8),
-// so the 64 stencils of one LDS read cover a compact rotated patch of the
-// array rather than a 64-pixel line: with the row stride at 5 mod 8 pairs
-// their 16-byte reads spread over the banks at any angle.  A store
-// instruction writes 8 runs of 32 bytes; plain stores let L2 merge the runs
-// of neighbouring tiles into whole lines (non-temporal ones were ~11% slower
-// end to end).  Coordinates and
-// B-spline weights in float64 (weights rounded once to float32); the 16 taps
-// are summed separably in float32 — each row's weighted sum of the k and k+1
-// coefficients, those rows weighted, then the radial blend — in the same
-// order as the gather form, so both give identical values.
-__global__ __launch_bounds__(1024) void build_cubic_lds_kernel(
-    const float2* __restrict__ pairs, int Np, int ls, int H, int nbands,
-    const ColGeom* __restrict__ geo, const int32_t* __restrict__ order,
-    const int4* __restrict__ items, const int32_t* __restrict__ nitems, int nb, int n, int64_t M,
-    int64_t ncols, float* __restrict__ A, double* __restrict__ tau) {
-#pragma clang fp contract(off)
-  extern __shared__ float2 band[];  // H rows of the extended array, stride ls
-  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
-  const int4 it = items[blockIdx.x];
-  const int bkt = it.x, start = it.y, len = it.z;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane >> 3, lj = lane & 7;  // row and column of the lane in its tile
-  const int nt = (n + 7) / 8;               // tiles per side
-  if (bkt == nb - 1) {  // identically zero columns (uniform per workgroup)
-    if (wave >= len) return;
-    const int64_t j = order[start + wave], j2 = ncols - 1 - j;
-    float* col = A + j * M;
-    float* col2 = A + j2 * M;
-    for (int a = 0; a < n; ++a)
-      for (int b = lane; b < n; b += 64) {
-        __builtin_nontemporal_store(0.0f, col + a * n + b);
-        __builtin_nontemporal_store(0.0f, col2 + a * n + b);
-      }
-    if (lane == 0) tau[j] = tau[j2] = 0.0;
-    return;
-  }
-  const float2* src = pairs + (int64_t)bkt * Np * Np;
-  const int Ne = cubic_ext(Np);
-  const bool live = wave < len;
-  int64_t j = 0;
-  ColGeom g;
-  g.ct = 1.0; g.st = 0.0; g.w = 0.0;
-  if (live) {
-    j = order[start + wave];
-    g = geo[j];
-  }
-  // the half turn of column j: column ncols-1-j, entry (n-1-a, n-1-b) = entry (a, b)
-  // (its tap coordinates are the same float64 values, the products negated twice)
-  const int64_t j2 = ncols - 1 - j;
-  const bool pair = j2 != j;
-  float* col = A + j * M;
-  float* col2 = A + j2 * M;
-  const double c = (double)(n - 1) * 0.5;
-  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
-  const double pad = (double)kSplinePad;
-  double tsum = 0.0;
-  for (int bi = 0; bi < nbands; ++bi) {
-    const int s0 = bi * (H - 3);
-    const int rows = (Ne - s0 < H) ? Ne - s0 : H;
-    const int hi = (bi == nbands - 1) ? Ne : s0 + H - 4;  // last origin row of this band
-    __syncthreads();  // the previous band's reads are done
-    for (int q = tid; q < rows * Ne; q += 1024) {
-      const int r = q / Ne, cc = q - r * Ne;
-      const int pr = s0 + r - kCubicMargin, pc = cc - kCubicMargin;
-      float2 v = make_float2(0.0f, 0.0f);
-      if ((unsigned)pr < (unsigned)Np && (unsigned)pc < (unsigned)Np) v = src[(int64_t)pr * Np + pc];
-      band[r * ls + cc] = v;
-    }
-    __syncthreads();
-    if (!live) continue;
-    for (int ta = 0; ta < nt; ++ta) {
-      const int a = 8 * ta + li;
-      double stuy, ctuy;
-      {
-        const double uy = (double)a - c;
-        stuy = g.st * uy;
-        ctuy = g.ct * uy;
-      }
-      for (int tb = 0; tb < nt; ++tb) {
-        const int b = 8 * tb + lj;
-        if (a >= n || b >= n) continue;
-        const double ux = (double)b - c;
-        const double rowf = c + ((-g.st) * ux + ctuy) + pad;
-        const double r0f = floor(rowf);
-        int r0 = (int)r0f;  // |rowf| < 3n + pad: exact
-        r0 = r0 < -3 ? -3 : (r0 > Np + 1 ? Np + 1 : r0);
-        const int R = r0 + kCubicMargin - 1;  // extended row of the first tap
-        if (R < s0 || R > hi) continue;
-        const double colf = c + (g.ct * ux + stuy) + pad;
-        const double c0f = floor(colf);
-        int c0 = (int)c0f;
-        c0 = c0 < -3 ? -3 : (c0 > Np + 1 ? Np + 1 : c0);
-        float wy[4], wx[4];
-        cubic_weights(rowf - r0f, wy);
-        cubic_weights(colf - c0f, wx);
-        const float2* t0 = band + (R - s0) * ls + (c0 + kCubicMargin - 1);
-        float X = 0.0f, Y = 0.0f;
-#pragma unroll
-        for (int dr = 0; dr < 4; ++dr) {
-          const float2* tr = t0 + dr * ls;
-          const float2 p0 = tr[0], p1 = tr[1], p2 = tr[2], p3 = tr[3];
-          float x = wx[0] * p0.x, y = wx[0] * p0.y;
-          x = fmaf(wx[1], p1.x, x);
-          y = fmaf(wx[1], p1.y, y);
-          x = fmaf(wx[2], p2.x, x);
-          y = fmaf(wx[2], p2.y, y);
-          x = fmaf(wx[3], p3.x, x);
-          y = fmaf(wx[3], p3.y, y);
-          X = fmaf(wy[dr], x, X);
-          Y = fmaf(wy[dr], y, Y);
-        }
-        const float val = fmaf(wk1, Y, wk0 * X);
-        col[a * n + b] = val;
-        if (pair) col2[(n - 1 - a) * n + (n - 1 - b)] = val;
-        tsum += (double)val;
-      }
-    }
-  }
-  if (!live) return;
-  tsum = wave_sum(tsum);
-  if (lane == 0) {
-    tau[j] = tsum;
-    if (pair) tau[j2] = tsum;
-  }
-}
-
 }  // namespace
 
 size_t spline_scratch_bytes(int K, int n) {
@@ -405,37 +237,6 @@ hipError_t launch_spline_pairs(const float* cube, int K, int n, void* scratch, f
     e = hipGetLastError();
   }
   return e;
-}
-
-bool build_cubic_lds_supported(int n) {
-  const int Np = n + 2 * kSplinePad;
-  return n <= 256 && cubic_band_rows(Np) >= 16;
-}
-
-size_t build_cubic_lds_scratch_bytes(int K, int64_t ncols) { return bucket_scratch_bytes(K, ncols); }
-
-hipError_t launch_build_cubic_lds(const float* pairs, int K, const ColGeom* geo, int n, int64_t M,
-                                  int64_t ncols, float* A32, double* tau, void* scratch,
-                                  hipStream_t s) {
-  // the first half of the columns (and the centre of an odd grid), each
-  // written with its half turn
-  BucketPlan bp;
-  hipError_t e = launch_bucket_sort(geo, (ncols + 1) / 2, K, scratch, &bp, s);
-  if (e != hipSuccess) return e;
-  const int Np = n + 2 * kSplinePad, Ne = cubic_ext(Np), ls = cubic_stride(Np);
-  const int H = cubic_band_rows(Np);
-  const int nbands = (H >= Ne) ? 1 : (Ne - 3 + (H - 3) - 1) / (H - 3);
-  const size_t lds = (size_t)H * ls * sizeof(float2);
-  const float2* P = reinterpret_cast<const float2*>(pairs);
-  auto launch = [&](auto kern) -> hipError_t {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    kern<<<(unsigned)bp.items_max, 1024, lds, s>>>(P, Np, ls, H, nbands, geo, bp.order, bp.items,
-                                                   bp.nitems, bp.nb, n, M, ncols, A32, tau);
-    return hipGetLastError();
-  };
-  return launch(build_cubic_lds_kernel);
 }
 
 }  // namespace psflib

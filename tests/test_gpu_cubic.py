@@ -29,8 +29,8 @@ CASES = [
     (33, 7, 0.37, 5, "nonuniform", "linear", "clamp"),
     (20, 45, 0.21, 9, "linear", "nearest", "zero"),
     (16, 13, 0.6, 1, "linear", "linear", "zero"),
-    (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),   # LDS build in two row bands
-    (260, 3, 0.4, 3, "nonuniform", "linear", "clamp"),   # too large for LDS bands: gather build
+    (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),   # orbit build, odd PSF side (scalar stores)
+    (260, 3, 0.4, 3, "nonuniform", "linear", "clamp"),   # 16-bit forms beyond 256^2: the gather build
 ]
 
 

@@ -21,9 +21,9 @@ pytestmark = pytest.mark.gpu
 U16 = {"bf16": 2.0**-8, "fp16": 2.0**-11}
 
 CASES = [
-    # n, N, S, K, kind, rotate  (32^2 takes the LDS build, 150^2 the orbit build
-    # from a staged box per tile (bilinear) or LDS row bands (cubic), 260^2 the
-    # gather build)
+    # n, N, S, K, kind, rotate  (32^2 takes the LDS build, 150^2 and 260^2 the
+    # orbit builds from a staged box per tile; flux-preserving columns are built
+    # in float32 and packed for the 16-bit forms)
     (32, 32, 0.5, 16, "c1", "bilinear"),
     (150, 5, 0.4, 4, "nonuniform", "bilinear"),
     (260, 3, 0.4, 3, "nonuniform", "bilinear"),

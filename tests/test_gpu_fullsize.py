@@ -235,7 +235,7 @@ MODES = {
 @pytest.mark.parametrize("mode", list(MODES))
 def test_c2_modes_sampled(torch, c2, sample, mode):
     """The build modes the bench times at 128^2 (nearest radial samples,
-    cubic-spline rotation in LDS row bands, flux-preserving columns) on the
+    cubic-spline rotation by orbits from staged boxes, flux-preserving columns) on the
     sampled columns and a scene supported on them.  Bounds as in the small-size
     tests of each mode: non-negative entries relative (1e-6, 2e-6 rescaled),
     cubic ones against the column bound b_j (times |s_j| when rescaled)."""

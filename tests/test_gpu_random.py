@@ -33,8 +33,8 @@ def _cases(count=24, seed=2106, n_range=(2, 49), N_range=(1, 41)):
     return out
 
 
-# small PSFs (one LDS-staged pair), then large ones (bilinear: a staged box per
-# tile up to 256^2; cubic: LDS row bands; the gather builds beyond)
+# small PSFs (one LDS-staged pair), then large ones (a staged box per tile; the
+# gather builds for 16-bit libraries beyond 256^2 that would need a float32 copy)
 @pytest.mark.parametrize("case", _cases() + _cases(8, 61209, (100, 271), (1, 13)), ids=lambda c: "n{n}-N{N}-K{K}-{interp}-{oob}-{rotate}-{flux}-{storage}-B{B}".format(**c))
 def test_random_configuration(case):
     import torch
