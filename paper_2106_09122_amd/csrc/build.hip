@@ -8,9 +8,10 @@
 // workgroup builds one group of 8 adjacent columns; each thread produces row i
 // of all 8 columns, so every store is coalesced: the FP32 form writes 8
 // contiguous 256-byte runs per wave (one per column), the 16-bit forms one
-// 16-byte group per thread (1 KiB per wave).  Coordinates and bilinear weights
-// are float64 (bit-for-bit the oracle's operation order, no contraction); the
-// radial blend and the weighted sum run in float32.  Column sums are
+// 16-byte group per thread (1 KiB per wave).  Coordinates are float64
+// (bit-for-bit the oracle's operation order, no contraction); the fractional
+// offsets are rounded once to float32, and the weights, the radial blend and
+// the weighted sum run in float32, in the LDS-staged builds' order.  Column sums are
 // accumulated in float64 and reduced in a fixed order.
 #include <math.h>
 
@@ -36,11 +37,14 @@ __device__ __forceinline__ float tap(const float2* __restrict__ P, int n, int r,
   return 0.0f;
 }
 
-// Source coordinates of output pixel offset (ux, uy) under R(-theta), and
-// their bilinear weights; float64, no contraction, in the oracle's order.
+// Source coordinates of output pixel offset (ux, uy) under R(-theta) (float64,
+// no contraction, in the oracle's order) and the fractional offsets and their
+// complements, each rounded once to float32; the bilinear weights are their
+// float32 products, as in the LDS-staged builds, so both forms give identical
+// values.
 struct Bilinear {
   int r0, c0;
-  float w00, w01, w10, w11;
+  float fx, gx, fy, gy;
 };
 
 __device__ __forceinline__ Bilinear bilinear_weights(double ct, double st, double c, double ux,
@@ -55,10 +59,10 @@ __device__ __forceinline__ Bilinear bilinear_weights(double ct, double st, doubl
   const double fx = colf - c0f;
   const double fy = rowf - r0f;
   Bilinear b;
-  b.w00 = (float)((1.0 - fy) * (1.0 - fx));
-  b.w01 = (float)((1.0 - fy) * fx);
-  b.w10 = (float)(fy * (1.0 - fx));
-  b.w11 = (float)(fy * fx);
+  b.fx = (float)fx;
+  b.gx = (float)(1.0 - fx);
+  b.fy = (float)fy;
+  b.gy = (float)(1.0 - fy);
   b.c0 = (int)c0f;
   b.r0 = (int)r0f;
   return b;
@@ -71,10 +75,10 @@ __device__ __forceinline__ float column_value(const ColumnParams& cp, int n, dou
   const float q01 = tap(cp.src, n, b.r0, b.c0 + 1, cp.wk0, cp.wk1);
   const float q10 = tap(cp.src, n, b.r0 + 1, b.c0, cp.wk0, cp.wk1);
   const float q11 = tap(cp.src, n, b.r0 + 1, b.c0 + 1, cp.wk0, cp.wk1);
-  float v = b.w00 * q00;
-  v = fmaf(b.w01, q01, v);
-  v = fmaf(b.w10, q10, v);
-  v = fmaf(b.w11, q11, v);
+  float v = (b.gy * b.gx) * q00;
+  v = fmaf(b.gy * b.fx, q01, v);
+  v = fmaf(b.fy * b.gx, q10, v);
+  v = fmaf(b.fy * b.fx, q11, v);
   return v;
 }
 
