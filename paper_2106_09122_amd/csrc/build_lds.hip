@@ -1325,192 +1325,6 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
 
-// 16-bit orbit build for pairs larger than the LDS (n > 141, N a
-// multiple of 8): build_orbit16_kernel's unit tiles and copies, with each
-// wave's taps read from a staged box (as build_orbit_box_kernel) of the 32 x 32
-// pixels it forms as four 8 x 32 tiles.  LDS: 16 box regions, then the two
-// unit tiles.
-template <bool BF16>
-__global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __restrict__ cube, int K,
-                                                                 const ColGeom* __restrict__ geo,
-                                                                 const int32_t* __restrict__ reps,
-                                                                 const int4* __restrict__ items,
-                                                                 const int32_t* __restrict__ nitems,
-                                                                 int nb, int n, int64_t M, int rpr,
-                                                                 int64_t nreps,
-                                                                 uint16_t* __restrict__ Mh,
-                                                                 double* __restrict__ part) {
-  constexpr int TA = 8, TB = 32, TP = TB + 1;
-  constexpr int TILE = 2 * TA * TP * 8;  // uint16 per buffer
-  extern __shared__ float QS[];
-  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
-  const int4 it = items[blockIdx.x];
-  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
-  const bool zero_bucket = bkt == nb - 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
-  uint16_t* tiles = reinterpret_cast<uint16_t*>(QS + 16 * kFpRegion);
-  float* Q = QS + wave * kFpRegion;
-  const int sp = w0 + wave;
-  const bool live = sp >= first && sp < first + len;  // uniform per wave
-  const int h = wave >> 3, u = wave & 7;
-  ColGeom g;
-  g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
-  if (live) g = geo[reps[sp]];
-  const double c = (double)(n - 1) * 0.5;
-  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
-  const float* Pk = cube + (int64_t)(zero_bucket ? 0 : bkt) * M;
-  const float* Pk1 = (K > 1) ? Pk + M : nullptr;
-  const int64_t G0 = (int64_t)(w0 / 8) * 4;
-  int lo[2], hi[2];  // the item's slots of each block, relative to the block
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int s0 = w0 + 8 * q;
-    lo[q] = (first > s0) ? first - s0 : 0;
-    hi[q] = (first + len < s0 + 8) ? first + len - s0 : 8;
-  }
-  const int li = lane >> 3, lk = lane & 7;
-  // copy roles: threads 0..511 along rows, 512..1023 along columns
-  const bool along_cols = tid >= 512;
-  const int cq = (tid & 511) >> 8, crem = tid & 255;
-  double tsum = 0.0;
-  int buf = 0;
-  for (int a0 = ra; a0 < rb; a0 += 32) {
-    const int ae = (a0 + 32 < rb) ? a0 + 32 : rb;
-    for (int b0 = 0; b0 < n; b0 += TB) {
-      const int be = (b0 + TB < n) ? b0 + TB : n;
-      int bs = 1, base = 0;
-      if (live && !zero_bucket) {  // uniform per wave: stage the box of rows [a0, ae), columns [b0, be)
-        int rmin, rmax, cmin, cmax;
-        {
-          int r0, c0;
-          tap_origin(g, c, a0, b0, r0, c0);
-          rmin = rmax = r0;
-          cmin = cmax = c0;
-#pragma unroll
-          for (int k = 1; k < 4; ++k) {
-            tap_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, r0, c0);
-            rmin = min(rmin, r0);
-            rmax = max(rmax, r0);
-            cmin = min(cmin, c0);
-            cmax = max(cmax, c0);
-          }
-        }
-        const int Rlo = max(rmin + 1, 0), Clo = max(cmin + 1, 0);
-        const int bh = min(max(min(rmax + 2, n + 1) - Rlo + 1, 0), kFpSpan);
-        const int bw = min(max(min(cmax + 2, n + 1) - Clo + 1, 0), kFpSpan);
-        bs = bw | 1;
-        base = Rlo * bs + Clo;
-        if (bh > 0 && bw > 0) {
-          const int q64 = 64 / bw, r64 = 64 - q64 * bw;
-          int rr = lane / bw, cc = lane - rr * bw;
-          while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
-            float xv[8], yv[8];
-            int dst[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              const int R = Rlo + rr, C = Clo + cc;
-              const bool in = rr < bh;
-              const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
-              const int off = (R - 1) * n + (C - 1);
-              xv[k] = inner ? Pk[off] : 0.0f;
-              yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
-              dst[k] = in ? rr * bs + cc : -1;
-              cc += r64;
-              rr += q64;
-              if (cc >= bw) {
-                cc -= bw;
-                ++rr;
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-              if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
-          }
-        }
-        wave_lds_sync();  // the box is staged
-      }
-      for (int a1 = a0; a1 < ae; a1 += TA, buf ^= 1) {  // uniform over the workgroup
-        uint16_t* tile = tiles + buf * TILE;
-        if (live) {
-          const int a = a1 + li, bb = b0 + 4 * lk;
-          if (a < ae) {
-            double stuy, ctuy;
-            {
-#pragma clang fp contract(off)
-              const double uy = (double)a - c;
-              stuy = g.st * uy;
-              ctuy = g.ct * uy;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (bb + q >= n) continue;
-              double ctux, mstux;
-              {
-#pragma clang fp contract(off)
-                const double ux = (double)(bb + q) - c;
-                ctux = g.ct * ux;
-                mstux = (-g.st) * ux;
-              }
-              const float val = zero_bucket ? 0.0f
-                                            : box_value(Q, ctux, mstux, stuy, ctuy, c, n, bs, base);
-              tsum += (double)val;
-              const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
-              uint32_t hv;
-              if constexpr (BF16) {
-                uint32_t w = __float_as_uint(xs);
-                w += 0x7FFFu + ((w >> 16) & 1u);  // finite: round to nearest, ties to even
-                hv = w >> 16;
-              } else {
-                hv = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)xs);
-              }
-              tile[((h * TA + li) * TP + 4 * lk + q) * 8 + u] = (uint16_t)hv;
-            }
-          }
-        }
-        __syncthreads();
-        // one unit per thread: block cq, 8 rows x 32 columns
-        if (lo[cq] < hi[cq]) {
-          int r, cb;
-          if (along_cols) {
-            cb = crem >> 3;
-            r = crem & 7;
-          } else {
-            r = crem >> 5;
-            cb = crem & 31;
-          }
-          const int a = a1 + r, b = b0 + cb;
-          if (a < ae && b < n) {
-            const uint16_t* src = tile + ((cq * TA + r) * TP + cb) * 8;
-            uint16_t* dA;
-            uint16_t* dB;
-            if (along_cols) {
-              dA = Mh + ((G0 + 4 * cq + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
-              dB = Mh + ((G0 + 4 * cq + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
-            } else {
-              dA = Mh + ((G0 + 4 * cq + 0) * M + (int64_t)a * n + b) * 8;
-              dB = Mh + ((G0 + 4 * cq + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
-            }
-            if (lo[cq] == 0 && hi[cq] == 8) {
-              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dA));
-              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dB));
-            } else {
-              for (int s = lo[cq]; s < hi[cq]; ++s) {
-                dA[s] = src[s];
-                dB[s] = src[s];
-              }
-            }
-          }
-        }
-      }
-    }
-  }
-  if (!live) return;
-  tsum = wave_sum_f64(tsum);
-  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
-}
-
 // Cubic-spline orbit build: the quarter-turn orbits of the bilinear builds
 // (the four members of an orbit sample the spline at the same source points,
 // so one base column is computed and four are written), each 32 x 32 pixel
@@ -1723,6 +1537,244 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
       }
     }
   }
+  tsum = wave_sum_f64(tsum);
+  if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
+}
+
+// 16-bit orbit build for pairs larger than the LDS (n > 141, N a multiple of
+// 8), bilinear or cubic-spline: build_orbit16_kernel's unit tiles and copies,
+// with each wave's taps read from a staged box (as build_orbit_box_kernel and
+// build_cubic_orbit_kernel) of the 32 x 32 pixels it forms as 32 / TA tiles of
+// TA x 32.  LDS: 16 box regions, then the two unit tiles; the cubic boxes are
+// larger (48 x 49 floats), so the cubic form takes 4-row tiles (each lane two
+// pixels of a tile row) where the bilinear form takes 8-row ones (four).
+template <bool BF16, bool CUBIC>
+__global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __restrict__ src0, int K,
+                                                                 const ColGeom* __restrict__ geo,
+                                                                 const int32_t* __restrict__ reps,
+                                                                 const int4* __restrict__ items,
+                                                                 const int32_t* __restrict__ nitems,
+                                                                 int nb, int n, int64_t M, int Np,
+                                                                 int rpr, int64_t nreps,
+                                                                 uint16_t* __restrict__ Mh,
+                                                                 double* __restrict__ part) {
+  constexpr int TA = CUBIC ? 4 : 8, TB = 32, TP = TB + 1;
+  constexpr int CPL = (TA * TB) / 64;      // pixels of a tile row per lane
+  constexpr int LPR = TB / CPL;            // lanes per tile row
+  constexpr int TILE = 2 * TA * TP * 8;    // uint16 per buffer
+  constexpr int REGION = CUBIC ? kCbRegion : kFpRegion;
+  extern __shared__ float QS[];
+  if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
+  const int4 it = items[blockIdx.x];
+  const int bkt = it.x, first = it.y, len = it.z, w0 = it.w;
+  const bool zero_bucket = bkt == nb - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ra = (int)blockIdx.y * rpr, rb = (ra + rpr < n) ? ra + rpr : n;
+  uint16_t* tiles = reinterpret_cast<uint16_t*>(QS + 16 * REGION);
+  float* Q = QS + wave * REGION;
+  const int sp = w0 + wave;
+  const bool live = sp >= first && sp < first + len;  // uniform per wave
+  const int h = wave >> 3, u = wave & 7;
+  ColGeom g;
+  g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
+  if (live) g = geo[reps[sp]];
+  const double c = (double)(n - 1) * 0.5;
+  const double pad = (double)kSplinePad;
+  const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
+  const int pb = zero_bucket ? 0 : bkt;
+  const float* Pk = CUBIC ? src0 : src0 + (int64_t)pb * M;  // bilinear: the sample pair
+  const float* Pk1 = (!CUBIC && K > 1) ? Pk + M : nullptr;
+  const float2* Pc = reinterpret_cast<const float2*>(src0) + (CUBIC ? (int64_t)pb * Np * Np : 0);  // cubic
+  const int64_t G0 = (int64_t)(w0 / 8) * 4;
+  int lo[2], hi[2];  // the item's slots of each block, relative to the block
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int s0 = w0 + 8 * q;
+    lo[q] = (first > s0) ? first - s0 : 0;
+    hi[q] = (first + len < s0 + 8) ? first + len - s0 : 8;
+  }
+  const int li = lane / LPR, lk = lane % LPR;
+  // copy roles: threads 0..511 along rows, 512..1023 along columns; unit cu of
+  // a direction is block cu / (TA TB), row and column from cu % (TA TB)
+  const bool along_cols = tid >= 512;
+  const int cu = tid & 511, cq = cu / (TA * TB), crem = cu % (TA * TB);
+  double tsum = 0.0;
+  int buf = 0;
+  for (int a0 = ra; a0 < rb; a0 += 32) {
+    const int ae = (a0 + 32 < rb) ? a0 + 32 : rb;
+    for (int b0 = 0; b0 < n; b0 += TB) {
+      const int be = (b0 + TB < n) ? b0 + TB : n;
+      int bs = 1, base = 0, Rlo = 0, Clo = 0;
+      if (live && !zero_bucket) {  // uniform per wave: stage the box of rows [a0, ae), columns [b0, be)
+        int rmin, rmax, cmin, cmax;
+        {
+          int r0, c0;
+          if constexpr (CUBIC) cubic_origin(g, c, a0, b0, Np, r0, c0);
+          else tap_origin(g, c, a0, b0, r0, c0);
+          rmin = rmax = r0;
+          cmin = cmax = c0;
+#pragma unroll
+          for (int k = 1; k < 4; ++k) {
+            if constexpr (CUBIC)
+              cubic_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, Np, r0, c0);
+            else
+              tap_origin(g, c, (k & 1) ? ae - 1 : a0, (k & 2) ? be - 1 : b0, r0, c0);
+            rmin = min(rmin, r0);
+            rmax = max(rmax, r0);
+            cmin = min(cmin, c0);
+            cmax = max(cmax, c0);
+          }
+        }
+        int bh, bw;
+        if constexpr (CUBIC) {
+          Rlo = rmin - 1;
+          Clo = cmin - 1;
+          bh = min(rmax - rmin + 4, kCbSpan);
+          bw = min(cmax - cmin + 4, kCbSpan);
+        } else {
+          Rlo = max(rmin + 1, 0);
+          Clo = max(cmin + 1, 0);
+          bh = min(max(min(rmax + 2, n + 1) - Rlo + 1, 0), kFpSpan);
+          bw = min(max(min(cmax + 2, n + 1) - Clo + 1, 0), kFpSpan);
+        }
+        bs = bw | 1;
+        base = Rlo * bs + Clo;
+        if (bh > 0 && bw > 0) {
+          const int q64 = 64 / bw, r64 = 64 - q64 * bw;
+          int rr = lane / bw, cc = lane - rr * bw;
+          while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
+            float xv[8], yv[8];
+            int dst[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int R = Rlo + rr, C = Clo + cc;
+              const bool in = rr < bh;
+              if constexpr (CUBIC) {
+                const bool inner = in && (unsigned)R < (unsigned)Np && (unsigned)C < (unsigned)Np;
+                const float2 p = inner ? Pc[R * Np + C] : make_float2(0.0f, 0.0f);
+                xv[k] = p.x;
+                yv[k] = p.y;
+              } else {
+                const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
+                const int off = (R - 1) * n + (C - 1);
+                xv[k] = inner ? Pk[off] : 0.0f;
+                yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
+              }
+              dst[k] = in ? rr * bs + cc : -1;
+              cc += r64;
+              rr += q64;
+              if (cc >= bw) {
+                cc -= bw;
+                ++rr;
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
+          }
+        }
+        wave_lds_sync();  // the box is staged
+      }
+      for (int a1 = a0; a1 < ae; a1 += TA, buf ^= 1) {  // uniform over the workgroup
+        uint16_t* tile = tiles + buf * TILE;
+        if (live) {
+          const int a = a1 + li, bb = b0 + CPL * lk;
+          if (a < ae) {
+            double stuy, ctuy;
+            {
+#pragma clang fp contract(off)
+              const double uy = (double)a - c;
+              stuy = g.st * uy;
+              ctuy = g.ct * uy;
+            }
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+              if (bb + q >= n) continue;
+              double ctux, mstux;
+              {
+#pragma clang fp contract(off)
+                const double ux = (double)(bb + q) - c;
+                ctux = g.ct * ux;
+                mstux = (-g.st) * ux;
+              }
+              float val = 0.0f;
+              if (!zero_bucket) {
+                if constexpr (CUBIC) {
+#pragma clang fp contract(off)
+                  const double rowf = c + (mstux + ctuy) + pad;
+                  const double colf = c + (ctux + stuy) + pad;
+                  const double r0f = floor(rowf), c0f = floor(colf);
+                  const int r0 = clamp_origin((int)r0f, Np), c0 = clamp_origin((int)c0f, Np);
+                  float wy[4], wx[4];
+                  cubic_weights(rowf - r0f, wy);
+                  cubic_weights(colf - c0f, wx);
+                  const float* t = Q + (r0 - 1 - Rlo) * bs + (c0 - 1 - Clo);
+#pragma unroll
+                  for (int dr = 0; dr < 4; ++dr) {
+                    const float* tr = t + dr * bs;
+                    float v = wx[0] * tr[0];
+                    v = fmaf(wx[1], tr[1], v);
+                    v = fmaf(wx[2], tr[2], v);
+                    v = fmaf(wx[3], tr[3], v);
+                    val = fmaf(wy[dr], v, val);
+                  }
+                } else {
+                  val = box_value(Q, ctux, mstux, stuy, ctuy, c, n, bs, base);
+                }
+              }
+              tsum += (double)val;
+              const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
+              uint32_t hv;
+              if constexpr (BF16) {
+                uint32_t w = __float_as_uint(xs);
+                w += 0x7FFFu + ((w >> 16) & 1u);  // finite: round to nearest, ties to even
+                hv = w >> 16;
+              } else {
+                hv = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)xs);
+              }
+              tile[((h * TA + li) * TP + CPL * lk + q) * 8 + u] = (uint16_t)hv;
+            }
+          }
+        }
+        __syncthreads();
+        // one unit per thread: block cq, TA rows x 32 columns
+        if (cq < 2 && lo[cq] < hi[cq]) {
+          int r, cb;
+          if (along_cols) {
+            cb = crem / TA;
+            r = crem % TA;
+          } else {
+            r = crem >> 5;
+            cb = crem & 31;
+          }
+          const int a = a1 + r, b = b0 + cb;
+          if (a < ae && b < n) {
+            const uint16_t* src = tile + ((cq * TA + r) * TP + cb) * 8;
+            uint16_t* dA;
+            uint16_t* dB;
+            if (along_cols) {
+              dA = Mh + ((G0 + 4 * cq + 1) * M + (int64_t)b * n + (n - 1 - a)) * 8;
+              dB = Mh + ((G0 + 4 * cq + 3) * M + (int64_t)(n - 1 - b) * n + a) * 8;
+            } else {
+              dA = Mh + ((G0 + 4 * cq + 0) * M + (int64_t)a * n + b) * 8;
+              dB = Mh + ((G0 + 4 * cq + 2) * M + (int64_t)(n - 1 - a) * n + (n - 1 - b)) * 8;
+            }
+            if (lo[cq] == 0 && hi[cq] == 8) {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(src);
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dA));
+              __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(dB));
+            } else {
+              for (int s = lo[cq]; s < hi[cq]; ++s) {
+                dA[s] = src[s];
+                dB[s] = src[s];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!live) return;
   tsum = wave_sum_f64(tsum);
   if (lane == 0) part[(int64_t)blockIdx.y * nreps + sp] = tsum;
 }
@@ -2068,13 +2120,16 @@ static size_t orbit16_pair_bytes(int n) {
 static size_t orbit16_lds_bytes(int n) { return orbit16_pair_bytes(n) + (size_t)2 * (2 * 8 * 33 * 16); }
 
 // LDS of the 16-bit box kernel: 16 box regions, then the two unit tiles
-static size_t orbit16_box_lds_bytes() { return (size_t)16 * kFpRegion * sizeof(float) + (size_t)2 * (2 * 8 * 33 * 16); }
+static size_t orbit16_box_lds_bytes(bool cubic) {
+  return cubic ? (size_t)16 * kCbRegion * sizeof(float) + (size_t)2 * (2 * 4 * 33 * 16)
+               : (size_t)16 * kFpRegion * sizeof(float) + (size_t)2 * (2 * 8 * 33 * 16);
+}
 
 // the pair in LDS with the unit tiles, or (up to kBoxMaxN) staged boxes
 bool build_orbit16_supported(int n, int K, int N) {
   if (N % 8 != 0 || !orbit_sort_fits(K, N)) return false;
   if (pair_fits_lds(n)) return orbit16_lds_bytes(n) <= (size_t)kLdsBuildMaxBytes;
-  return n <= kBoxMaxN && orbit16_box_lds_bytes() <= (size_t)kLdsBuildMaxBytes;
+  return n <= kBoxMaxN && orbit16_box_lds_bytes(false) <= (size_t)kLdsBuildMaxBytes;
 }
 
 // float32: the pair in LDS, or (up to kBoxMaxN) a staged box per tile
@@ -2096,17 +2151,17 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
   uint16_t* Mh = reinterpret_cast<uint16_t*>(lib);
   const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
   if (!pair_fits_lds(n)) {  // a staged box per 32 x 32 pixels
-    const size_t lds = orbit16_box_lds_bytes();
+    const size_t lds = orbit16_box_lds_bytes(false);
     auto launch = [&](auto kern) -> hipError_t {
       const void* fn = reinterpret_cast<const void*>(kern);
       hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return err;
-      kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, pl.rpr,
+      kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, 0, pl.rpr,
                                    pl.o.nreps, Mh, pl.part);
       return hipGetLastError();
     };
-    e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true>)
-                                    : launch(build_orbit16_box_kernel<false>);
+    e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true, false>)
+                                    : launch(build_orbit16_box_kernel<false, false>);
     if (e != hipSuccess) return e;
     return orbit_finish(pl, tau, s);
   }
@@ -2121,6 +2176,36 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
     return hipGetLastError();
   };
   e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_kernel<true>) : launch(build_orbit16_kernel<false>);
+  if (e != hipSuccess) return e;
+  return orbit_finish(pl, tau, s);
+}
+
+bool build_cubic_orbit16_supported(int n, int K, int N) {
+  return N % 8 == 0 && build_cubic_orbit_supported(n, K, N) &&
+         orbit16_box_lds_bytes(true) <= (size_t)kLdsBuildMaxBytes;
+}
+
+hipError_t launch_build_cubic_orbit16(int storage, const float* pairs, int K, const ColGeom* geo,
+                                      int n, int N, int64_t M, int32_t* perm, int32_t* eslot,
+                                      int32_t* slot_of, void* lib, double* tau, void* scratch,
+                                      hipStream_t s) {
+  const OrbitPlan pl = orbit_plan(K, N, n, scratch);
+  hipError_t e = orbit_sort(geo, pl, perm, slot_of, eslot, s);
+  if (e != hipSuccess) return e;
+  uint16_t* Mh = reinterpret_cast<uint16_t*>(lib);
+  const dim3 grid((unsigned)pl.items_max, (unsigned)pl.nranges);
+  const size_t lds = orbit16_box_lds_bytes(true);
+  const int Np = n + 2 * kSplinePad;
+  auto launch = [&](auto kern) -> hipError_t {
+    const void* fn = reinterpret_cast<const void*>(kern);
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    kern<<<grid, 1024, lds, s>>>(pairs, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, Np, pl.rpr,
+                                 pl.o.nreps, Mh, pl.part);
+    return hipGetLastError();
+  };
+  e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true, true>)
+                                  : launch(build_orbit16_box_kernel<false, true>);
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
 }

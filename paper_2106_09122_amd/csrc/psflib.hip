@@ -324,23 +324,26 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   // fits the LDS, else a box of it per tile, read by the rotation-orbit
   // builds.  The gathers from pair-interleaved copies serve what those cannot
   // (bracket or column counts beyond the sort's bounds), and the 16-bit
-  // libraries of PSFs larger than 256 x 256 that would need a float32 copy
-  // (bilinear: N not a multiple of 8; cubic: any N; no rescale), which they
-  // write directly.  The builds write float32 columns when the
-  // flux-preserving rescale follows, or when a 16-bit library cannot be
+  // libraries of PSFs larger than 256 x 256 whose scene side is not a
+  // multiple of 8 (no rescale), which they write directly where the orbit
+  // builds would stage a float32 copy.  The builds write float32 columns when
+  // the flux-preserving rescale follows, or when a 16-bit library cannot be
   // written directly; the 16-bit forms then pack those columns in a last pass.
   const bool cubic = desc->rotate == PSFLIB_ROTATE_CUBIC;
   const bool flux = desc->flux == PSFLIB_FLUX_PRESERVE;
-  const bool big16 = desc->n > 256 && storage != PSFLIB_FP32 && !flux && (cubic || desc->N % 8 != 0);
+  const bool big16 = desc->n > 256 && storage != PSFLIB_FP32 && !flux && desc->N % 8 != 0;
   const bool lds = !big16 && (cubic ? psflib::build_cubic_orbit_supported(desc->n, K, desc->N)
                                     : psflib::build_lds_supported(desc->n, K, desc->N));
-  // 16-bit libraries of bilinear, unrescaled columns are written directly in
-  // bracket order: by quarter-turn orbits when N is a multiple of 8, else
-  // column by column when the pair fits the LDS; the other 16-bit builds go
-  // through float32 columns and a packing pass (natural order)
-  const bool plain16 = storage != PSFLIB_FP32 && !cubic && !flux && lds;
-  const bool orbit16 = plain16 && psflib::build_orbit16_supported(desc->n, K, desc->N);
-  const bool direct16 = orbit16 || (plain16 && psflib::build_lds16_supported(desc->n, K, L.ncols));
+  // 16-bit libraries of unrescaled columns are written directly in bracket
+  // order: by quarter-turn orbits when N is a multiple of 8 (bilinear or
+  // cubic), else (bilinear) column by column when the pair fits the LDS; the
+  // other 16-bit builds go through float32 columns and a packing pass
+  // (natural order)
+  const bool plain16 = storage != PSFLIB_FP32 && !flux && lds;
+  const bool orbit16 = plain16 && (cubic ? psflib::build_cubic_orbit16_supported(desc->n, K, desc->N)
+                                         : psflib::build_orbit16_supported(desc->n, K, desc->N));
+  const bool direct16 =
+      orbit16 || (plain16 && !cubic && psflib::build_lds16_supported(desc->n, K, L.ncols));
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
@@ -388,7 +391,15 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
-  if (cubic && lds) {
+  if (cubic && orbit16) {
+    e = psflib::launch_build_cubic_orbit16(storage, psflib::spline_pairs_of(path_tmp, K, desc->n), K,
+                                           h->geo, desc->n, desc->N, L.M,
+                                           reinterpret_cast<int32_t*>(lib + L.off_perm),
+                                           reinterpret_cast<int32_t*>(lib + L.off_eslot),
+                                           reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
+                                           tp + spline_bytes, s);
+    if (e != hipSuccess) return bail(e, "16-bit cubic orbit build kernels");
+  } else if (cubic && lds) {
     e = psflib::launch_build_cubic_orbit(psflib::spline_pairs_of(path_tmp, K, desc->n), K, h->geo,
                                          desc->n, desc->N, L.M, reinterpret_cast<float*>(bdst), tau,
                                          tp + spline_bytes, s);

@@ -154,6 +154,13 @@ bool build_cubic_orbit_supported(int n, int K, int N);
 hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* geo, int n, int N,
                                     int64_t M, float* A32, double* tau, void* scratch,
                                     hipStream_t s);
+// 16-bit cubic storage built by the same orbits (N % 8 == 0), slots as
+// launch_build_orbit16's; scratch of build_orbit_scratch_bytes(K, N, n) bytes.
+bool build_cubic_orbit16_supported(int n, int K, int N);
+hipError_t launch_build_cubic_orbit16(int storage, const float* pairs, int K, const ColGeom* geo,
+                                      int n, int N, int64_t M, int32_t* perm, int32_t* eslot,
+                                      int32_t* slot_of, void* lib, double* tau, void* scratch,
+                                      hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K, int N);

@@ -30,6 +30,8 @@ CASES = [
     (20, 45, 0.21, 9, "linear", "nearest", "zero"),
     (16, 13, 0.6, 1, "linear", "linear", "zero"),
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),   # orbit build, odd PSF side (scalar stores)
+    (150, 16, 0.4, 4, "nonuniform", "linear", "zero"),   # 16-bit forms written directly by orbits
+    (21, 8, 0.5, 3, "linear", "nearest", "clamp"),       # the same with partial tiles and one block
     (260, 3, 0.4, 3, "nonuniform", "linear", "clamp"),   # 16-bit forms beyond 256^2: the gather build
 ]
 

@@ -450,7 +450,7 @@ def test_get_columns_out_of_range_indices_give_zeros(torch, psflib, c1, c1_oracl
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("case", ["c1", "odd", "c2", "box", "gather", "cubic_gather"])
+@pytest.mark.parametrize("case", ["c1", "odd", "c2", "box", "gather", "cubic_box", "cubic_gather"])
 def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
     """The 16-bit library (built directly: by rotation orbits from the
     LDS-staged pair or from staged boxes, by columns in bracket order, or by
@@ -458,8 +458,8 @@ def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
     entries A32: the same float32 arithmetic, one rounding.  Checked on every
     column at 32^2, on an odd shape whose column count leaves a partial 8-slot
     group (padding), on 512 sampled columns at 128^2, on the 16-bit box
-    kernel (150^2 PSFs), and on the bilinear and cubic gathers (260^2 PSFs,
-    odd scene) against the float32 box builds."""
+    kernel (150^2 PSFs, bilinear and cubic), and on the bilinear and cubic
+    gathers (260^2 PSFs, odd scene) against the float32 box builds."""
     kw = {}
     if case == "c1":
         d = synth.config_inputs(1)
@@ -472,10 +472,10 @@ def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
         d = synth.config_inputs(2)
         cube, radii, N, S = d["cube"], d["radii"], d["N"], d["S"]
     else:
-        n, N = (150, 16) if case == "box" else (260, 3)
+        n, N = (150, 16) if case in ("box", "cubic_box") else (260, 3)
         cube, radii, _ = _shape_inputs(n, N, 0.4, 4, "nonuniform", n + N)
         S = 0.4
-        if case == "cubic_gather":
+        if case.startswith("cubic"):
             kw = dict(rotate="cubic")
     K = N * N
     cols = np.arange(K) if case != "c2" else np.unique(np.concatenate(
