@@ -32,6 +32,7 @@ CASES = [
     (150, 5, 0.4, 4, "nonuniform", "linear", "clamp"),   # orbit build, odd PSF side (scalar stores)
     (150, 16, 0.4, 4, "nonuniform", "linear", "zero"),   # 16-bit forms written directly by orbits
     (21, 8, 0.5, 3, "linear", "nearest", "clamp"),       # the same with partial tiles and one block
+    (143, 1, 0.5, 3, "linear", "linear", "zero"),        # one scene pixel: the centre orbit alone
     (260, 3, 0.4, 3, "nonuniform", "linear", "clamp"),   # 16-bit forms beyond 256^2: the gather build
 ]
 
@@ -88,17 +89,17 @@ def test_cubic_fp32(torch, case):
     assert np.all(np.abs(tau - A.sum(axis=0)) <= ENTRY * b * n * n + 1e-300)
     Z = rng.random(N * N).astype(np.float32)
     img = lib.apply(torch.from_numpy(Z).cuda()).cpu().numpy()
-    den = np.abs(A) @ Z.astype(np.float64) + ENTRY * (b @ Z.astype(np.float64))
-    assert np.all(np.abs(img - O.apply(A, Z)) <= IMG * den + 1e-300)
+    bound = IMG * (np.abs(A) @ Z.astype(np.float64)) + ENTRY * (b @ Z.astype(np.float64))
+    assert np.all(np.abs(img - O.apply(A, Z)) <= bound + 1e-300)
     g = rng.standard_normal(n * n).astype(np.float32)
     G = lib.apply_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
     gd = np.abs(g.astype(np.float64))
-    den = np.abs(A).T @ gd + ENTRY * b * gd.sum()
-    assert np.all(np.abs(G - O.apply_adjoint(A, g)) <= IMG * den + 1e-300)
+    bound = IMG * (np.abs(A).T @ gd) + ENTRY * b * gd.sum()
+    assert np.all(np.abs(G - O.apply_adjoint(A, g)) <= bound + 1e-300)
     Zb = rng.random((6, N * N)).astype(np.float32)
     out = lib.apply_batched(torch.from_numpy(Zb).cuda()).cpu().numpy()
-    den = (np.abs(A) @ Zb.T.astype(np.float64)).T + ENTRY * (Zb.astype(np.float64) @ b)[:, None]
-    assert np.all(np.abs(out - O.apply_batched(A, Zb)) <= IMG * den + 1e-300)
+    bound = IMG * (np.abs(A) @ Zb.T.astype(np.float64)).T + ENTRY * (Zb.astype(np.float64) @ b)[:, None]
+    assert np.all(np.abs(out - O.apply_batched(A, Zb)) <= bound + 1e-300)
     lib.close()
 
 

@@ -178,6 +178,7 @@ SHAPES = [
     (151, 16, 0.45, 3, "linear", "nearest", "clamp"),  # odd PSF side in the 16-bit box kernel
     (142, 24, 0.5, 5, "linear", "linear", "zero"),  # smallest pair beyond the LDS; 8-base blocks across brackets
     (145, 9, 0.5, 1, "linear", "linear", "clamp"),  # one PSF: boxes of a single sample
+    (143, 1, 0.5, 3, "linear", "linear", "zero"),   # one scene pixel: the centre orbit alone
     (199, 4, 0.5, 3, "nonuniform", "linear", "zero"),
     (256, 3, 0.9, 3, "linear", "linear", "clamp"),
     # PSFs larger than 256 x 256: staged boxes (float32; 16-bit when N is a
@@ -220,7 +221,7 @@ def test_shapes_fp32(torch, psflib, n, N, S, K, kind, interp, oob):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + SHAPES[13:18] + [SHAPES[-4], SHAPES[-2], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
+@pytest.mark.parametrize("n,N,S,K,kind,interp,oob", SHAPES[:3] + SHAPES[6:11] + SHAPES[13:19] + [SHAPES[-4], SHAPES[-2], SHAPES[-1]] + [(32, 32, 0.5, 16, "linear", "linear", "clamp")])
 def test_shapes_16bit(torch, psflib, fmt, n, N, S, K, kind, interp, oob):
     cube, radii, rng = _shape_inputs(n, N, S, K, kind, n * 1000 + N + 7)
     A = O.build_library(cube, radii, N, S, interp, oob)
