@@ -832,6 +832,12 @@ __device__ __forceinline__ float orbit_value(const float2* __restrict__ P2, doub
   return t.ok ? val : 0.0f;
 }
 
+// Modes of the float32 orbit kernels: the plain build; only the column sums
+// (no stores: the first pass of a flux-preserving build); or every value
+// multiplied by its column's float32 scale before it is stored and summed
+// (the second pass).
+constexpr int kPlain = kOrbitPlain, kSumsOnly = kOrbitSumsOnly, kScaled = kOrbitScaled;
+
 // Float32 orbit build.  Wave = base column over the item's rows in tiles of
 // 32 x 32 pixels; lane (i, k) = (lane / 8, lane % 8) forms the 4 x 4 block
 // at rows 4i.., columns 4k.. of a tile.  Each lane then holds four runs of
@@ -840,7 +846,7 @@ __device__ __forceinline__ float orbit_value(const float2* __restrict__ P2, doub
 // instruction fills eight whole 128-byte lines of one member (VEC: n % 4 ==
 // 0, every 4 x 4 block is wholly inside or outside the image, runs 16-byte
 // aligned; otherwise scalar stores).
-template <bool VEC>
+template <bool VEC, int MODE>
 __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restrict__ cube, int K,
                                                            const ColGeom* __restrict__ geo,
                                                            const int32_t* __restrict__ reps,
@@ -849,7 +855,8 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
                                                            int nb, int n, int ls, int N, int64_t M,
                                                            int rpr, int64_t nreps,
                                                            float* __restrict__ A,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part,
+    const float* __restrict__ colscale) {
   extern __shared__ float2 P2[];
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
@@ -868,7 +875,7 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
   float* C2 = A + orbit_member(j0, N, 2) * M;
   float* C3 = A + orbit_member(j0, N, 3) * M;
   if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
-    for (int x = lane; x < (rb - ra) * n; x += 64) {
+    for (int x = lane; MODE != kSumsOnly && x < (rb - ra) * n; x += 64) {
       const int64_t p = (int64_t)ra * n + x;
       __builtin_nontemporal_store(0.0f, C0 + p);
       if (!centre) {
@@ -881,6 +888,7 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
     return;
   }
   const ColGeom g = geo[j0];
+  const float sf = (MODE == kScaled) ? colscale[j0] : 1.0f;  // flux-preserving scale
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   const int li = lane >> 3, lk = lane & 7;
@@ -915,11 +923,12 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
           x[r][q] = 0.0f;
           if (VEC || (a < rb && bb + q < n)) {
             x[r][q] = orbit_value(P2, ctux[q], mstux[q], stuy, ctuy, c, n, ls, wk0, wk1);
+            if constexpr (MODE == kScaled) x[r][q] *= sf;
             tsum += (double)x[r][q];
           }
           if (q == 1) __builtin_amdgcn_sched_barrier(0);  // two elements in flight
         }
-        if constexpr (VEC) {  // the row's runs of C0 and C2
+        if constexpr (VEC && MODE != kSumsOnly) {  // the row's runs of C0 and C2
           __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
                                       reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
           if (!centre)
@@ -929,7 +938,8 @@ __global__ __launch_bounds__(1024) void build_orbit_kernel(const float* __restri
         // one row of the block at a time: bounds the live coordinate temporaries
         __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (VEC) {
+      if constexpr (MODE == kSumsOnly) {
+      } else if constexpr (VEC) {
         if (!centre) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -1013,7 +1023,7 @@ __device__ __forceinline__ float box_value(const float* __restrict__ Q, double c
   return t.ok ? val : 0.0f;
 }
 
-template <bool VEC>
+template <bool VEC, int MODE>
 __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __restrict__ cube, int K,
                                                                const ColGeom* __restrict__ geo,
                                                                const int32_t* __restrict__ reps,
@@ -1022,7 +1032,8 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
                                                                int nb, int n, int N, int64_t M,
                                                                int rpr, int64_t nreps,
                                                                float* __restrict__ A,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part,
+    const float* __restrict__ colscale) {
   extern __shared__ float QS[];  // 16 regions of kFpRegion floats
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
@@ -1039,7 +1050,7 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
   float* C2 = A + orbit_member(j0, N, 2) * M;
   float* C3 = A + orbit_member(j0, N, 3) * M;
   if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
-    for (int x = lane; x < (rb - ra) * n; x += 64) {
+    for (int x = lane; MODE != kSumsOnly && x < (rb - ra) * n; x += 64) {
       const int64_t p = (int64_t)ra * n + x;
       __builtin_nontemporal_store(0.0f, C0 + p);
       if (!centre) {
@@ -1055,6 +1066,7 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
   const float* Pk = cube + (int64_t)bkt * M;
   const float* Pk1 = (K > 1) ? Pk + M : nullptr;
   const ColGeom g = geo[j0];
+  const float sf = (MODE == kScaled) ? colscale[j0] : 1.0f;  // flux-preserving scale
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   const int li = lane >> 3, lk = lane & 7;
@@ -1140,11 +1152,12 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
           x[r][q] = 0.0f;
           if (VEC || (a < ae && bb + q < be)) {
             x[r][q] = box_value(Q, ctux[q], mstux[q], stuy, ctuy, c, n, bs, base);
+            if constexpr (MODE == kScaled) x[r][q] *= sf;
             tsum += (double)x[r][q];
           }
           if (q == 1) __builtin_amdgcn_sched_barrier(0);  // two elements in flight
         }
-        if constexpr (VEC) {  // the row's runs of C0 and C2
+        if constexpr (VEC && MODE != kSumsOnly) {  // the row's runs of C0 and C2
           __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
                                       reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
           if (!centre)
@@ -1153,7 +1166,8 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (VEC) {
+      if constexpr (MODE == kSumsOnly) {
+      } else if constexpr (VEC) {
         if (!centre) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -1200,7 +1214,7 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
 // written again two tiles later, after every thread has passed the barrier
 // behind the copy that read it.  Slots of a block outside the item (the block
 // straddles two brackets) are left to the other item: 2-byte stores.
-template <bool BF16>
+template <bool BF16, bool SCALED>
 __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __restrict__ cube, int K,
                                                              const ColGeom* __restrict__ geo,
                                                              const int32_t* __restrict__ reps,
@@ -1209,7 +1223,8 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
                                                              int nb, int n, int ls, int64_t M,
                                                              int rpr, int64_t nreps,
                                                              uint16_t* __restrict__ Mh,
-                                                             double* __restrict__ part) {
+                                                             double* __restrict__ part,
+    const float* __restrict__ colscale) {
   constexpr int TA = 8, TB = 32, TP = TB + 1;
   constexpr int TILE = 2 * TA * TP * 8;  // uint16 per buffer
   extern __shared__ float2 P2[];  // bordered pair, then the two tile buffers
@@ -1227,6 +1242,7 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
   ColGeom g;
   g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
   if (live) g = geo[reps[sp]];
+  const float sf = (SCALED && live) ? colscale[reps[sp]] : 1.0f;  // flux-preserving scale
   const double c = (double)(n - 1) * 0.5;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
   const int64_t G0 = (int64_t)(w0 / 8) * 4;
@@ -1267,8 +1283,9 @@ __global__ __launch_bounds__(1024) void build_orbit16_kernel(const float* __rest
               ctux = g.ct * ux;
               mstux = (-g.st) * ux;
             }
-            const float val = zero_bucket ? 0.0f
-                                          : orbit_value(P2, ctux, mstux, stuy, ctuy, c, n, ls, wk0, wk1);
+            float val = zero_bucket ? 0.0f
+                                    : orbit_value(P2, ctux, mstux, stuy, ctuy, c, n, ls, wk0, wk1);
+            if constexpr (SCALED) val *= sf;
             tsum += (double)val;
             const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
             uint32_t hv;
@@ -1354,7 +1371,7 @@ __device__ __forceinline__ void cubic_origin(const ColGeom& g, double c, int a, 
   c0 = clamp_origin((int)floor(colf), Np);
 }
 
-template <bool VEC>
+template <bool VEC, int MODE>
 __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* __restrict__ pairs,
                                                                  int Np,
                                                                  const ColGeom* __restrict__ geo,
@@ -1364,7 +1381,8 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
                                                                  int nb, int n, int N, int64_t M,
                                                                  int rpr, int64_t nreps,
                                                                  float* __restrict__ A,
-                                                                 double* __restrict__ part) {
+                                                                 double* __restrict__ part,
+    const float* __restrict__ colscale) {
   extern __shared__ float QS[];  // 16 regions of kCbRegion floats
   if ((int)blockIdx.x >= *nitems) return;  // uniform: surplus workgroups of the upper bound
   const int4 it = items[blockIdx.x];
@@ -1381,7 +1399,7 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
   float* C2 = A + orbit_member(j0, N, 2) * M;
   float* C3 = A + orbit_member(j0, N, 3) * M;
   if (zero_bucket) {  // identically zero orbit: rows [ra, rb) of every member
-    for (int x = lane; x < (rb - ra) * n; x += 64) {
+    for (int x = lane; MODE != kSumsOnly && x < (rb - ra) * n; x += 64) {
       const int64_t p = (int64_t)ra * n + x;
       __builtin_nontemporal_store(0.0f, C0 + p);
       if (!centre) {
@@ -1396,6 +1414,7 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
   float* Q = QS + wave * kCbRegion;
   const float2* src = pairs + (int64_t)bkt * Np * Np;
   const ColGeom g = geo[j0];
+  const float sf = (MODE == kScaled) ? colscale[j0] : 1.0f;  // flux-preserving scale
   const double c = (double)(n - 1) * 0.5;
   const double pad = (double)kSplinePad;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
@@ -1496,11 +1515,12 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
               v = fmaf(wx[3], tr[3], v);
               V = fmaf(wy[dr], v, V);
             }
+            if constexpr (MODE == kScaled) V *= sf;
             x[r][q] = V;
             tsum += (double)V;
           }
         }
-        if constexpr (VEC) {  // the row's runs of C0 and C2
+        if constexpr (VEC && MODE != kSumsOnly) {  // the row's runs of C0 and C2
           __builtin_nontemporal_store((f32x4){x[r][0], x[r][1], x[r][2], x[r][3]},
                                       reinterpret_cast<f32x4*>(C0 + (int64_t)a * n + bb));
           if (!centre)
@@ -1509,7 +1529,8 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (VEC) {
+      if constexpr (MODE == kSumsOnly) {
+      } else if constexpr (VEC) {
         if (!centre) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -1548,7 +1569,7 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
 // TA x 32.  LDS: 16 box regions, then the two unit tiles; the cubic boxes are
 // larger (48 x 49 floats), so the cubic form takes 4-row tiles (each lane two
 // pixels of a tile row) where the bilinear form takes 8-row ones (four).
-template <bool BF16, bool CUBIC>
+template <bool BF16, bool CUBIC, bool SCALED>
 __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __restrict__ src0, int K,
                                                                  const ColGeom* __restrict__ geo,
                                                                  const int32_t* __restrict__ reps,
@@ -1557,7 +1578,8 @@ __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __
                                                                  int nb, int n, int64_t M, int Np,
                                                                  int rpr, int64_t nreps,
                                                                  uint16_t* __restrict__ Mh,
-                                                                 double* __restrict__ part) {
+                                                                 double* __restrict__ part,
+    const float* __restrict__ colscale) {
   constexpr int TA = CUBIC ? 4 : 8, TB = 32, TP = TB + 1;
   constexpr int CPL = (TA * TB) / 64;      // pixels of a tile row per lane
   constexpr int LPR = TB / CPL;            // lanes per tile row
@@ -1578,6 +1600,7 @@ __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __
   ColGeom g;
   g.ct = 1.0; g.st = 0.0; g.w = 0.0; g.e = 0;
   if (live) g = geo[reps[sp]];
+  const float sf = (SCALED && live) ? colscale[reps[sp]] : 1.0f;  // flux-preserving scale
   const double c = (double)(n - 1) * 0.5;
   const double pad = (double)kSplinePad;
   const float wk0 = (float)(1.0 - g.w), wk1 = (float)g.w;
@@ -1722,6 +1745,7 @@ __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __
                   val = box_value(Q, ctux, mstux, stuy, ctuy, c, n, bs, base);
                 }
               }
+              if constexpr (SCALED) val *= sf;
               tsum += (double)val;
               const float xs = ldexpf(val, -g.e);  // exact power-of-two scaling
               uint32_t hv;
@@ -1948,11 +1972,13 @@ hipError_t launch_build_lds16(int storage, const float* cube, int K, const ColGe
 
 static bool build_orbit_supported(int n, int K, int N);
 static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
-                                     int64_t M, float* A32, double* tau, void* scratch, hipStream_t s);
+                                     int64_t M, float* A32, double* tau, void* scratch, int mode,
+                                     const float* colscale, hipStream_t s);
 
 hipError_t launch_build_lds(const float* cube, int K, const ColGeom* geo, int n, int N, int64_t M,
                             float* A32, double* tau, void* scratch, hipStream_t s) {
-  if (build_orbit_supported(n, K, N)) return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, s);
+  if (build_orbit_supported(n, K, N))
+    return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, kPlain, nullptr, s);
   if (!pair_fits_lds(n)) return hipErrorInvalidValue;  // larger pairs: the orbit builds only
   const int64_t ncols = (int64_t)N * N;
   BucketPlan bp;
@@ -2049,7 +2075,8 @@ static hipError_t orbit_finish(const OrbitPlan& pl, double* tau, hipStream_t s) 
 }
 
 static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* geo, int n, int N,
-                                     int64_t M, float* A32, double* tau, void* scratch, hipStream_t s) {
+                                     int64_t M, float* A32, double* tau, void* scratch, int mode,
+                                     const float* colscale, hipStream_t s) {
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, nullptr, nullptr, nullptr, s);
   if (e != hipSuccess) return e;
@@ -2062,10 +2089,19 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
       hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return err;
       kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, N, M, pl.rpr,
-                                   pl.o.nreps, A32, pl.part);
+                                   pl.o.nreps, A32, pl.part, colscale);
       return hipGetLastError();
     };
-    e = vec ? launch(build_orbit_box_kernel<true>) : launch(build_orbit_box_kernel<false>);
+    switch (mode) {
+      case kSumsOnly:
+        e = vec ? launch(build_orbit_box_kernel<true, kSumsOnly>) : launch(build_orbit_box_kernel<false, kSumsOnly>);
+        break;
+      case kScaled:
+        e = vec ? launch(build_orbit_box_kernel<true, kScaled>) : launch(build_orbit_box_kernel<false, kScaled>);
+        break;
+      default:
+        e = vec ? launch(build_orbit_box_kernel<true, kPlain>) : launch(build_orbit_box_kernel<false, kPlain>);
+    }
     if (e != hipSuccess) return e;
     return orbit_finish(pl, tau, s);
   }
@@ -2076,12 +2112,35 @@ static hipError_t launch_build_orbit(const float* cube, int K, const ColGeom* ge
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, ls, N, M,
-                                 pl.rpr, pl.o.nreps, A32, pl.part);
+                                 pl.rpr, pl.o.nreps, A32, pl.part, colscale);
     return hipGetLastError();
   };
-  e = vec ? launch(build_orbit_kernel<true>) : launch(build_orbit_kernel<false>);
+  switch (mode) {
+    case kSumsOnly:
+      e = vec ? launch(build_orbit_kernel<true, kSumsOnly>) : launch(build_orbit_kernel<false, kSumsOnly>);
+      break;
+    case kScaled:
+      e = vec ? launch(build_orbit_kernel<true, kScaled>) : launch(build_orbit_kernel<false, kScaled>);
+      break;
+    default:
+      e = vec ? launch(build_orbit_kernel<true, kPlain>) : launch(build_orbit_kernel<false, kPlain>);
+  }
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
+}
+
+// The two float32 passes of a flux-preserving orbit build (see the modes above).
+bool build_orbit_flux_supported(int n, int K, int N) { return K <= 8192 && build_orbit_supported(n, K, N); }
+
+hipError_t launch_build_orbit_sums(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                   int64_t M, float* A32, double* tau, void* scratch, hipStream_t s) {
+  return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, kSumsOnly, nullptr, s);
+}
+
+hipError_t launch_build_orbit_scaled(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                     int64_t M, const float* colscale, float* A32, double* tau,
+                                     void* scratch, hipStream_t s) {
+  return launch_build_orbit(cube, K, geo, n, N, M, A32, tau, scratch, kScaled, colscale, s);
 }
 
 // cubic-spline orbit build from staged boxes of the padded coefficient pairs
@@ -2091,8 +2150,8 @@ bool build_cubic_orbit_supported(int n, int K, int N) {
 }
 
 hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* geo, int n, int N,
-                                    int64_t M, float* A32, double* tau, void* scratch,
-                                    hipStream_t s) {
+                                    int64_t M, float* A32, double* tau, void* scratch, int mode,
+                                    const float* colscale, hipStream_t s) {
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, nullptr, nullptr, nullptr, s);
   if (e != hipSuccess) return e;
@@ -2105,10 +2164,20 @@ hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* ge
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     kern<<<grid, 1024, lds, s>>>(P, Np, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, N, M, pl.rpr,
-                                 pl.o.nreps, A32, pl.part);
+                                 pl.o.nreps, A32, pl.part, colscale);
     return hipGetLastError();
   };
-  e = (n % 4) == 0 ? launch(build_cubic_orbit_kernel<true>) : launch(build_cubic_orbit_kernel<false>);
+  const bool vec = (n % 4) == 0;
+  switch (mode) {
+    case kSumsOnly:
+      e = vec ? launch(build_cubic_orbit_kernel<true, kSumsOnly>) : launch(build_cubic_orbit_kernel<false, kSumsOnly>);
+      break;
+    case kScaled:
+      e = vec ? launch(build_cubic_orbit_kernel<true, kScaled>) : launch(build_cubic_orbit_kernel<false, kScaled>);
+      break;
+    default:
+      e = vec ? launch(build_cubic_orbit_kernel<true, kPlain>) : launch(build_cubic_orbit_kernel<false, kPlain>);
+  }
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
 }
@@ -2144,7 +2213,8 @@ size_t build_lds_scratch_bytes(int K, int N, int n) {
 
 hipError_t launch_build_orbit16(int storage, const float* cube, int K, const ColGeom* geo, int n,
                                 int N, int64_t M, int32_t* perm, int32_t* eslot, int32_t* slot_of,
-                                void* lib, double* tau, void* scratch, hipStream_t s) {
+                                void* lib, double* tau, void* scratch, const float* colscale,
+                                hipStream_t s) {
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, perm, slot_of, eslot, s);
   if (e != hipSuccess) return e;
@@ -2157,11 +2227,14 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
       hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return err;
       kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, 0, pl.rpr,
-                                   pl.o.nreps, Mh, pl.part);
+                                   pl.o.nreps, Mh, pl.part, colscale);
       return hipGetLastError();
     };
-    e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true, false>)
-                                    : launch(build_orbit16_box_kernel<false, false>);
+    const bool bf = storage == PSFLIB_BF16_POW2;
+    if (colscale)
+      e = bf ? launch(build_orbit16_box_kernel<true, false, true>) : launch(build_orbit16_box_kernel<false, false, true>);
+    else
+      e = bf ? launch(build_orbit16_box_kernel<true, false, false>) : launch(build_orbit16_box_kernel<false, false, false>);
     if (e != hipSuccess) return e;
     return orbit_finish(pl, tau, s);
   }
@@ -2172,10 +2245,14 @@ hipError_t launch_build_orbit16(int storage, const float* cube, int K, const Col
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     kern<<<grid, 1024, lds, s>>>(cube, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, ls, M,
-                                 pl.rpr, pl.o.nreps, Mh, pl.part);
+                                 pl.rpr, pl.o.nreps, Mh, pl.part, colscale);
     return hipGetLastError();
   };
-  e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_kernel<true>) : launch(build_orbit16_kernel<false>);
+  const bool bf = storage == PSFLIB_BF16_POW2;
+  if (colscale)
+    e = bf ? launch(build_orbit16_kernel<true, true>) : launch(build_orbit16_kernel<false, true>);
+  else
+    e = bf ? launch(build_orbit16_kernel<true, false>) : launch(build_orbit16_kernel<false, false>);
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
 }
@@ -2188,7 +2265,7 @@ bool build_cubic_orbit16_supported(int n, int K, int N) {
 hipError_t launch_build_cubic_orbit16(int storage, const float* pairs, int K, const ColGeom* geo,
                                       int n, int N, int64_t M, int32_t* perm, int32_t* eslot,
                                       int32_t* slot_of, void* lib, double* tau, void* scratch,
-                                      hipStream_t s) {
+                                      const float* colscale, hipStream_t s) {
   const OrbitPlan pl = orbit_plan(K, N, n, scratch);
   hipError_t e = orbit_sort(geo, pl, perm, slot_of, eslot, s);
   if (e != hipSuccess) return e;
@@ -2201,11 +2278,14 @@ hipError_t launch_build_cubic_orbit16(int storage, const float* pairs, int K, co
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
     kern<<<grid, 1024, lds, s>>>(pairs, K, geo, pl.reps, pl.items, pl.nitems, pl.nb, n, M, Np, pl.rpr,
-                                 pl.o.nreps, Mh, pl.part);
+                                 pl.o.nreps, Mh, pl.part, colscale);
     return hipGetLastError();
   };
-  e = storage == PSFLIB_BF16_POW2 ? launch(build_orbit16_box_kernel<true, true>)
-                                  : launch(build_orbit16_box_kernel<false, true>);
+  const bool bf = storage == PSFLIB_BF16_POW2;
+  if (colscale)
+    e = bf ? launch(build_orbit16_box_kernel<true, true, true>) : launch(build_orbit16_box_kernel<false, true, true>);
+  else
+    e = bf ? launch(build_orbit16_box_kernel<true, true, false>) : launch(build_orbit16_box_kernel<false, true, false>);
   if (e != hipSuccess) return e;
   return orbit_finish(pl, tau, s);
 }

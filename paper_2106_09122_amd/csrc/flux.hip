@@ -8,7 +8,10 @@
 // flux of the PSF it was interpolated from.  The scale is applied to the
 // float32 column (one rounding), the column sum is recomputed from the
 // stored values, and for the 16-bit forms the column exponent is recomputed
-// from the rescaled bound before the column is rounded.
+// from the rescaled bound before the column is rounded.  The orbit builds do
+// this in two passes instead of rewriting the library: the column sums of the
+// plain build (nothing stored), the scales (flux_scale_kernel), then the build
+// with every value scaled as it is stored: the plain build's entries rescaled.
 #include <math.h>
 
 #include "psflib_internal.h"
@@ -101,7 +104,47 @@ __global__ __launch_bounds__(256) void flux_rescale_kernel(
   }
 }
 
+// The scales alone (the orbit builds apply them as they store): for column j
+// the float32 scale t_j / tau_j of flux_rescale_kernel from the plain build's
+// column sum, and for the 16-bit forms the exponent from the rescaled bound;
+// identically zero columns keep scale 1 and their exponent.
+__global__ __launch_bounds__(256) void flux_scale_kernel(ColGeom* __restrict__ geo, int K,
+                                                         const double* __restrict__ sums,
+                                                         const float* __restrict__ pmax,
+                                                         int64_t ncols, const double* __restrict__ tau,
+                                                         float* __restrict__ colscale,
+                                                         int32_t* __restrict__ exps, int want_exp) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= ncols) return;
+  const ColGeom g = geo[j];
+  if (g.k < 0) {
+    colscale[j] = 1.0f;
+    return;
+  }
+  const double t = (K == 1) ? sums[0] : (1.0 - g.w) * sums[g.k] + g.w * sums[g.k + 1];
+  const double old = tau[j];
+  const double scale = (old != 0.0) ? t / old : 1.0;
+  const float sf = (float)scale;
+  colscale[j] = sf;
+  if (want_exp) {
+    const double bound = (K == 1) ? (double)pmax[0]
+                                  : (1.0 - g.w) * (double)pmax[g.k] + g.w * (double)pmax[g.k + 1];
+    const int32_t e = exponent_of(bound * fabs((double)sf));
+    geo[j].e = e;
+    exps[j] = e;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_flux_scale(ColGeom* geo, int K, const double* sums, const float* pmax,
+                             int64_t ncols, const double* tau, float* colscale, int32_t* exps,
+                             bool want_exp, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  flux_scale_kernel<<<(unsigned)((ncols + 255) / 256), 256, 0, s>>>(geo, K, sums, pmax, ncols, tau,
+                                                                    colscale, exps, want_exp ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_psf_sums(const float* cube, int K, int64_t M, double* sums, hipStream_t s) {
   psf_sums_kernel<<<K, 256, 0, s>>>(cube, M, sums);

@@ -334,27 +334,32 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   const bool big16 = desc->n > 256 && storage != PSFLIB_FP32 && !flux && desc->N % 8 != 0;
   const bool lds = !big16 && (cubic ? psflib::build_cubic_orbit_supported(desc->n, K, desc->N)
                                     : psflib::build_lds_supported(desc->n, K, desc->N));
-  // 16-bit libraries of unrescaled columns are written directly in bracket
+  // Flux-preserving orbit builds take two passes (the plain build's column
+  // sums, then the build with each column scaled as it is stored) instead of
+  // rewriting the library.  16-bit libraries are written directly in bracket
   // order: by quarter-turn orbits when N is a multiple of 8 (bilinear or
-  // cubic), else (bilinear) column by column when the pair fits the LDS; the
-  // other 16-bit builds go through float32 columns and a packing pass
-  // (natural order)
-  const bool plain16 = storage != PSFLIB_FP32 && !flux && lds;
+  // cubic, rescaled or not), else (bilinear, not rescaled) column by column
+  // when the pair fits the LDS; the other 16-bit builds go through float32
+  // columns and a packing pass (natural order)
+  const bool flux_orbit =
+      flux && lds && (cubic || psflib::build_orbit_flux_supported(desc->n, K, desc->N));
+  const bool plain16 = storage != PSFLIB_FP32 && lds && (!flux || flux_orbit);
   const bool orbit16 = plain16 && (cubic ? psflib::build_cubic_orbit16_supported(desc->n, K, desc->N)
                                          : psflib::build_orbit16_supported(desc->n, K, desc->N));
   const bool direct16 =
-      orbit16 || (plain16 && !cubic && psflib::build_lds16_supported(desc->n, K, L.ncols));
+      orbit16 || (plain16 && !flux && !cubic && psflib::build_lds16_supported(desc->n, K, L.ncols));
   const bool stage32 = storage != PSFLIB_FP32 && (lds || flux) && !direct16;
   const size_t spline_bytes = cubic ? align256(psflib::spline_scratch_bytes(K, desc->n)) : 0;
   const size_t path_bytes =
-      spline_bytes + align256(orbit16    ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
+      spline_bytes + align256(orbit16 || flux_orbit ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
                               : direct16 ? psflib::build_lds16_scratch_bytes(K, L.ncols)
                               : cubic && lds ? psflib::build_orbit_scratch_bytes(K, desc->N, desc->n)
                               : lds    ? psflib::build_lds_scratch_bytes(K, desc->N, desc->n)
                               : cubic  ? 0
                                        : (size_t)((K > 1) ? (K - 1) : 1) * (size_t)L.M * 8);
   const size_t stage_bytes = align256(stage32 ? (size_t)L.ncols * (size_t)L.M * 4 : 0);
-  const size_t sums_bytes = align256(flux ? (size_t)K * 8 : 0);
+  const size_t sums_bytes =
+      align256(flux ? (size_t)K * 8 : 0) + align256(flux_orbit ? (size_t)L.ncols * 4 : 0);
   const size_t tmp_bytes = path_bytes + stage_bytes + sums_bytes;
   void* tmp = nullptr;
   // on failure: wait for what this build enqueued (on its own stream), then
@@ -375,6 +380,9 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
   void* path_tmp = tp;
   float* A32 = stage32 ? reinterpret_cast<float*>(tp + path_bytes) : reinterpret_cast<float*>(d_lib);
   double* sums = flux ? reinterpret_cast<double*>(tp + path_bytes + stage_bytes) : nullptr;
+  float* colscale = flux_orbit ? reinterpret_cast<float*>(tp + path_bytes + stage_bytes +
+                                                          align256((size_t)K * 8))
+                               : nullptr;
   // the format the build kernel writes, and where
   const int bstore = stage32 ? PSFLIB_FP32 : storage;
   void* bdst = stage32 ? reinterpret_cast<void*>(A32) : d_lib;
@@ -391,18 +399,50 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                               desc->oob, h->pmax, storage != PSFLIB_FP32, h->geo, L.ncols_pad,
                               exps, s);
   if (e != hipSuccess) return bail(e, "geometry kernel");
-  if (cubic && orbit16) {
+  const float* cpairs = cubic ? psflib::spline_pairs_of(path_tmp, K, desc->n) : nullptr;
+  void* otmp = tp + spline_bytes;  // the orbit builds' scratch
+  int32_t* perm = reinterpret_cast<int32_t*>(lib + L.off_perm);
+  int32_t* eslot = reinterpret_cast<int32_t*>(lib + L.off_eslot);
+  int32_t* slot_of = reinterpret_cast<int32_t*>(lib + L.off_slot);
+  if (flux_orbit) {
+    // pass 1: the plain build's column sums, nothing stored
+    e = psflib::launch_psf_sums(d_cube, K, L.M, sums, s);
+    if (e != hipSuccess) return bail(e, "psf sums kernel");
+    float* none = reinterpret_cast<float*>(d_lib);  // not written in this pass
+    e = cubic ? psflib::launch_build_cubic_orbit(cpairs, K, h->geo, desc->n, desc->N, L.M, none, tau,
+                                                 otmp, psflib::kOrbitSumsOnly, nullptr, s)
+              : psflib::launch_build_orbit_sums(d_cube, K, h->geo, desc->n, desc->N, L.M, none, tau,
+                                                otmp, s);
+    if (e != hipSuccess) return bail(e, "flux column-sum pass");
+    e = psflib::launch_flux_scale(h->geo, K, sums, h->pmax, L.ncols, tau, colscale, exps,
+                                  storage != PSFLIB_FP32, s);
+    if (e != hipSuccess) return bail(e, "flux scale kernel");
+    // pass 2: the build, each column scaled as it is stored
+    if (orbit16)
+      e = cubic ? psflib::launch_build_cubic_orbit16(storage, cpairs, K, h->geo, desc->n, desc->N, L.M,
+                                                     perm, eslot, slot_of, d_lib, tau, otmp,
+                                                     colscale, s)
+                : psflib::launch_build_orbit16(storage, d_cube, K, h->geo, desc->n, desc->N, L.M,
+                                               perm, eslot, slot_of, d_lib, tau, otmp, colscale, s);
+    else
+      e = cubic ? psflib::launch_build_cubic_orbit(cpairs, K, h->geo, desc->n, desc->N, L.M,
+                                                   reinterpret_cast<float*>(bdst), tau, otmp,
+                                                   psflib::kOrbitScaled, colscale, s)
+                : psflib::launch_build_orbit_scaled(d_cube, K, h->geo, desc->n, desc->N, L.M, colscale,
+                                                    reinterpret_cast<float*>(bdst), tau, otmp, s);
+    if (e != hipSuccess) return bail(e, "flux-preserving orbit build kernels");
+  } else if (cubic && orbit16) {
     e = psflib::launch_build_cubic_orbit16(storage, psflib::spline_pairs_of(path_tmp, K, desc->n), K,
                                            h->geo, desc->n, desc->N, L.M,
                                            reinterpret_cast<int32_t*>(lib + L.off_perm),
                                            reinterpret_cast<int32_t*>(lib + L.off_eslot),
                                            reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
-                                           tp + spline_bytes, s);
+                                           tp + spline_bytes, nullptr, s);
     if (e != hipSuccess) return bail(e, "16-bit cubic orbit build kernels");
   } else if (cubic && lds) {
     e = psflib::launch_build_cubic_orbit(psflib::spline_pairs_of(path_tmp, K, desc->n), K, h->geo,
                                          desc->n, desc->N, L.M, reinterpret_cast<float*>(bdst), tau,
-                                         tp + spline_bytes, s);
+                                         tp + spline_bytes, psflib::kOrbitPlain, nullptr, s);
     if (e != hipSuccess) return bail(e, "cubic orbit build kernels");
   } else if (cubic) {
     e = psflib::launch_build_cubic(bstore, psflib::spline_pairs_of(path_tmp, K, desc->n), h->geo,
@@ -413,7 +453,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                                      reinterpret_cast<int32_t*>(lib + L.off_perm),
                                      reinterpret_cast<int32_t*>(lib + L.off_eslot),
                                      reinterpret_cast<int32_t*>(lib + L.off_slot), d_lib, tau,
-                                     path_tmp, s);
+                                     path_tmp, nullptr, s);
     if (e != hipSuccess) return bail(e, "16-bit orbit build kernels");
   } else if (direct16) {
     e = psflib::launch_build_lds16(storage, d_cube, K, h->geo, desc->n, L.M, L.ncols, L.ncols_pad,
@@ -433,7 +473,7 @@ psflib_status psflib_build(const psflib_desc* desc, const float* d_cube, const d
                              L.M, L.ncols, L.ncols_pad, bdst, tau, s);
     if (e != hipSuccess) return bail(e, "build kernel");
   }
-  if (flux) {
+  if (flux && !flux_orbit) {
     e = psflib::launch_psf_sums(d_cube, K, L.M, sums, s);
     if (e != hipSuccess) return bail(e, "psf sums kernel");
     e = psflib::launch_flux_rescale(reinterpret_cast<float*>(bdst), h->geo, K, sums, h->pmax, L.M,

@@ -147,20 +147,32 @@ const float* spline_pairs_of(const void* scratch, int K, int n);
 hipError_t launch_build_cubic(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                               int64_t ncols, int64_t ncols_pad, void* lib, double* tau,
                               hipStream_t s);
+// Modes of the float32 orbit builds: plain; column sums only (nothing
+// stored); every value times its column's scale colscale[j] before it is
+// stored and summed.  The 16-bit orbit builds scale when colscale is given.
+constexpr int kOrbitPlain = 0, kOrbitSumsOnly = 1, kOrbitScaled = 2;
+// The two passes of a flux-preserving bilinear orbit build: the column sums
+// of the plain build (tau), then the build scaled per column.
+bool build_orbit_flux_supported(int n, int K, int N);
+hipError_t launch_build_orbit_sums(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                   int64_t M, float* A32, double* tau, void* scratch, hipStream_t s);
+hipError_t launch_build_orbit_scaled(const float* cube, int K, const ColGeom* geo, int n, int N,
+                                     int64_t M, const float* colscale, float* A32, double* tau,
+                                     void* scratch, hipStream_t s);
 // Cubic build by quarter-turn orbits, the taps read from a box of the padded
 // coefficient pair staged per tile in LDS (float32 columns); scratch of
 // build_orbit_scratch_bytes(K, N, n) bytes.
 bool build_cubic_orbit_supported(int n, int K, int N);
 hipError_t launch_build_cubic_orbit(const float* pairs, int K, const ColGeom* geo, int n, int N,
-                                    int64_t M, float* A32, double* tau, void* scratch,
-                                    hipStream_t s);
+                                    int64_t M, float* A32, double* tau, void* scratch, int mode,
+                                    const float* colscale, hipStream_t s);
 // 16-bit cubic storage built by the same orbits (N % 8 == 0), slots as
 // launch_build_orbit16's; scratch of build_orbit_scratch_bytes(K, N, n) bytes.
 bool build_cubic_orbit16_supported(int n, int K, int N);
 hipError_t launch_build_cubic_orbit16(int storage, const float* pairs, int K, const ColGeom* geo,
                                       int n, int N, int64_t M, int32_t* perm, int32_t* eslot,
                                       int32_t* slot_of, void* lib, double* tau, void* scratch,
-                                      hipStream_t s);
+                                      const float* colscale, hipStream_t s);
 hipError_t launch_build(int storage, const float* pairs, const ColGeom* geo, int n, int64_t M,
                         int64_t ncols, int64_t ncols_pad, void* lib, double* tau, hipStream_t s);
 bool build_lds_supported(int n, int K, int N);
@@ -193,7 +205,8 @@ bool build_orbit16_supported(int n, int K, int N);
 size_t build_orbit_scratch_bytes(int K, int N, int n);
 hipError_t launch_build_orbit16(int storage, const float* cube, int K, const ColGeom* geo, int n,
                                 int N, int64_t M, int32_t* perm, int32_t* eslot, int32_t* slot_of,
-                                void* lib, double* tau, void* scratch, hipStream_t s);
+                                void* lib, double* tau, void* scratch, const float* colscale,
+                                hipStream_t s);
 // 16-bit storage built directly (bilinear rotation, no column rescale, the
 // pair and a 16-bit tile in LDS): columns ordered by radial bracket (perm,
 // slot_of, eslot written here, exps per column given), mantissas written as
@@ -215,6 +228,11 @@ hipError_t launch_pack16_range(int storage, const float* A32, int64_t col0, int6
 // column j scaled by t_j / tau_j, tau_j recomputed; with want_exp the 16-bit
 // exponents (geo[j].e and exps[j]) follow the rescaled bound.
 hipError_t launch_psf_sums(const float* cube, int K, int64_t M, double* sums, hipStream_t s);
+// Per-column flux scales (and, with want_exp, exponents) from the plain
+// build's column sums, for the orbit builds' scaled pass.
+hipError_t launch_flux_scale(ColGeom* geo, int K, const double* sums, const float* pmax,
+                             int64_t ncols, const double* tau, float* colscale, int32_t* exps,
+                             bool want_exp, hipStream_t s);
 hipError_t launch_flux_rescale(float* A32, ColGeom* geo, int K, const double* sums,
                                const float* pmax, int64_t M, int64_t ncols, double* tau,
                                int32_t* exps, bool want_exp, hipStream_t s);

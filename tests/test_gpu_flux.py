@@ -113,3 +113,40 @@ def test_flux_16bit(torch, fmt, case):
     ok = t != 0
     assert np.max(np.abs(tau[ok] - t[ok]) / np.abs(t[ok])) <= 1e-6
     lib.close()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3]])
+def test_flux_is_the_plain_build_scaled(torch, case):
+    """A flux-preserving column is the plain build's float32 column times one
+    float32 scale, rounded once per entry: for every column some float32 s_j
+    within 2 ulp of t_j / tau_j (the PSF flux over the plain column's sum)
+    reproduces every entry exactly."""
+    from paper_2106_09122_amd import psflib
+    n, N, S, K, kind, rotate = case
+    cube, radii, A, t, s, b = _oracle(case)
+    lib1 = _lib(torch, case)
+    lib0 = psflib.Library(torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float32)).cuda(),
+                          radii, N, S, rotate=rotate)
+    A1 = lib1.get_columns(np.arange(N * N)).cpu().numpy()
+    A0 = lib0.get_columns(np.arange(N * N)).cpu().numpy()
+    tau0 = lib0.column_sums().cpu().numpy()
+    for j in range(N * N):
+        if tau0[j] == 0:
+            assert np.all(A1[j] == A0[j])
+            continue
+        want = np.float32(t[j] / tau0[j])
+        ok = [sf for sf in _ulps(want, 2) if np.array_equal(A0[j] * sf, A1[j])]
+        assert ok, j
+    lib0.close()
+    lib1.close()
+
+
+def _ulps(x, k):
+    """x and its k float32 neighbours on either side."""
+    out = [np.float32(x)]
+    lo = hi = np.float32(x)
+    for _ in range(k):
+        lo = np.nextafter(lo, np.float32(-np.inf))
+        hi = np.nextafter(hi, np.float32(np.inf))
+        out += [lo, hi]
+    return out

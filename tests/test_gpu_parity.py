@@ -451,7 +451,8 @@ def test_get_columns_out_of_range_indices_give_zeros(torch, psflib, c1, c1_oracl
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
-@pytest.mark.parametrize("case", ["c1", "odd", "c2", "box", "gather", "cubic_box", "cubic_gather"])
+@pytest.mark.parametrize("case", ["c1", "odd", "c2", "box", "gather", "cubic_box", "cubic_gather",
+                                  "flux_c1", "flux_cubic_box"])
 def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
     """The 16-bit library (built directly: by rotation orbits from the
     LDS-staged pair or from staged boxes, by columns in bracket order, or by
@@ -460,9 +461,11 @@ def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
     column at 32^2, on an odd shape whose column count leaves a partial 8-slot
     group (padding), on 512 sampled columns at 128^2, on the 16-bit box
     kernel (150^2 PSFs, bilinear and cubic), and on the bilinear and cubic
-    gathers (260^2 PSFs, odd scene) against the float32 box builds."""
+    gathers (260^2 PSFs, odd scene) against the float32 box builds, and on
+    flux-preserving libraries (each column scaled as it is stored: 32^2 with
+    the pair in LDS, 150^2 cubic from boxes)."""
     kw = {}
-    if case == "c1":
+    if case in ("c1", "flux_c1"):
         d = synth.config_inputs(1)
         cube, radii, N, S = d["cube"], d["radii"], d["N"], d["S"]
     elif case == "odd":
@@ -473,11 +476,13 @@ def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
         d = synth.config_inputs(2)
         cube, radii, N, S = d["cube"], d["radii"], d["N"], d["S"]
     else:
-        n, N = (150, 16) if case in ("box", "cubic_box") else (260, 3)
+        n, N = (150, 16) if case in ("box", "cubic_box", "flux_cubic_box") else (260, 3)
         cube, radii, _ = _shape_inputs(n, N, 0.4, 4, "nonuniform", n + N)
         S = 0.4
-        if case.startswith("cubic"):
+        if "cubic" in case:
             kw = dict(rotate="cubic")
+    if case.startswith("flux"):
+        kw["flux"] = "preserve"
     K = N * N
     cols = np.arange(K) if case != "c2" else np.unique(np.concatenate(
         [np.random.default_rng(7).choice(K, 500, replace=False), [0, K - 1, K // 2, K // 2 + 64]]))
@@ -498,7 +503,7 @@ def test_16bit_build_rounds_the_fp32_build(torch, psflib, fmt, case):
     # (cubic entries mix signs: the bound takes the sum of magnitudes)
     t16, t32 = l16.column_sums().cpu().numpy(), l32.column_sums().cpu().numpy()
     n2 = cube.shape[1] * cube.shape[2]
-    mag = np.abs(t32[cols]) if not kw else np.abs(A32.astype(np.float64)).sum(axis=1)
+    mag = np.abs(t32[cols]) if "rotate" not in kw else np.abs(A32.astype(np.float64)).sum(axis=1)
     assert np.all(np.abs(t16[cols] - t32[cols]) <= 2 * n2 * 2.0**-53 * mag)
     l32.close()
     l16.close()
