@@ -1023,6 +1023,54 @@ __device__ __forceinline__ float box_value(const float* __restrict__ Q, double c
   return t.ok ? val : 0.0f;
 }
 
+// Stage rows [Rlo, Rlo + bh) x columns [Clo, Clo + bw) of a box into Q (row
+// stride bs), each entry the radial blend (1-w) x + w y of its pair, formed as
+// the pair kernels form their taps.  Bilinear: bordered indices of the
+// sample pair Pk, Pk1 (zero border); cubic: padded indices of the coefficient
+// pairs Pc (zero outside the Np x Np array).  The box is taken in row-major
+// order 64 entries at a time, lane l taking entry l of each step, 8 steps'
+// loads in flight before their LDS writes.
+template <bool CUBIC>
+__device__ __forceinline__ void stage_box(float* __restrict__ Q, const float* __restrict__ Pk,
+                                          const float* __restrict__ Pk1,
+                                          const float2* __restrict__ Pc, int n, int Np, int Rlo,
+                                          int Clo, int bh, int bw, int bs, float wk0, float wk1,
+                                          int lane) {
+  if (bh <= 0 || bw <= 0) return;  // uniform
+  const int q64 = 64 / bw, r64 = 64 - q64 * bw;
+  int rr = lane / bw, cc = lane - rr * bw;
+  while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest entry
+    float xv[8], yv[8];
+    int dst[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int R = Rlo + rr, C = Clo + cc;
+      const bool in = rr < bh;
+      if constexpr (CUBIC) {
+        const bool inner = in && (unsigned)R < (unsigned)Np && (unsigned)C < (unsigned)Np;
+        const float2 p = inner ? Pc[R * Np + C] : make_float2(0.0f, 0.0f);
+        xv[k] = p.x;
+        yv[k] = p.y;
+      } else {
+        const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
+        const int off = (R - 1) * n + (C - 1);
+        xv[k] = inner ? Pk[off] : 0.0f;
+        yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
+      }
+      dst[k] = in ? rr * bs + cc : -1;
+      cc += r64;
+      rr += q64;
+      if (cc >= bw) {
+        cc -= bw;
+        ++rr;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
+  }
+}
+
 template <bool VEC, int MODE>
 __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __restrict__ cube, int K,
                                                                const ColGeom* __restrict__ geo,
@@ -1097,33 +1145,7 @@ __global__ __launch_bounds__(1024) void build_orbit_box_kernel(const float* __re
       const int bw = min(max(min(cmax + 2, n + 1) - Clo + 1, 0), kFpSpan);
       const int bs = bw | 1;
       wave_lds_sync();  // the previous tile's reads are done
-      if (bh > 0 && bw > 0) {
-        const int q64 = 64 / bw, r64 = 64 - q64 * bw;
-        int rr = lane / bw, cc = lane - rr * bw;
-        while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
-          float xv[8], yv[8];
-          int dst[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int R = Rlo + rr, C = Clo + cc;
-            const bool in = rr < bh;
-            const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
-            const int off = (R - 1) * n + (C - 1);
-            xv[k] = inner ? Pk[off] : 0.0f;
-            yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
-            dst[k] = in ? rr * bs + cc : -1;
-            cc += r64;
-            rr += q64;
-            if (cc >= bw) {
-              cc -= bw;
-              ++rr;
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
-        }
-      }
+      stage_box<false>(Q, Pk, Pk1, nullptr, n, 0, Rlo, Clo, bh, bw, bs, wk0, wk1, lane);
       wave_lds_sync();  // the box is staged
       const int base = Rlo * bs + Clo;
       const int bb = b0 + 4 * lk;
@@ -1445,31 +1467,7 @@ __global__ __launch_bounds__(1024) void build_cubic_orbit_kernel(const float2* _
       const int bh = min(rmax - rmin + 4, kCbSpan), bw = min(cmax - cmin + 4, kCbSpan);
       const int bs = bw | 1;
       wave_lds_sync();  // the previous tile's reads are done
-      {
-        const int q64 = 64 / bw, r64 = 64 - q64 * bw;
-        int rr = lane / bw, cc = lane - rr * bw;
-        while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
-          float2 pv[8];
-          int dst[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int R = Rlo + rr, C = Clo + cc;
-            const bool in = rr < bh;
-            const bool inner = in && (unsigned)R < (unsigned)Np && (unsigned)C < (unsigned)Np;
-            pv[k] = inner ? src[R * Np + C] : make_float2(0.0f, 0.0f);
-            dst[k] = in ? rr * bs + cc : -1;
-            cc += r64;
-            rr += q64;
-            if (cc >= bw) {
-              cc -= bw;
-              ++rr;
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, pv[k].y, wk0 * pv[k].x);
-        }
-      }
+      stage_box<true>(Q, nullptr, nullptr, src, n, Np, Rlo, Clo, bh, bw, bs, wk0, wk1, lane);
       wave_lds_sync();  // the box is staged
       const int bb = b0 + 4 * lk;
       if (ab >= ae || bb >= be) continue;  // VEC: the whole block is outside the tile
@@ -1662,40 +1660,7 @@ __global__ __launch_bounds__(1024) void build_orbit16_box_kernel(const float* __
         }
         bs = bw | 1;
         base = Rlo * bs + Clo;
-        if (bh > 0 && bw > 0) {
-          const int q64 = 64 / bw, r64 = 64 - q64 * bw;
-          int rr = lane / bw, cc = lane - rr * bw;
-          while (__builtin_amdgcn_readfirstlane(rr) < bh) {  // lane 0 has the lowest element
-            float xv[8], yv[8];
-            int dst[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              const int R = Rlo + rr, C = Clo + cc;
-              const bool in = rr < bh;
-              if constexpr (CUBIC) {
-                const bool inner = in && (unsigned)R < (unsigned)Np && (unsigned)C < (unsigned)Np;
-                const float2 p = inner ? Pc[R * Np + C] : make_float2(0.0f, 0.0f);
-                xv[k] = p.x;
-                yv[k] = p.y;
-              } else {
-                const bool inner = in && (unsigned)(R - 1) < (unsigned)n && (unsigned)(C - 1) < (unsigned)n;
-                const int off = (R - 1) * n + (C - 1);
-                xv[k] = inner ? Pk[off] : 0.0f;
-                yv[k] = (inner && Pk1) ? Pk1[off] : 0.0f;
-              }
-              dst[k] = in ? rr * bs + cc : -1;
-              cc += r64;
-              rr += q64;
-              if (cc >= bw) {
-                cc -= bw;
-                ++rr;
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-              if (dst[k] >= 0) Q[dst[k]] = fmaf(wk1, yv[k], wk0 * xv[k]);
-          }
-        }
+        stage_box<CUBIC>(Q, Pk, Pk1, Pc, n, Np, Rlo, Clo, bh, bw, bs, wk0, wk1, lane);
         wave_lds_sync();  // the box is staged
       }
       for (int a1 = a0; a1 < ae; a1 += TA, buf ^= 1) {  // uniform over the workgroup
