@@ -95,11 +95,12 @@ typedef enum { PSFLIB_OOB_CLAMP = 0, PSFLIB_OOB_ZERO = 1 } psflib_oob;
  *             at ((s/8)*n*n + i)*8 + s%8, so one 16-byte load holds row i of
  *             8 slots (the operand shape of the matrix cores).  Slot s holds
  *             column perm[s]; the build picks the order so that one workgroup
- *             can write whole 16-byte groups: for N a multiple of 8 (bilinear,
- *             no flux rescale, the PSF pair within the LDS) slots 32b + 8k + u
+ *             can write whole 16-byte groups: for N a multiple of 8 (either
+ *             rotation, with or without the flux rescale) slots 32b + 8k + u
  *             hold the k-th quarter turn about the star of the u-th of the
  *             b-th eight base columns (one quadrant, sorted by radial
- *             bracket); in other such builds the columns sorted by bracket;
+ *             bracket); for other N, bilinear columns without the rescale
+ *             whose PSF pair fits the LDS (n <= 141) are sorted by bracket;
  *             otherwise the natural order (slot j = column j).  The slot
  *             order is part of the library buffer (see psflib_library_bytes);
  *             psflib_get_columns reads columns by index whatever the order.
@@ -132,8 +133,9 @@ typedef enum { PSFLIB_ROTATE_BILINEAR = 0, PSFLIB_ROTATE_CUBIC = 1 } psflib_rota
  *            interpolated PSF before rotation, (1-w) sum(P_k) + w sum(P_{k+1}):
  *            the part of the PSF that the rotation carries out of the frame
  *            (and the spline's overshoot) no longer changes the total.  A
- *            column that sums to zero is left as is.  The 16-bit forms are
- *            built in float32, rescaled, then rounded, with the column
+ *            column that sums to zero is left as is.  Each entry is the
+ *            unscaled float32 entry times the column's float32 scale,
+ *            rounded once; the 16-bit forms round that value, with the column
  *            exponent taken from the rescaled bound. */
 typedef enum { PSFLIB_FLUX_NONE = 0, PSFLIB_FLUX_PRESERVE = 1 } psflib_flux;
 
